@@ -1,0 +1,500 @@
+/*
+ * oracle.c -- plain, slow FP64 reference of the SBIP-DPPS passing-point search
+ * (arXiv 1909.07717, Sec. 4.1-4.3).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it.  It shares no code, header, table or
+ * constant with the HIP path: every formula below is written out again from
+ * the paper and from the readings listed with each function.
+ *
+ * What it computes, per candidate point c and pass variant (type, v0):
+ *   - the ideal ball model's travel time to each of K path samples
+ *     (Sec. 4.1: slide down to 5/7 of the kick speed, then roll to rest);
+ *   - for every robot except the passer, its earliest interception along the
+ *     sampled path (SBIP, Sec. 4.2): the ball time at the first sample the
+ *     robot reaches no later than the ball;
+ *   - the first-teammate and first-opponent interception times, the margin
+ *     between them and the feasibility filter (Sec. 4.3, last feature);
+ *   - the weighted-sum score of Eq. (3) with lengths and angles divided by
+ *     their upper bound (Sec. 4.3);
+ *   - the argmax over everything (Sec. 4.3, best pass line).
+ * The per-robot interception times are computed robot by robot, with no
+ * factorisation across robots or variants.
+ *
+ * Readings where the paper is silent (the paper's own figure of the ball
+ * model and its interception predictor are not available):
+ *   ball deceleration values, chip model, path sampling, robot arrival time,
+ *   the open goal angle and the lattice follow the configuration constants
+ *   passed in orc_params; each function states the reading it implements.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_FLAT 0
+#define ORC_CHIP 1
+
+/* ambiguity flags (parity bands) */
+#define ORC_AMB_REACH 1   /* |d - D| or |d - s_f| below eps_reach           */
+#define ORC_AMB_LAND 2    /* chip sample within eps_land of the landing point */
+#define ORC_AMB_CROSS 4   /* a robot's arrival within the crossing band       */
+#define ORC_AMB_MARGIN 8  /* margin within eps_margin of the threshold        */
+
+typedef struct {
+    double field_len, field_wid, goal_x, goal_width;
+    double robot_radius, vmax, amax;
+    double slide_decel, roll_decel, slide_ratio;
+    double chip_angle, gravity;
+    double margin_s, margin_cap_s;
+    double w_angle, w_dist, w_margin, dist_norm;
+    double goal_eps;
+    int32_t n_samples;
+    int32_t n_threads;
+    /* parity bands, used only when bands are requested */
+    double eps_reach, eps_land, eps_cross_t, eps_cross_s, eps_margin;
+} orc_params;
+
+typedef struct {
+    int32_t n_team, n_opp, passer, pad;
+    const double *team; /* n_team x (x, y, vx, vy) */
+    const double *opp;  /* n_opp  x (x, y, vx, vy) */
+    double ball_x, ball_y;
+} orc_world;
+
+typedef struct {
+    int32_t reachable, feasible, ambig, pad;
+    double t_team, t_opp, margin, score, open_angle;
+} orc_result;
+
+/* ------------------------------------------------------------------------ */
+/* Ball model (Sec. 4.1).                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Stopping distance D and, for chips, the carry s_f (flat: s_f = 0).
+ * Flat: the ball slides from v0 down to v1 = ratio * v0 at the sliding
+ * deceleration, covering (v0^2 - v1^2) / (2 a_s), then rolls from v1 to rest,
+ * covering v1^2 / (2 a_r).  The forward model keeps the sliding distance.
+ * Chip (no model in the paper; reading): launched at v0 and the chip angle with
+ * no drag, it lands after s_f = v_h * 2 v_z / g and then rolls from the
+ * horizontal speed v_h to rest at the rolling deceleration. */
+void orc_ball_range(const orc_params *P, int type, double v0, double *D, double *s_f)
+{
+    if (type == ORC_CHIP) {
+        double vh = v0 * cos(P->chip_angle), vz = v0 * sin(P->chip_angle);
+        double tf = 2.0 * vz / P->gravity;
+        double sf = vh * tf;
+        *s_f = sf;
+        *D = sf + vh * vh / (2.0 * P->roll_decel);
+    } else {
+        double v1 = P->slide_ratio * v0;
+        double d1 = (v0 * v0 - v1 * v1) / (2.0 * P->slide_decel);
+        *s_f = 0.0;
+        *D = d1 + v1 * v1 / (2.0 * P->roll_decel);
+    }
+}
+
+/* Time for the ball to travel distance s along its path; +inf beyond the
+ * stopping distance.  Under constant deceleration a from speed v, the time to
+ * cover x is the smaller root of x = v t - a t^2 / 2, written here in the
+ * cancellation-free form 2x / (v + sqrt(v^2 - 2 a x)). */
+static double phase_time(double v, double a, double x)
+{
+    double q = v * v - 2.0 * a * x;
+    if (q < 0.0) q = 0.0;
+    return 2.0 * x / (v + sqrt(q));
+}
+
+double orc_ball_time(const orc_params *P, int type, double v0, double s)
+{
+    double D, sf;
+    orc_ball_range(P, type, v0, &D, &sf);
+    if (s > D) return INFINITY;
+    if (type == ORC_CHIP) {
+        double vh = v0 * cos(P->chip_angle), vz = v0 * sin(P->chip_angle);
+        double tf = 2.0 * vz / P->gravity;
+        if (s <= sf) return s / vh; /* in the air: horizontal speed is constant */
+        return tf + phase_time(vh, P->roll_decel, s - sf);
+    } else {
+        double v1 = P->slide_ratio * v0;
+        double t1 = (v0 - v1) / P->slide_decel;
+        double d1 = (v0 * v0 - v1 * v1) / (2.0 * P->slide_decel);
+        if (s <= d1) return phase_time(v0, P->slide_decel, s);
+        return t1 + phase_time(v1, P->roll_decel, s - d1);
+    }
+}
+
+/* Distance travelled by the ball at time t (the forward model; only used for
+ * the parity bands). */
+double orc_ball_dist(const orc_params *P, int type, double v0, double t)
+{
+    double D, sf;
+    orc_ball_range(P, type, v0, &D, &sf);
+    if (type == ORC_CHIP) {
+        double vh = v0 * cos(P->chip_angle), vz = v0 * sin(P->chip_angle);
+        double tf = 2.0 * vz / P->gravity;
+        if (t <= tf) return vh * t;
+        double tau = t - tf, tr = vh / P->roll_decel;
+        if (tau >= tr) return D;
+        return sf + vh * tau - 0.5 * P->roll_decel * tau * tau;
+    } else {
+        double v1 = P->slide_ratio * v0;
+        double t1 = (v0 - v1) / P->slide_decel;
+        double d1 = (v0 * v0 - v1 * v1) / (2.0 * P->slide_decel);
+        if (t <= t1) return v0 * t - 0.5 * P->slide_decel * t * t;
+        double tau = t - t1, tr = v1 / P->roll_decel;
+        if (tau >= tr) return D;
+        return d1 + v1 * tau - 0.5 * P->roll_decel * tau * tau;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Robot arrival time (reading: the cited predictor is not available).       */
+/* Straight-line 1-D motion with |a| <= A and |v| <= V that ends at rest at   */
+/* the point.  delta is the distance left to cover (centre distance minus the */
+/* robot radius, floored at 0); u is the initial speed along the line toward  */
+/* the point (negative: moving away).                                        */
+/* ------------------------------------------------------------------------ */
+
+/* From rest to rest over distance D: triangular if D < V^2/A, else
+ * accelerate, cruise at V, decelerate. */
+static double rest_to_rest(double D, double A, double V)
+{
+    if (D >= V * V / A) return D / V + V / A;
+    return 2.0 * sqrt(D / A);
+}
+
+double orc_robot_time(const orc_params *P, double delta, double u)
+{
+    double A = P->amax, V = P->vmax;
+    if (u < 0.0) {
+        /* stop first (time -u/A, drifting u^2/2A further away), then go */
+        return -u / A + rest_to_rest(delta + u * u / (2.0 * A), A, V);
+    }
+    double stop = u * u / (2.0 * A);
+    if (stop >= delta) {
+        /* cannot stop in time: overshoot, stop, come back */
+        return u / A + rest_to_rest(stop - delta, A, V);
+    }
+    /* accelerate from u to a peak speed, then decelerate to rest */
+    double d_acc = (V * V - u * u) / (2.0 * A) + V * V / (2.0 * A);
+    if (delta >= d_acc) return (V - u) / A + V / A + (delta - d_acc) / V;
+    double vp = sqrt(A * delta + 0.5 * u * u);
+    return (2.0 * vp - u) / A;
+}
+
+/* Arrival time of robot (x, y, vx, vy) at point (px, py). */
+static double robot_time_to(const orc_params *P, const double *rb, double px, double py)
+{
+    double dx = px - rb[0], dy = py - rb[1];
+    double rho = sqrt(dx * dx + dy * dy);
+    double delta = rho - P->robot_radius;
+    if (delta < 0.0) delta = 0.0;
+    double u = 0.0;
+    if (rho > 0.0) u = (rb[2] * dx + rb[3] * dy) / rho;
+    if (u > P->vmax) u = P->vmax;
+    if (u < -P->vmax) u = -P->vmax;
+    return orc_robot_time(P, delta, u);
+}
+
+double orc_robot_time_to(const orc_params *P, double x, double y, double vx, double vy,
+                         double px, double py)
+{
+    double rb[4] = {x, y, vx, vy};
+    return robot_time_to(P, rb, px, py);
+}
+
+/* ------------------------------------------------------------------------ */
+/* SBIP for one robot (Sec. 4.2).                                            */
+/* K samples uniform in distance along the segment from the ball b to c:     */
+/* f_k = (k+1)/K, so the kick point is excluded and the target included.     */
+/* The robot intercepts at sample k when its arrival time there does not     */
+/* exceed the ball's; its interception time is the ball time at the first    */
+/* such sample.  Chip samples still in the air cannot be intercepted.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double bx, by, cx, cy, d, D, sf, v0;
+    int type;
+} orc_path;
+
+static double sbip_robot(const orc_params *P, const orc_path *pa, const double *rb, int *k_hit)
+{
+    int K = P->n_samples;
+    for (int k = 0; k < K; ++k) {
+        double f = (double)(k + 1) / (double)K;
+        double s = f * pa->d;
+        if (pa->type == ORC_CHIP && s < pa->sf) continue;
+        double tb = orc_ball_time(P, pa->type, pa->v0, s);
+        double px = pa->bx + f * (pa->cx - pa->bx);
+        double py = pa->by + f * (pa->cy - pa->by);
+        double tr = robot_time_to(P, rb, px, py);
+        if (tr <= tb) {
+            if (k_hit) *k_hit = k;
+            return tb;
+        }
+    }
+    if (k_hit) *k_hit = K;
+    return INFINITY;
+}
+
+double orc_sbip_robot(const orc_params *P, double bx, double by, double cx, double cy,
+                      int type, double v0, double x, double y, double vx, double vy, int *k_hit)
+{
+    orc_path pa;
+    pa.bx = bx; pa.by = by; pa.cx = cx; pa.cy = cy;
+    pa.d = sqrt((cx - bx) * (cx - bx) + (cy - by) * (cy - by));
+    pa.type = type; pa.v0 = v0;
+    orc_ball_range(P, type, v0, &pa.D, &pa.sf);
+    double rb[4] = {x, y, vx, vy};
+    return sbip_robot(P, &pa, rb, k_hit);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Open goal angle (Sec. 4.3 shoot-angle feature, Sec. 4.4 valid angle).     */
+/* Directions from c to the goal mouth [goal_x] x [-w/2, w/2] not shadowed   */
+/* by an opponent disc of the robot radius; opponents at or beyond the goal  */
+/* line do not block; a point inside an opponent disc has angle 0.           */
+/* The depth to the goal line is floored at goal_eps.                        */
+/* ------------------------------------------------------------------------ */
+double orc_open_angle(const orc_params *P, double cx, double cy, int n_opp, const double *opp)
+{
+    double dx = P->goal_x - cx;
+    if (dx < P->goal_eps) dx = P->goal_eps;
+    double lo = atan2(-0.5 * P->goal_width - cy, dx);
+    double hi = atan2(0.5 * P->goal_width - cy, dx);
+    double a[32], b[32];
+    int n = 0;
+    for (int o = 0; o < n_opp; ++o) {
+        const double *r = opp + 4 * o;
+        if (r[0] >= P->goal_x) continue;
+        double ox = r[0] - cx, oy = r[1] - cy;
+        double rho = sqrt(ox * ox + oy * oy);
+        if (rho <= P->robot_radius) return 0.0;
+        double phi = atan2(oy, ox);
+        double al = asin(P->robot_radius / rho);
+        double s = phi - al, e = phi + al;
+        if (s < lo) s = lo;
+        if (e > hi) e = hi;
+        if (e > s && n < 32) {
+            a[n] = s; b[n] = e; ++n;
+        }
+    }
+    /* sort the blocked intervals by start, then merge */
+    for (int i = 1; i < n; ++i) {
+        double sa = a[i], sb = b[i];
+        int j = i - 1;
+        while (j >= 0 && a[j] > sa) {
+            a[j + 1] = a[j]; b[j + 1] = b[j]; --j;
+        }
+        a[j + 1] = sa; b[j + 1] = sb;
+    }
+    double blocked = 0.0, cs = 0.0, ce = 0.0;
+    int open = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!open) { cs = a[i]; ce = b[i]; open = 1; continue; }
+        if (a[i] <= ce) { if (b[i] > ce) ce = b[i]; }
+        else { blocked += ce - cs; cs = a[i]; ce = b[i]; }
+    }
+    if (open) blocked += ce - cs;
+    return (hi - lo) - blocked;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One (point, variant): interception times, feasibility, score.            */
+/* ------------------------------------------------------------------------ */
+static void side_bands(const orc_params *P, const orc_path *pa, const double *robots,
+                       int n, int skip, int k_side, int *amb)
+{
+    int K = P->n_samples;
+    int klim = k_side < K ? k_side : K - 1;
+    for (int j = 0; j < n; ++j) {
+        if (j == skip) continue;
+        const double *rb = robots + 4 * j;
+        for (int k = 0; k <= klim; ++k) {
+            double f = (double)(k + 1) / (double)K;
+            double s = f * pa->d;
+            double px = pa->bx + f * (pa->cx - pa->bx);
+            double py = pa->by + f * (pa->cy - pa->by);
+            double tr = robot_time_to(P, rb, px, py);
+            if (pa->type == ORC_CHIP && fabs(s - pa->sf) < P->eps_land) {
+                double tb_land = s / (pa->v0 * cos(P->chip_angle));
+                if (tr <= tb_land + P->eps_cross_t) *amb |= ORC_AMB_LAND;
+            }
+            if (pa->type == ORC_CHIP && s < pa->sf) continue;
+            double tb = orc_ball_time(P, pa->type, pa->v0, s);
+            if (fabs(tr - tb) < P->eps_cross_t) *amb |= ORC_AMB_CROSS;
+            double sb = orc_ball_dist(P, pa->type, pa->v0, tr);
+            if (fabs(sb - s) < P->eps_cross_s) *amb |= ORC_AMB_CROSS;
+        }
+    }
+}
+
+void orc_eval(const orc_params *P, const orc_world *W, int type, double v0,
+              double cx, double cy, int bands, orc_result *out)
+{
+    orc_path pa;
+    pa.bx = W->ball_x; pa.by = W->ball_y; pa.cx = cx; pa.cy = cy;
+    pa.d = sqrt((cx - pa.bx) * (cx - pa.bx) + (cy - pa.by) * (cy - pa.by));
+    pa.type = type; pa.v0 = v0;
+    orc_ball_range(P, type, v0, &pa.D, &pa.sf);
+
+    memset(out, 0, sizeof(*out));
+    out->open_angle = orc_open_angle(P, cx, cy, W->n_opp, W->opp);
+    int amb = 0;
+    if (bands) {
+        if (fabs(pa.d - pa.D) < P->eps_reach) amb |= ORC_AMB_REACH;
+        if (type == ORC_CHIP && fabs(pa.d - pa.sf) < P->eps_reach) amb |= ORC_AMB_REACH;
+    }
+    /* a point at the ball cannot be passed to; beyond the stopping distance
+     * (or, for a chip, short of the landing point) it is not reachable */
+    int reachable = pa.d >= 1e-9 && pa.d <= pa.D && (type != ORC_CHIP || pa.d >= pa.sf);
+    out->reachable = reachable;
+    if (!reachable) {
+        out->t_team = INFINITY;
+        out->t_opp = INFINITY;
+        out->margin = -INFINITY;
+        out->score = -INFINITY;
+        out->feasible = 0;
+        out->ambig = amb;
+        return;
+    }
+    double t_team = INFINITY, t_opp = INFINITY;
+    int k_team = P->n_samples, k_opp = P->n_samples;
+    for (int j = 0; j < W->n_team; ++j) {
+        if (j == W->passer) continue;
+        int kh;
+        double tau = sbip_robot(P, &pa, W->team + 4 * j, &kh);
+        if (tau < t_team) t_team = tau;
+        if (kh < k_team) k_team = kh;
+    }
+    for (int j = 0; j < W->n_opp; ++j) {
+        int kh;
+        double tau = sbip_robot(P, &pa, W->opp + 4 * j, &kh);
+        if (tau < t_opp) t_opp = tau;
+        if (kh < k_opp) k_opp = kh;
+    }
+    double m;
+    if (!isfinite(t_team)) m = -INFINITY;
+    else if (!isfinite(t_opp)) m = INFINITY;
+    else m = t_opp - t_team;
+    int feasible = isfinite(t_team) && m >= P->margin_s;
+    out->t_team = t_team;
+    out->t_opp = t_opp;
+    out->margin = m;
+    out->feasible = feasible;
+    if (feasible) {
+        double gx = cx - P->goal_x, gy = cy;
+        double dg = sqrt(gx * gx + gy * gy);
+        double mc = m < 0.0 ? 0.0 : (m > P->margin_cap_s ? P->margin_cap_s : m);
+        out->score = P->w_angle * out->open_angle / M_PI + P->w_dist * (1.0 - dg / P->dist_norm)
+                   + P->w_margin * mc;
+    } else {
+        out->score = -INFINITY;
+    }
+    if (bands) {
+        side_bands(P, &pa, W->team, W->n_team, W->passer, k_team, &amb);
+        side_bands(P, &pa, W->opp, W->n_opp, -1, k_opp, &amb);
+        if (isfinite(t_team) && isfinite(m) && fabs(m - P->margin_s) < P->eps_margin)
+            amb |= ORC_AMB_MARGIN;
+    }
+    out->ambig = amb;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice (reading): field-centred, endpoints included.  At spacing h the   */
+/* lattice has Nx = round(L/h) + 1 by Ny = round(W/h) + 1 points and point   */
+/* (I, J) sits at (h (I - (Nx-1)/2), h (J - (Ny-1)/2)).  A window (h, i0, j0,*/
+/* nx, ny) holds the points I = i0 + i, J = j0 + j.                          */
+/* ------------------------------------------------------------------------ */
+void orc_point(const orc_params *P, double h, int I, int J, double *x, double *y)
+{
+    int Nx = (int)lround(P->field_len / h) + 1;
+    int Ny = (int)lround(P->field_wid / h) + 1;
+    *x = h * ((double)I - 0.5 * (double)(Nx - 1));
+    *y = h * ((double)J - 0.5 * (double)(Ny - 1));
+}
+
+/* Whole frame.  Windows are (h, i0, j0, nx, ny) with h given as a double and
+ * the integers in win_int[4*w ..].  Outputs are laid out window-major, then
+ * variant-major, then row-major [ny][nx]; any output pointer may be NULL.
+ * Returns the number of evaluations. */
+int64_t orc_search(const orc_params *P, const orc_world *W,
+                   int n_win, const double *win_h, const int32_t *win_int,
+                   int n_var, const int32_t *var_type, const double *var_v0,
+                   int bands,
+                   uint8_t *mask, double *score, double *t_team, double *t_opp,
+                   double *margin, uint8_t *ambig)
+{
+    int64_t base = 0;
+    for (int w = 0; w < n_win; ++w) {
+        double h = win_h[w];
+        int i0 = win_int[4 * w], j0 = win_int[4 * w + 1];
+        int nx = win_int[4 * w + 2], ny = win_int[4 * w + 3];
+        int64_t npts = (int64_t)nx * ny;
+#ifdef _OPENMP
+        int nt = P->n_threads > 0 ? P->n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
+#endif
+        for (int64_t p = 0; p < npts; ++p) {
+            int i = (int)(p % nx), j = (int)(p / nx);
+            double cx, cy;
+            orc_point(P, h, i0 + i, j0 + j, &cx, &cy);
+            for (int v = 0; v < n_var; ++v) {
+                orc_result r;
+                orc_eval(P, W, var_type[v], var_v0[v], cx, cy, bands, &r);
+                int64_t o = base + (int64_t)v * npts + p;
+                if (mask) mask[o] = (uint8_t)r.feasible;
+                if (score) score[o] = r.score;
+                if (t_team) t_team[o] = r.t_team;
+                if (t_opp) t_opp[o] = r.t_opp;
+                if (margin) margin[o] = r.margin;
+                if (ambig) ambig[o] = (uint8_t)r.ambig;
+            }
+        }
+        base += npts * n_var;
+    }
+    return base;
+}
+
+/* A list of points given by coordinates; outputs are [point][variant]. */
+void orc_search_points(const orc_params *P, const orc_world *W, int64_t n_pts, const double *xy,
+                       int n_var, const int32_t *var_type, const double *var_v0, int bands,
+                       uint8_t *mask, double *score, double *t_team, double *t_opp,
+                       double *margin, uint8_t *ambig)
+{
+#ifdef _OPENMP
+    int nt = P->n_threads > 0 ? P->n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+#endif
+    for (int64_t p = 0; p < n_pts; ++p) {
+        for (int v = 0; v < n_var; ++v) {
+            orc_result r;
+            orc_eval(P, W, var_type[v], var_v0[v], xy[2 * p], xy[2 * p + 1], bands, &r);
+            int64_t o = p * n_var + v;
+            if (mask) mask[o] = (uint8_t)r.feasible;
+            if (score) score[o] = r.score;
+            if (t_team) t_team[o] = r.t_team;
+            if (t_opp) t_opp[o] = r.t_opp;
+            if (margin) margin[o] = r.margin;
+            if (ambig) ambig[o] = (uint8_t)r.ambig;
+        }
+    }
+}
+
+/* Best entry of a score array: largest score, ties to the lowest index.
+ * Returns the index, or -1 when no entry is finite (no feasible pass). */
+int64_t orc_argmax(int64_t n, const double *score)
+{
+    int64_t best = -1;
+    double bs = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        if (score[i] > bs) { bs = score[i]; best = i; }
+    }
+    return best;
+}
+
+int orc_abi_version(void) { return 1; }

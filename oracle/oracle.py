@@ -1,0 +1,243 @@
+"""ctypes front end of the FP64 oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU
+baseline leg of the benchmark are its only users.  It imports nothing from the
+product package; frames and parameters are read by attribute (any object with
+``team``, ``opp``, ``passer``, ``ball``, ``windows``, ``variants`` works).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN = 1, 2, 4, 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
+                               "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class OrcParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "field_len", "field_wid", "goal_x", "goal_width", "robot_radius", "vmax", "amax",
+        "slide_decel", "roll_decel", "slide_ratio", "chip_angle", "gravity", "margin_s",
+        "margin_cap_s", "w_angle", "w_dist", "w_margin", "dist_norm", "goal_eps")] + [
+        ("n_samples", C.c_int32), ("n_threads", C.c_int32)] + [
+        (n, C.c_double) for n in ("eps_reach", "eps_land", "eps_cross_t", "eps_cross_s",
+                                  "eps_margin")]
+
+
+class OrcWorld(C.Structure):
+    _fields_ = [("n_team", C.c_int32), ("n_opp", C.c_int32), ("passer", C.c_int32),
+                ("pad", C.c_int32), ("team", C.POINTER(C.c_double)),
+                ("opp", C.POINTER(C.c_double)), ("ball_x", C.c_double), ("ball_y", C.c_double)]
+
+
+class OrcResult(C.Structure):
+    _fields_ = [("reachable", C.c_int32), ("feasible", C.c_int32), ("ambig", C.c_int32),
+                ("pad", C.c_int32), ("t_team", C.c_double), ("t_opp", C.c_double),
+                ("margin", C.c_double), ("score", C.c_double), ("open_angle", C.c_double)]
+
+
+# Parity bands (widths of the ambiguity regions computed by the oracle).
+DEFAULT_BANDS = dict(eps_reach=1e-4, eps_land=1e-5, eps_cross_t=1e-5, eps_cross_s=1e-5,
+                     eps_margin=1e-3)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(LIB)
+        d, i32, i64 = C.c_double, C.c_int32, C.c_int64
+        P, Wp = C.POINTER(OrcParams), C.POINTER(OrcWorld)
+        pd, pu8, pi32 = C.POINTER(C.c_double), C.POINTER(C.c_uint8), C.POINTER(C.c_int32)
+        L.orc_ball_range.argtypes = [P, C.c_int, d, pd, pd]
+        L.orc_ball_time.argtypes = [P, C.c_int, d, d]
+        L.orc_ball_time.restype = d
+        L.orc_ball_dist.argtypes = [P, C.c_int, d, d]
+        L.orc_ball_dist.restype = d
+        L.orc_robot_time.argtypes = [P, d, d]
+        L.orc_robot_time.restype = d
+        L.orc_robot_time_to.argtypes = [P, d, d, d, d, d, d]
+        L.orc_robot_time_to.restype = d
+        L.orc_sbip_robot.argtypes = [P, d, d, d, d, C.c_int, d, d, d, d, d, C.POINTER(C.c_int)]
+        L.orc_sbip_robot.restype = d
+        L.orc_open_angle.argtypes = [P, d, d, C.c_int, pd]
+        L.orc_open_angle.restype = d
+        L.orc_eval.argtypes = [P, Wp, C.c_int, d, d, d, C.c_int, C.POINTER(OrcResult)]
+        L.orc_point.argtypes = [P, d, C.c_int, C.c_int, pd, pd]
+        L.orc_search.argtypes = [P, Wp, C.c_int, pd, pi32, C.c_int, pi32, pd, C.c_int,
+                                 pu8, pd, pd, pd, pd, pu8]
+        L.orc_search.restype = i64
+        L.orc_search_points.argtypes = [P, Wp, i64, pd, C.c_int, pi32, pd, C.c_int,
+                                        pu8, pd, pd, pd, pd, pu8]
+        L.orc_argmax.argtypes = [i64, pd]
+        L.orc_argmax.restype = i64
+        _lib = L
+    return _lib
+
+
+def make_params(p, n_threads: int = 0, **bands) -> OrcParams:
+    """Oracle parameters from any object with the Params attributes."""
+    o = OrcParams()
+    for name, _ in OrcParams._fields_:
+        if name in ("n_threads",) or name.startswith("eps_"):
+            continue
+        setattr(o, name, getattr(p, name))
+    o.n_threads = int(n_threads)
+    b = dict(DEFAULT_BANDS)
+    b.update(bands)
+    for k, v in b.items():
+        setattr(o, k, float(v))
+    return o
+
+
+class _WorldHolder:
+    """Keeps the float64 robot arrays alive while the C side points into them."""
+
+    def __init__(self, frame):
+        self.team = np.ascontiguousarray(np.asarray(frame.team, dtype=np.float64).reshape(-1, 4))
+        self.opp = np.ascontiguousarray(np.asarray(frame.opp, dtype=np.float64).reshape(-1, 4))
+        if self.opp.size == 0:
+            self.opp = np.zeros((1, 4))
+        w = OrcWorld()
+        w.n_team = int(np.asarray(frame.team).reshape(-1, 4).shape[0])
+        w.n_opp = int(np.asarray(frame.opp).reshape(-1, 4).shape[0])
+        w.passer = int(frame.passer)
+        w.team = self.team.ctypes.data_as(C.POINTER(C.c_double))
+        w.opp = self.opp.ctypes.data_as(C.POINTER(C.c_double))
+        w.ball_x = float(frame.ball[0])
+        w.ball_y = float(frame.ball[1])
+        self.w = w
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(C.POINTER(t))
+
+
+def search_frame(frame, params, bands: bool = False, n_threads: int = 0, **band_eps):
+    """Run the oracle on every (window, variant, point) of a frame.
+
+    Returns a dict of flat arrays in output order (window-major, then variant,
+    then row-major [ny][nx]) plus ``best`` (index or -1) and ``best_score``.
+    """
+    L = lib()
+    P = make_params(params, n_threads, **band_eps)
+    wh = _WorldHolder(frame)
+    win_h = np.array([w[0] for w in frame.windows], dtype=np.float64)
+    win_i = np.array([[w[1], w[2], w[3], w[4]] for w in frame.windows], dtype=np.int32).reshape(-1)
+    vt = np.array([v[0] for v in frame.variants], dtype=np.int32)
+    vv = np.array([v[1] for v in frame.variants], dtype=np.float64)
+    n = int(sum(w[3] * w[4] for w in frame.windows)) * len(frame.variants)
+    out = dict(mask=np.zeros(n, np.uint8), score=np.zeros(n), t_team=np.zeros(n),
+               t_opp=np.zeros(n), margin=np.zeros(n), ambig=np.zeros(n, np.uint8))
+    L.orc_search(C.byref(P), C.byref(wh.w), len(win_h), _ptr(win_h, C.c_double),
+                 _ptr(win_i, C.c_int32), len(vt), _ptr(vt, C.c_int32), _ptr(vv, C.c_double),
+                 int(bands), _ptr(out["mask"], C.c_uint8), _ptr(out["score"], C.c_double),
+                 _ptr(out["t_team"], C.c_double), _ptr(out["t_opp"], C.c_double),
+                 _ptr(out["margin"], C.c_double), _ptr(out["ambig"], C.c_uint8))
+    best = int(L.orc_argmax(n, _ptr(out["score"], C.c_double)))
+    out["best"] = best
+    out["best_score"] = float(out["score"][best]) if best >= 0 else float("-inf")
+    return out
+
+
+def search_points(frame, params, xy, bands: bool = False, n_threads: int = 0, **band_eps):
+    """Oracle at explicit points ``xy`` (n, 2); outputs shaped (n, n_variants)."""
+    L = lib()
+    P = make_params(params, n_threads, **band_eps)
+    wh = _WorldHolder(frame)
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64).reshape(-1, 2))
+    vt = np.array([v[0] for v in frame.variants], dtype=np.int32)
+    vv = np.array([v[1] for v in frame.variants], dtype=np.float64)
+    n, V = xy.shape[0], len(vt)
+    out = dict(mask=np.zeros((n, V), np.uint8), score=np.zeros((n, V)), t_team=np.zeros((n, V)),
+               t_opp=np.zeros((n, V)), margin=np.zeros((n, V)), ambig=np.zeros((n, V), np.uint8))
+    L.orc_search_points(C.byref(P), C.byref(wh.w), n, _ptr(xy, C.c_double), V,
+                        _ptr(vt, C.c_int32), _ptr(vv, C.c_double), int(bands),
+                        _ptr(out["mask"], C.c_uint8), _ptr(out["score"], C.c_double),
+                        _ptr(out["t_team"], C.c_double), _ptr(out["t_opp"], C.c_double),
+                        _ptr(out["margin"], C.c_double), _ptr(out["ambig"], C.c_uint8))
+    return out
+
+
+def eval_point(frame, params, vtype: int, v0: float, cx: float, cy: float, bands: bool = False):
+    L = lib()
+    P = make_params(params)
+    wh = _WorldHolder(frame)
+    r = OrcResult()
+    L.orc_eval(C.byref(P), C.byref(wh.w), vtype, v0, cx, cy, int(bands), C.byref(r))
+    return {k: getattr(r, k) for k, _ in OrcResult._fields_ if k != "pad"}
+
+
+def points_of_window(params, win):
+    """Coordinates (ny*nx, 2) of a window's points, row-major, from the oracle."""
+    L = lib()
+    P = make_params(params)
+    h, i0, j0, nx, ny = win
+    out = np.zeros((ny * nx, 2))
+    x, y = C.c_double(), C.c_double()
+    for j in range(ny):
+        for i in range(nx):
+            L.orc_point(C.byref(P), h, i0 + i, j0 + j, C.byref(x), C.byref(y))
+            out[j * nx + i] = (x.value, y.value)
+    return out
+
+
+# scalar primitives -----------------------------------------------------------
+
+def ball_range(params, vtype, v0):
+    P = make_params(params)
+    D, sf = C.c_double(), C.c_double()
+    lib().orc_ball_range(C.byref(P), vtype, v0, C.byref(D), C.byref(sf))
+    return D.value, sf.value
+
+
+def ball_time(params, vtype, v0, s):
+    return lib().orc_ball_time(C.byref(make_params(params)), vtype, v0, s)
+
+
+def ball_dist(params, vtype, v0, t):
+    return lib().orc_ball_dist(C.byref(make_params(params)), vtype, v0, t)
+
+
+def robot_time(params, delta, u):
+    return lib().orc_robot_time(C.byref(make_params(params)), delta, u)
+
+
+def robot_time_to(params, robot, px, py):
+    x, y, vx, vy = [float(a) for a in robot]
+    return lib().orc_robot_time_to(C.byref(make_params(params)), x, y, vx, vy, px, py)
+
+
+def sbip_robot(params, ball, c, vtype, v0, robot):
+    k = C.c_int()
+    x, y, vx, vy = [float(a) for a in robot]
+    t = lib().orc_sbip_robot(C.byref(make_params(params)), float(ball[0]), float(ball[1]),
+                             float(c[0]), float(c[1]), vtype, v0, x, y, vx, vy, C.byref(k))
+    return t, k.value
+
+
+def open_angle(params, cx, cy, opp):
+    o = np.ascontiguousarray(np.asarray(opp, dtype=np.float64).reshape(-1, 4))
+    n = o.shape[0]
+    if n == 0:
+        o = np.zeros((1, 4))
+    return lib().orc_open_angle(C.byref(make_params(params)), cx, cy, n, _ptr(o, C.c_double))
