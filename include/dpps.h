@@ -1,0 +1,192 @@
+/*
+ * dpps.h -- C ABI of the MI355X passing-point search (SBIP-DPPS).
+ *
+ * The search is the one of arXiv 1909.07717, Sec. 4.2-4.3: for every candidate
+ * point of a lattice over the field and every pass variant (kick type and
+ * speed) it takes the ideal two-phase ball model of Sec. 4.1, finds each
+ * robot's earliest interception along the sampled ball path (SBIP, Sec. 4.2),
+ * keeps the pass when the first opponent arrives sufficiently later than the
+ * first teammate (Sec. 4.3, delta-time feature), scores it with the weighted
+ * sum of Eq. (3) and returns the best one (Sec. 4.3, best pass line).
+ *
+ * Conventions
+ *   - Plain C types only.  Host pointers are read during the call and may be
+ *     reused as soon as it returns.  Device pointers are allocated and owned by
+ *     the caller (any HIP allocation on the context's device).
+ *   - Every entry point returns 0 (DPPS_OK) or a negative DPPS_E_* code; no C++
+ *     exception crosses this boundary.  dpps_strerror() names a code and
+ *     dpps_last_error() describes the last failure on the calling thread.
+ *   - A context is not thread safe: one context per host thread or stream, and
+ *     calls on one context are serialised by the caller.
+ *   - Units: metres, seconds, m/s, m/s^2, radians.  +x attacks the goal at
+ *     x = goal_x.
+ */
+#ifndef DPPS_H
+#define DPPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes -------------------------------------------------------- */
+#define DPPS_OK 0
+#define DPPS_E_INVALID (-1)     /* bad argument: NaN/Inf input, count or index out of range, window
+                                   outside the lattice, spacing that does not divide the field,
+                                   K not 64, 128, 192 or 256, v0 <= 0, NULL where required */
+#define DPPS_E_NOMEM (-2)       /* a host or device allocation failed */
+#define DPPS_E_DEVICE (-3)      /* a HIP call failed (see dpps_last_error) */
+#define DPPS_E_BUDGET (-4)      /* the request needs more device memory than the budget allows */
+#define DPPS_E_UNSUPPORTED (-5) /* valid but not built (e.g. more than 64 variants in a frame) */
+
+/* ---- pass variants ------------------------------------------------------ */
+#define DPPS_FLAT 0 /* flat kick: slides down to slide_ratio * v0, then rolls to rest (Sec. 4.1) */
+#define DPPS_CHIP 1 /* chip kick: drag-free flight at chip_angle, then rolls; not interceptable
+                       in the air (Sec. 4.3 chip passes; the paper gives no chip model) */
+
+/* ---- output modes (dpps_params.out_flags) ------------------------------ */
+#define DPPS_OUT_REDUCED 1u /* per point only: score = best over variants, mask = that variant's
+                               index (255: none); layout window-major [ny][nx] */
+
+#define DPPS_MAX_SIDE 16     /* robots per team (the paper assumes 16 a side, Sec. 4.2) */
+#define DPPS_MAX_VARIANTS 64 /* pass variants per frame */
+
+typedef struct dpps_ctx dpps_ctx;
+typedef struct dpps_batch dpps_batch;
+
+/* Robot state: position (m) and velocity (m/s). */
+typedef struct {
+    float x, y, vx, vy;
+} dpps_robot;
+
+/* A window of the field-centred lattice of spacing h.  The full lattice has
+ * Nx = round(field_len/h) + 1 by Ny = round(field_wid/h) + 1 points (h must
+ * divide both field dimensions); lattice point (I, J) sits at
+ * (h (I - (Nx-1)/2), h (J - (Ny-1)/2)).  The window holds I = i0 .. i0+nx-1,
+ * J = j0 .. j0+ny-1. */
+typedef struct {
+    float h;
+    int32_t i0, j0, nx, ny;
+} dpps_window;
+
+/* A pass variant: kick type (DPPS_FLAT / DPPS_CHIP) and kick speed v0 (m/s). */
+typedef struct {
+    int32_t type;
+    float v0;
+} dpps_variant;
+
+/* One frame of a request.  Its robots are robots[robot_off .. robot_off +
+ * n_team + n_opp): the team first (passer included at index `passer` within
+ * the team), then the opponents.  Its windows and variants are likewise slices
+ * of the window and variant arrays.  out_off is the element offset of the
+ * frame's first output (filled in by dpps_layout).  The ball is at
+ * (ball_x, ball_y); the passer is never an interceptor. */
+typedef struct {
+    int32_t n_team, n_opp, passer, robot_off;
+    int32_t n_windows, window_off, n_variants, variant_off;
+    int64_t out_off;
+    float ball_x, ball_y;
+} dpps_frame;
+
+/* Geometry, motion limits, ball model and scoring constants, and the sample
+ * count K.  The score of a feasible pass is
+ *   w_angle * open_goal_angle / pi + w_dist * (1 - |c - goal| / dist_norm)
+ *   + w_margin * clamp(t_opp - t_team, 0, margin_cap_s)
+ * (Eq. 3 with lengths and angles divided by their upper bound, Sec. 4.3). */
+typedef struct {
+    float field_len, field_wid, goal_x, goal_width; /* 12, 9, 6, 1.2 */
+    float robot_radius, vmax, amax;                 /* 0.09, 3.25 (Sec. 2.1), 3 */
+    float slide_decel, roll_decel, slide_ratio;     /* 5, 0.5, 5/7 (Sec. 4.1) */
+    float chip_angle, gravity;                      /* pi/4, 9.81 */
+    int32_t n_samples;                              /* K: 64, 128, 192 or 256 */
+    float margin_s, margin_cap_s;                   /* 0.1, 1.0 */
+    float w_angle, w_dist, w_margin, dist_norm;     /* 0.5, 0.3, 0.2, 15 */
+    float goal_eps;                                 /* floor of the depth to the goal line, 1e-3 */
+    uint32_t out_flags;                             /* 0 or DPPS_OUT_REDUCED */
+    uint32_t reserved;                              /* must be 0 */
+    uint64_t hbm_budget_bytes;                      /* 0: no limit */
+} dpps_params;
+
+/* Device-side outputs of a search.  Element e of a frame is the (window,
+ * variant, point) with e = out_off + window base + variant * nx*ny + j*nx + i
+ * (window-major, then variant-major, then row-major); with DPPS_OUT_REDUCED
+ * the variant axis is dropped.  Any map pointer may be NULL (not written). */
+typedef struct {
+    uint8_t *mask;  /* 1 where the pass is feasible (REDUCED: best variant or 255) */
+    float *score;   /* score where feasible, -inf elsewhere (REDUCED: best score) */
+    float *t_team;  /* first-teammate interception time, +inf if none (not with REDUCED) */
+    float *t_opp;   /* first-opponent interception time, +inf if none (not with REDUCED) */
+    struct dpps_best_s *best; /* one record per frame (required) */
+} dpps_outputs;
+
+/* The best pass of a frame: largest score, ties to the lowest element index.
+ * found = 0 and score = -inf when no pass is feasible (not an error). */
+typedef struct dpps_best_s {
+    int32_t found, window, variant, i, j, type;
+    float x, y, v0, score, t_team, t_opp, t_ball; /* t_ball: ball time to the point */
+    int32_t pad;
+} dpps_best;
+
+/* Create a context on HIP device `device` that launches on `hip_stream`
+ * (NULL: the context creates its own stream).  Validates and copies *p. */
+int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stream);
+
+/* Wait for the context's work and free what it owns (never caller buffers). */
+void dpps_destroy(dpps_ctx *c);
+
+/* Assign out_off of n_frames frames (densely, in order) and return the total
+ * number of output elements in *total.  Host-only. */
+int dpps_layout(const dpps_params *p, int32_t n_frames, dpps_frame *frames,
+                const dpps_window *windows, int64_t *total);
+
+/* One frame, synchronous: copy the inputs, search, write the maps to the
+ * device outputs and the best pass to *h_best (host).  out->best may be NULL
+ * here (the context keeps a device record).  frame->out_off is honoured. */
+int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,
+                const dpps_window *windows, const dpps_variant *variants,
+                const dpps_outputs *out, dpps_best *h_best);
+
+/* Many frames, asynchronous on `hip_stream` (NULL: the context's stream):
+ * inputs are staged through the context's pinned buffer, then one persistent
+ * launch covers every (frame, window, tile).  Results are valid once the
+ * stream has completed.  Calls on one context must not overlap. */
+int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_variant *variants, const dpps_outputs *out,
+                      void *hip_stream);
+
+/* Device-resident batches: dpps_batch_create validates the frames, builds the
+ * tile list and copies everything to device memory owned by the batch
+ * (synchronous).  dpps_batch_run only launches (inputs already in HBM);
+ * with use_graph != 0 the launches are captured once into a HIP graph keyed
+ * by the output pointers and replayed afterwards. */
+int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_variant *variants, dpps_batch **out);
+int dpps_batch_set_robots(dpps_ctx *c, dpps_batch *b, const dpps_robot *robots, void *hip_stream);
+int dpps_batch_run(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip_stream,
+                   int use_graph);
+void dpps_batch_destroy(dpps_batch *b);
+int64_t dpps_batch_tiles(const dpps_batch *b);
+int64_t dpps_batch_points(const dpps_batch *b);
+
+/* Launch shape: points per tile (a multiple of 8, <= 64) and waves per
+ * workgroup (1, 2, 4 or 8); 0 keeps the current value.  Persistent grids use
+ * `wg_per_cu` workgroups per compute unit (0: default). */
+int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int32_t wg_per_cu);
+int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_wg,
+                    int32_t *wg_per_cu);
+
+/* Device timing of the last dpps_batch_run / dpps_search_batch main kernel
+ * (milliseconds, from HIP events on the launch stream); -1 if unavailable. */
+float dpps_last_kernel_ms(dpps_ctx *c);
+
+const char *dpps_strerror(int code);
+const char *dpps_last_error(void);
+int dpps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPPS_H */

@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libdpps (include/dpps.h).
+
+Argument marshalling only: host inputs are packed into the C structs of the
+ABI, device outputs are torch tensors whose data pointers are handed to the
+library, and the stream is torch's current stream unless one is given.  Every
+step of the search runs in the HIP kernels; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpps.so")
+
+DPPS_OK = 0
+DPPS_FLAT, DPPS_CHIP = 0, 1
+DPPS_OUT_REDUCED = 1
+MAX_SIDE, MAX_VARIANTS = 16, 64
+
+ROBOT_DT = np.dtype([("x", "<f4"), ("y", "<f4"), ("vx", "<f4"), ("vy", "<f4")])
+WINDOW_DT = np.dtype([("h", "<f4"), ("i0", "<i4"), ("j0", "<i4"), ("nx", "<i4"), ("ny", "<i4")])
+VARIANT_DT = np.dtype([("type", "<i4"), ("v0", "<f4")])
+FRAME_DT = np.dtype({
+    "names": ["n_team", "n_opp", "passer", "robot_off", "n_windows", "window_off", "n_variants",
+              "variant_off", "out_off", "ball_x", "ball_y"],
+    "formats": ["<i4"] * 8 + ["<i8", "<f4", "<f4"],
+    "offsets": [0, 4, 8, 12, 16, 20, 24, 28, 32, 40, 44],
+    "itemsize": 48,
+})
+BEST_DT = np.dtype([("found", "<i4"), ("window", "<i4"), ("variant", "<i4"), ("i", "<i4"),
+                    ("j", "<i4"), ("type", "<i4"), ("x", "<f4"), ("y", "<f4"), ("v0", "<f4"),
+                    ("score", "<f4"), ("t_team", "<f4"), ("t_opp", "<f4"), ("t_ball", "<f4"),
+                    ("pad", "<i4")])
+
+
+class DppsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dpps error {code}: {msg}")
+        self.code = code
+
+
+class Params_C(C.Structure):
+    _fields_ = [(n, C.c_float) for n in (
+        "field_len", "field_wid", "goal_x", "goal_width", "robot_radius", "vmax", "amax",
+        "slide_decel", "roll_decel", "slide_ratio", "chip_angle", "gravity")] + [
+        ("n_samples", C.c_int32)] + [(n, C.c_float) for n in (
+            "margin_s", "margin_cap_s", "w_angle", "w_dist", "w_margin", "dist_norm",
+            "goal_eps")] + [("out_flags", C.c_uint32), ("reserved", C.c_uint32),
+                            ("hbm_budget_bytes", C.c_uint64)]
+
+
+class Outputs_C(C.Structure):
+    _fields_ = [("mask", C.c_void_p), ("score", C.c_void_p), ("t_team", C.c_void_p),
+                ("t_opp", C.c_void_p), ("best", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdpps.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.dpps_create.argtypes = [C.POINTER(vp), C.POINTER(Params_C), C.c_int, vp]
+        L.dpps_destroy.argtypes = [vp]
+        L.dpps_destroy.restype = None
+        L.dpps_layout.argtypes = [C.POINTER(Params_C), i32, vp, vp, C.POINTER(i64)]
+        L.dpps_search.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
+        L.dpps_search_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
+        L.dpps_batch_create.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(vp)]
+        L.dpps_batch_set_robots.argtypes = [vp, vp, vp, vp]
+        L.dpps_batch_run.argtypes = [vp, vp, C.POINTER(Outputs_C), vp, C.c_int]
+        L.dpps_batch_destroy.argtypes = [vp]
+        L.dpps_batch_destroy.restype = None
+        L.dpps_batch_tiles.argtypes = [vp]
+        L.dpps_batch_tiles.restype = i64
+        L.dpps_batch_points.argtypes = [vp]
+        L.dpps_batch_points.restype = i64
+        L.dpps_set_launch.argtypes = [vp, i32, i32, i32]
+        L.dpps_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.dpps_last_kernel_ms.argtypes = [vp]
+        L.dpps_last_kernel_ms.restype = C.c_float
+        L.dpps_strerror.argtypes = [C.c_int]
+        L.dpps_strerror.restype = C.c_char_p
+        L.dpps_last_error.argtypes = []
+        L.dpps_last_error.restype = C.c_char_p
+        L.dpps_version.argtypes = []
+        L.dpps_version.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != DPPS_OK:
+        L = lib()
+        raise DppsError(rc, f"{L.dpps_strerror(rc).decode()}: {L.dpps_last_error().decode()}")
+
+
+def params_c(p, out_flags: int = 0, budget: int = 0) -> Params_C:
+    """ABI parameter struct from any object with the Params attributes."""
+    c = Params_C()
+    for name, _ in Params_C._fields_:
+        if name in ("out_flags", "reserved", "hbm_budget_bytes"):
+            continue
+        setattr(c, name, getattr(p, name))
+    c.out_flags = out_flags
+    c.reserved = 0
+    c.hbm_budget_bytes = budget
+    return c
+
+
+@dataclass
+class Packed:
+    """Host arrays of a request in ABI layout."""
+    frames: np.ndarray
+    robots: np.ndarray
+    windows: np.ndarray
+    variants: np.ndarray
+    total: int                      # output elements
+    frame_elems: np.ndarray         # per-frame element counts
+
+
+def pack(frames, p, out_flags: int = 0) -> Packed:
+    """Pack framegen-style frames (team, opp, passer, ball, windows, variants)."""
+    nf = len(frames)
+    fr = np.zeros(nf, FRAME_DT)
+    rob, win, var = [], [], []
+    ro = wo = vo = 0
+    for i, f in enumerate(frames):
+        team = np.asarray(f.team, np.float32).reshape(-1, 4)
+        opp = np.asarray(f.opp, np.float32).reshape(-1, 4)
+        fr[i]["n_team"], fr[i]["n_opp"], fr[i]["passer"] = team.shape[0], opp.shape[0], f.passer
+        fr[i]["robot_off"], fr[i]["window_off"], fr[i]["variant_off"] = ro, wo, vo
+        fr[i]["n_windows"], fr[i]["n_variants"] = len(f.windows), len(f.variants)
+        fr[i]["ball_x"], fr[i]["ball_y"] = float(f.ball[0]), float(f.ball[1])
+        rob.append(np.concatenate([team, opp]))
+        for w in f.windows:
+            win.append(tuple(w))
+        for v in f.variants:
+            var.append((int(v[0]), float(v[1])))
+        ro += team.shape[0] + opp.shape[0]
+        wo += len(f.windows)
+        vo += len(f.variants)
+    robots = np.zeros(ro, ROBOT_DT)
+    if ro:
+        r = np.concatenate(rob).astype(np.float32)
+        robots["x"], robots["y"], robots["vx"], robots["vy"] = r[:, 0], r[:, 1], r[:, 2], r[:, 3]
+    windows = np.array(win, WINDOW_DT) if win else np.zeros(0, WINDOW_DT)
+    variants = np.array(var, VARIANT_DT) if var else np.zeros(0, VARIANT_DT)
+    total = C.c_int64()
+    pc = params_c(p, out_flags)
+    _check(lib().dpps_layout(C.byref(pc), nf, _ptr(fr), _ptr(windows), C.byref(total)))
+    ends = np.append(fr["out_off"][1:], total.value) if nf else np.zeros(0, np.int64)
+    return Packed(fr, robots, windows, variants, int(total.value),
+                  (ends - fr["out_off"]).astype(np.int64) if nf else ends)
+
+
+def _ptr(a):
+    return None if a is None or a.size == 0 else a.ctypes.data
+
+
+def _tptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class DeviceOutputs:
+    """torch tensors for one request's outputs (device memory)."""
+
+    def __init__(self, total: int, n_frames: int, device, mask=True, score=True, times=False):
+        import torch
+        self.mask = torch.empty(total, dtype=torch.uint8, device=device) if mask else None
+        self.score = torch.empty(total, dtype=torch.float32, device=device) if score else None
+        self.t_team = torch.empty(total, dtype=torch.float32, device=device) if times else None
+        self.t_opp = torch.empty(total, dtype=torch.float32, device=device) if times else None
+        self.best = torch.empty(n_frames * BEST_DT.itemsize, dtype=torch.uint8, device=device)
+
+    def c(self) -> Outputs_C:
+        o = Outputs_C()
+        o.mask, o.score = _tptr(self.mask), _tptr(self.score)
+        o.t_team, o.t_opp = _tptr(self.t_team), _tptr(self.t_opp)
+        o.best = _tptr(self.best)
+        return o
+
+    def best_host(self) -> np.ndarray:
+        return np.frombuffer(self.best.cpu().numpy().tobytes(), BEST_DT)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream) if hasattr(stream, "cuda_stream") else C.c_void_p(stream)
+
+
+class Searcher:
+    """A libdpps context on one device."""
+
+    def __init__(self, params, device: int = 0, out_flags: int = 0, budget: int = 0, stream=None):
+        import torch
+        self.params = params
+        self.out_flags = out_flags
+        self.device = torch.device("cuda", device)
+        self.pc = params_c(params, out_flags, budget)
+        h = C.c_void_p()
+        torch.cuda.init()
+        sp = None if stream is None else _stream_ptr(stream)
+        _check(lib().dpps_create(C.byref(h), C.byref(self.pc), device, sp))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().dpps_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, tile_points=0, waves=0, wg_per_cu=0):
+        _check(lib().dpps_set_launch(self.h, tile_points, waves, wg_per_cu))
+
+    def get_launch(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().dpps_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def outputs_for(self, pk: Packed, mask=True, score=True, times=False) -> DeviceOutputs:
+        return DeviceOutputs(pk.total, len(pk.frames), self.device, mask, score, times)
+
+    def search(self, frame, mask=True, score=True, times=False):
+        """One frame, synchronous.  Returns (DeviceOutputs, best record)."""
+        pk = pack([frame], self.params, self.out_flags)
+        out = self.outputs_for(pk, mask, score, times)
+        oc = out.c()
+        best = np.zeros(1, BEST_DT)
+        _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
+                                 _ptr(pk.variants), C.byref(oc), best.ctypes.data))
+        return out, best[0]
+
+    def search_batch(self, frames, mask=True, score=True, times=False, stream=None, out=None):
+        """Many frames, asynchronous on the stream.  Returns (Packed, DeviceOutputs)."""
+        pk = frames if isinstance(frames, Packed) else pack(frames, self.params, self.out_flags)
+        if out is None:
+            out = self.outputs_for(pk, mask, score, times)
+        oc = out.c()
+        _check(lib().dpps_search_batch(self.h, len(pk.frames), _ptr(pk.frames), _ptr(pk.robots),
+                                       _ptr(pk.windows), _ptr(pk.variants), C.byref(oc),
+                                       _stream_ptr(stream)))
+        return pk, out
+
+    def batch(self, frames) -> "Batch":
+        pk = frames if isinstance(frames, Packed) else pack(frames, self.params, self.out_flags)
+        return Batch(self, pk)
+
+    def last_kernel_ms(self) -> float:
+        return float(lib().dpps_last_kernel_ms(self.h))
+
+
+class Batch:
+    """A device-resident batch (inputs uploaded once)."""
+
+    def __init__(self, s: Searcher, pk: Packed):
+        self.s = s
+        self.pk = pk
+        b = C.c_void_p()
+        _check(lib().dpps_batch_create(s.h, len(pk.frames), _ptr(pk.frames), _ptr(pk.robots),
+                                       _ptr(pk.windows), _ptr(pk.variants), C.byref(b)))
+        self.h = b
+
+    @property
+    def tiles(self) -> int:
+        return int(lib().dpps_batch_tiles(self.h))
+
+    @property
+    def points(self) -> int:
+        return int(lib().dpps_batch_points(self.h))
+
+    def run(self, out: DeviceOutputs, stream=None, graph: bool = False):
+        self._oc = out.c()
+        _check(lib().dpps_batch_run(self.s.h, self.h, C.byref(self._oc), _stream_ptr(stream),
+                                    int(graph)))
+
+    def set_robots(self, robots: np.ndarray, stream=None):
+        r = np.ascontiguousarray(robots, ROBOT_DT)
+        _check(lib().dpps_batch_set_robots(self.s.h, self.h, r.ctypes.data, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().dpps_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,733 @@
+// dpps_api.hip -- host runtime and C ABI of libdpps (see include/dpps.h).
+//
+// The runtime validates requests, lays out outputs, builds the tile list
+// (bookkeeping only: which window and which first point each tile covers),
+// stages inputs through pinned memory, and launches the kernels of
+// dpps_kernels.hip.  Every step of the search itself runs on the GPU.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dpps_internal.h"
+
+using namespace dpps;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(DPPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
+
+int lattice_dim(float len, float h, int32_t *n)
+{
+    double q = (double)len / (double)h;
+    double r = nearbyint(q);
+    if (!(fabs(q - r) <= 1e-3) || r < 1.0 || r > 1e6) return -1;
+    *n = (int32_t)r + 1;
+    return 0;
+}
+
+int check_params(const dpps_params *p)
+{
+    if (!p) return fail(DPPS_E_INVALID, "params is NULL");
+    const float pos[] = {p->field_len, p->field_wid, p->goal_width, p->robot_radius, p->vmax,
+                         p->amax, p->slide_decel, p->roll_decel, p->gravity, p->dist_norm,
+                         p->goal_eps};
+    for (float x : pos)
+        if (!finite_pos(x)) return fail(DPPS_E_INVALID, "a positive parameter is not positive/finite");
+    const float fin[] = {p->goal_x, p->margin_s, p->margin_cap_s, p->w_angle, p->w_dist,
+                         p->w_margin};
+    for (float x : fin)
+        if (!isfinite(x)) return fail(DPPS_E_INVALID, "a parameter is not finite");
+    if (!(p->slide_ratio > 0.0f && p->slide_ratio < 1.0f))
+        return fail(DPPS_E_INVALID, "slide_ratio must be in (0, 1)");
+    if (!(p->roll_decel < p->slide_decel))
+        return fail(DPPS_E_INVALID, "roll_decel must be below slide_decel");
+    if (!(p->chip_angle > 0.0f && p->chip_angle < 1.5707f))
+        return fail(DPPS_E_INVALID, "chip_angle must be in (0, pi/2)");
+    if (p->n_samples != 64 && p->n_samples != 128 && p->n_samples != 192 && p->n_samples != 256)
+        return fail(DPPS_E_INVALID, "n_samples must be 64, 128, 192 or 256 (got %d)", p->n_samples);
+    if (p->out_flags & ~DPPS_OUT_REDUCED) return fail(DPPS_E_INVALID, "unknown out_flags bits");
+    if (p->reserved != 0) return fail(DPPS_E_INVALID, "reserved must be 0");
+    if (p->margin_cap_s < 0.0f) return fail(DPPS_E_INVALID, "margin_cap_s < 0");
+    return DPPS_OK;
+}
+
+DevParams derive(const dpps_params *p)
+{
+    DevParams P;
+    memset(&P, 0, sizeof P);
+    double A = p->amax, V = p->vmax, as = p->slide_decel, ar = p->roll_decel;
+    double rho = p->slide_ratio, th = p->chip_angle, g = p->gravity;
+    P.goal_x = p->goal_x;
+    P.half_goal_w = 0.5f * p->goal_width;
+    P.goal_eps = p->goal_eps;
+    P.goal_xA = (float)(p->goal_x * A);
+    P.RA = (float)(p->robot_radius * A);
+    P.V = p->vmax;
+    P.A = p->amax;
+    P.invA = (float)(1.0 / A);
+    P.invV = (float)(1.0 / V);
+    P.a_s = p->slide_decel;
+    P.a_r = p->roll_decel;
+    P.ratio = p->slide_ratio;
+    P.cos_th = (float)cos(th);
+    double lam2 = cos(th), lam3 = 2.0 * sin(th) / g, lam1 = lam2 * lam3;
+    P.lam1_inv = (float)(1.0 / lam1);
+    // flat: slide time k1 v0, slide distance k2 v0^2, roll time k3 v0, roll distance k4 v0^2
+    double k1 = (1.0 - rho) / as, k2 = (1.0 - rho * rho) / (2.0 * as);
+    double k3 = rho / ar, k4 = rho * rho / (2.0 * ar);
+    double cD = k2 + k4, cTs = k1 + k3;
+    P.f_cD = (float)cD;
+    P.f_cA = (float)(cD / (cTs * cTs));
+    P.f_cB = (float)(1.0 / k1 - 0.5 * as);
+    double fal = k2 - rho * k1 - 0.5 * ar * k1 * k1, fbe = rho + ar * k1;
+    P.f_alpha4 = (float)(4.0 * fal);
+    P.f_beta = (float)fbe;
+    P.f_beta2 = (float)(fbe * fbe);
+    P.f_hfast = (float)(0.5 * as);
+    P.f_pfast = 1.0f;
+    // chip: flight time lam3 v0, carry lam1 v0^2, then roll from lam2 v0
+    double ccD = lam1 + lam2 * lam2 / (2.0 * ar), ccTs = lam3 + lam2 / ar;
+    P.c_cD = (float)ccD;
+    P.c_cA = (float)(ccD / (ccTs * ccTs));
+    P.c_cB = (float)(lam2 / lam3);
+    double cal = -0.5 * ar * lam3 * lam3, cbe = lam2 + ar * lam3;
+    P.c_alpha4 = (float)(4.0 * cal);
+    P.c_beta = (float)cbe;
+    P.c_beta2 = (float)(cbe * cbe);
+    P.c_hfast = 0.0f;
+    P.c_pfast = (float)lam2;
+    P.half_ar = (float)(0.5 * ar);
+    P.margin_cap = p->margin_cap_s;
+    P.w_ang_pi = (float)(p->w_angle / M_PI);
+    P.w_dist = p->w_dist;
+    P.inv_dist_norm = (float)(1.0 / p->dist_norm);
+    P.w_margin = p->w_margin;
+    P.K = p->n_samples;
+    P.out_flags = (int32_t)p->out_flags;
+    P.a_s_d = p->slide_decel;
+    P.a_r_d = p->roll_decel;
+    P.ratio_d = p->slide_ratio;
+    P.cos_d = cos((double)p->chip_angle);
+    P.sin_d = sin((double)p->chip_angle);
+    P.g_d = p->gravity;
+    P.margin_d = p->margin_s;
+    P.invK_d = 1.0 / (double)p->n_samples;
+    return P;
+}
+
+// Host-side description of a batch: the device tables before upload.
+struct HostTables {
+    std::vector<FrameDev> frames;
+    std::vector<dpps_robot> robots;
+    std::vector<dpps_variant> variants;
+    std::vector<WinDev> wins;
+    std::vector<TileDev> tiles;
+    int64_t points = 0;
+};
+
+int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
+                 const dpps_robot *robots, const dpps_window *windows,
+                 const dpps_variant *variants, int tile_points, HostTables &T)
+{
+    if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
+    if (n_frames > 0 && (!frames || !robots || !windows || !variants))
+        return fail(DPPS_E_INVALID, "NULL input array");
+    T = HostTables();
+    T.frames.reserve(n_frames);
+    const bool reduced = (p->out_flags & DPPS_OUT_REDUCED) != 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const dpps_frame &F = frames[f];
+        if (F.n_team < 1 || F.n_team > DPPS_MAX_SIDE || F.n_opp < 0 || F.n_opp > DPPS_MAX_SIDE)
+            return fail(DPPS_E_INVALID, "frame %d: n_team %d / n_opp %d out of range", f, F.n_team,
+                        F.n_opp);
+        if (F.passer < 0 || F.passer >= F.n_team)
+            return fail(DPPS_E_INVALID, "frame %d: passer %d out of range", f, F.passer);
+        if (F.robot_off < 0 || F.window_off < 0 || F.variant_off < 0 || F.n_windows < 0)
+            return fail(DPPS_E_INVALID, "frame %d: negative offset", f);
+        if (F.n_variants < 1) return fail(DPPS_E_INVALID, "frame %d: no variants", f);
+        if (F.n_variants > DPPS_MAX_VARIANTS)
+            return fail(DPPS_E_UNSUPPORTED, "frame %d: %d variants (max %d)", f, F.n_variants,
+                        DPPS_MAX_VARIANTS);
+        if (reduced && F.n_variants > 255)
+            return fail(DPPS_E_UNSUPPORTED, "frame %d: too many variants for REDUCED", f);
+        if (!isfinite(F.ball_x) || !isfinite(F.ball_y))
+            return fail(DPPS_E_INVALID, "frame %d: ball not finite", f);
+        if (F.out_off < 0) return fail(DPPS_E_INVALID, "frame %d: out_off < 0", f);
+        FrameDev D;
+        memset(&D, 0, sizeof D);
+        D.n_team = F.n_team;
+        D.n_opp = F.n_opp;
+        D.passer = F.passer;
+        D.robot_off = (int32_t)T.robots.size();
+        D.n_windows = F.n_windows;
+        D.win_off = (int32_t)T.wins.size();
+        D.n_variants = F.n_variants;
+        D.variant_off = (int32_t)T.variants.size();
+        D.ball_x = F.ball_x;
+        D.ball_y = F.ball_y;
+        for (int r = 0; r < F.n_team + F.n_opp; ++r) {
+            const dpps_robot &R = robots[F.robot_off + r];
+            if (!isfinite(R.x) || !isfinite(R.y) || !isfinite(R.vx) || !isfinite(R.vy))
+                return fail(DPPS_E_INVALID, "frame %d robot %d: not finite", f, r);
+            T.robots.push_back(R);
+        }
+        for (int v = 0; v < F.n_variants; ++v) {
+            const dpps_variant &Vv = variants[F.variant_off + v];
+            if (Vv.type != DPPS_FLAT && Vv.type != DPPS_CHIP)
+                return fail(DPPS_E_INVALID, "frame %d variant %d: bad type %d", f, v, Vv.type);
+            if (!finite_pos(Vv.v0) || Vv.v0 > 100.0f)
+                return fail(DPPS_E_INVALID, "frame %d variant %d: v0 must be in (0, 100]", f, v);
+            T.variants.push_back(Vv);
+        }
+        int64_t elem = 0;
+        for (int w = 0; w < F.n_windows; ++w) {
+            const dpps_window &Wn = windows[F.window_off + w];
+            int32_t Nx, Ny;
+            if (!finite_pos(Wn.h) || lattice_dim(p->field_len, Wn.h, &Nx) ||
+                lattice_dim(p->field_wid, Wn.h, &Ny))
+                return fail(DPPS_E_INVALID, "frame %d window %d: spacing %g does not divide the field",
+                            f, w, (double)Wn.h);
+            if (Wn.nx < 0 || Wn.ny < 0 || Wn.i0 < 0 || Wn.j0 < 0 || Wn.i0 + Wn.nx > Nx ||
+                Wn.j0 + Wn.ny > Ny)
+                return fail(DPPS_E_INVALID, "frame %d window %d: outside the %dx%d lattice", f, w,
+                            Nx, Ny);
+            WinDev W;
+            memset(&W, 0, sizeof W);
+            W.h = Wn.h;
+            W.i0 = Wn.i0;
+            W.j0 = Wn.j0;
+            W.nx = Wn.nx;
+            W.ny = Wn.ny;
+            W.halfNx = 0.5f * (float)(Nx - 1);
+            W.halfNy = 0.5f * (float)(Ny - 1);
+            W.frame = f;
+            W.npts = Wn.nx * Wn.ny;
+            W.elem_base = (int32_t)elem;
+            W.out_base = F.out_off + elem;
+            elem += (int64_t)W.npts * (reduced ? 1 : F.n_variants);
+            if (elem >= 0x7FFFFFFF)
+                return fail(DPPS_E_UNSUPPORTED, "frame %d: more than 2^31 output elements", f);
+            int32_t widx = (int32_t)T.wins.size();
+            for (int32_t p0 = 0; p0 < W.npts; p0 += tile_points) T.tiles.push_back({widx, p0});
+            T.points += W.npts;
+            T.wins.push_back(W);
+        }
+        T.frames.push_back(D);
+    }
+    // full (non-reduced) keys index elements as window base + v * npts + p
+    if (reduced) {
+        // in REDUCED mode the key still encodes the variant: rebase per frame
+        for (auto &F : T.frames) {
+            int64_t e = 0;
+            for (int w = 0; w < F.n_windows; ++w) {
+                WinDev &W = T.wins[F.win_off + w];
+                W.elem_base = (int32_t)e;
+                e += (int64_t)W.npts * F.n_variants;
+            }
+        }
+    }
+    return DPPS_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// contexts and batches
+// ----------------------------------------------------------------------------
+
+struct DeviceArena {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct dpps_batch {
+    dpps_ctx *ctx = nullptr;
+    HostTables T;
+    int32_t n_frames = 0;
+    int tile_points = 0;
+    DeviceArena arena;       // frames, robots, variants, wins, tiles
+    FrameDev *d_frames = nullptr;
+    dpps_robot *d_robots = nullptr;
+    dpps_variant *d_variants = nullptr;
+    WinDev *d_wins = nullptr;
+    TileDev *d_tiles = nullptr;
+    DeviceArena aux;         // counter, keys, best
+    uint32_t *d_counter = nullptr;
+    unsigned long long *d_keys = nullptr;
+    dpps_best *d_best = nullptr;
+    // graph cache
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    dpps_outputs graph_out;
+    void *graph_stream = nullptr;
+    int graph_cfg[3] = {0, 0, 0};
+};
+
+struct dpps_ctx {
+    dpps_params p;
+    DevParams P;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 256;
+    int tile_points = 32;
+    int waves = 4;
+    int wg_per_cu = 2;
+    int persistent = 1;
+    dpps_batch scratch;      // used by dpps_search / dpps_search_batch
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t staged = nullptr;   // pinned staging consumed
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    uint64_t budget_used = 0;
+};
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes)
+{
+    if (bytes <= A.cap) return DPPS_OK;
+    size_t want = align_up(bytes + bytes / 4, 1 << 16);
+    if (c->p.hbm_budget_bytes && c->budget_used - A.cap + want > c->p.hbm_budget_bytes) {
+        want = bytes;
+        if (c->budget_used - A.cap + want > c->p.hbm_budget_bytes)
+            return fail(DPPS_E_BUDGET, "request needs %zu device bytes; budget %llu (in use %llu)",
+                        bytes, (unsigned long long)c->p.hbm_budget_bytes,
+                        (unsigned long long)c->budget_used);
+    }
+    if (A.ptr) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        HIP_OK(hipFree(A.ptr));
+        c->budget_used -= A.cap;
+        A.ptr = nullptr;
+        A.cap = 0;
+    }
+    if (hipMalloc(&A.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        A.ptr = nullptr;
+        return fail(DPPS_E_NOMEM, "hipMalloc(%zu) failed", want);
+    }
+    A.cap = want;
+    c->budget_used += want;
+    return DPPS_OK;
+}
+
+static void graph_drop(dpps_batch *b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Sizes of the table section of the arena.
+struct Layout {
+    size_t off_frames, off_robots, off_variants, off_wins, off_tiles, total;
+};
+
+static Layout table_layout(const HostTables &T)
+{
+    Layout L;
+    size_t o = 0;
+    L.off_frames = o; o = align_up(o + T.frames.size() * sizeof(FrameDev), 256);
+    L.off_robots = o; o = align_up(o + T.robots.size() * sizeof(dpps_robot), 256);
+    L.off_variants = o; o = align_up(o + T.variants.size() * sizeof(dpps_variant), 256);
+    L.off_wins = o; o = align_up(o + T.wins.size() * sizeof(WinDev), 256);
+    L.off_tiles = o; o = align_up(o + T.tiles.size() * sizeof(TileDev), 256);
+    L.total = o < 256 ? 256 : o;
+    return L;
+}
+
+static void pack_tables(const HostTables &T, const Layout &L, char *dst)
+{
+    if (!T.frames.empty()) memcpy(dst + L.off_frames, T.frames.data(), T.frames.size() * sizeof(FrameDev));
+    if (!T.robots.empty()) memcpy(dst + L.off_robots, T.robots.data(), T.robots.size() * sizeof(dpps_robot));
+    if (!T.variants.empty())
+        memcpy(dst + L.off_variants, T.variants.data(), T.variants.size() * sizeof(dpps_variant));
+    if (!T.wins.empty()) memcpy(dst + L.off_wins, T.wins.data(), T.wins.size() * sizeof(WinDev));
+    if (!T.tiles.empty()) memcpy(dst + L.off_tiles, T.tiles.data(), T.tiles.size() * sizeof(TileDev));
+}
+
+static int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
+{
+    int rc = arena_reserve(c, b->arena, L.total);
+    if (rc) return rc;
+    char *base = (char *)b->arena.ptr;
+    b->d_frames = (FrameDev *)(base + L.off_frames);
+    b->d_robots = (dpps_robot *)(base + L.off_robots);
+    b->d_variants = (dpps_variant *)(base + L.off_variants);
+    b->d_wins = (WinDev *)(base + L.off_wins);
+    b->d_tiles = (TileDev *)(base + L.off_tiles);
+    size_t n = (size_t)(b->n_frames > 0 ? b->n_frames : 1);
+    size_t aux = align_up(sizeof(uint32_t), 256) + align_up(n * 8, 256) + n * sizeof(dpps_best);
+    rc = arena_reserve(c, b->aux, aux);
+    if (rc) return rc;
+    char *ab = (char *)b->aux.ptr;
+    b->d_counter = (uint32_t *)ab;
+    b->d_keys = (unsigned long long *)(ab + 256);
+    b->d_best = (dpps_best *)(ab + 256 + align_up(n * 8, 256));
+    return DPPS_OK;
+}
+
+static int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st,
+                     bool timed)
+{
+    if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
+    if (b->tile_points != c->tile_points)
+        return fail(DPPS_E_INVALID, "batch built for tile_points %d, context now uses %d",
+                    b->tile_points, c->tile_points);
+    LaunchArgs a;
+    memset(&a, 0, sizeof a);
+    a.P = c->P;
+    a.frames = b->d_frames;
+    a.robots = b->d_robots;
+    a.variants = b->d_variants;
+    a.wins = b->d_wins;
+    a.tiles = b->d_tiles;
+    a.n_tiles = (int32_t)b->T.tiles.size();
+    a.n_frames = b->n_frames;
+    a.tile_points = c->tile_points;
+    a.persistent = c->persistent;
+    a.counter = b->d_counter;
+    a.keys = b->d_keys;
+    a.mask = out->mask;
+    a.score = out->score;
+    bool reduced = (c->p.out_flags & DPPS_OUT_REDUCED) != 0;
+    a.t_team = reduced ? nullptr : out->t_team;
+    a.t_opp = reduced ? nullptr : out->t_opp;
+    a.best = out->best ? out->best : b->d_best;
+    int64_t cap = (int64_t)c->n_cu * c->wg_per_cu;
+    int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
+    if (!c->persistent) grid = a.n_tiles;
+    int rc = launch_search(a, c->waves, grid, (void *)st, timed ? (void *)c->ev0 : nullptr,
+                           timed ? (void *)c->ev1 : nullptr);
+    c->timed = timed;
+    if (rc) {
+        hipError_t e = hipGetLastError();
+        return fail(DPPS_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    return DPPS_OK;
+}
+
+extern "C" {
+
+const char *dpps_strerror(int code)
+{
+    switch (code) {
+    case DPPS_OK: return "ok";
+    case DPPS_E_INVALID: return "invalid argument";
+    case DPPS_E_NOMEM: return "out of memory";
+    case DPPS_E_DEVICE: return "HIP device error";
+    case DPPS_E_BUDGET: return "device memory budget exceeded";
+    case DPPS_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown error";
+    }
+}
+
+const char *dpps_last_error(void) { return g_last_error.c_str(); }
+
+int dpps_version(void) { return 1; }
+
+int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stream)
+{
+    if (!out) return fail(DPPS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    int ndev = 0;
+    HIP_OK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(DPPS_E_INVALID, "device %d of %d", device, ndev);
+    dpps_ctx *c = new (std::nothrow) dpps_ctx();
+    if (!c) return fail(DPPS_E_NOMEM, "context allocation failed");
+    c->p = *p;
+    c->P = derive(p);
+    c->device = device;
+    c->scratch.ctx = c;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return fail(DPPS_E_DEVICE, "hipSetDevice(%d) failed", device);
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(DPPS_E_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        dpps_destroy(c);
+        return fail(DPPS_E_DEVICE, "hipEventCreate failed");
+    }
+    *out = c;
+    return DPPS_OK;
+}
+
+static void batch_free_device(dpps_batch *b)
+{
+    graph_drop(b);
+    if (b->arena.ptr) hipFree(b->arena.ptr);
+    if (b->aux.ptr) hipFree(b->aux.ptr);
+    if (b->ctx) b->ctx->budget_used -= b->arena.cap + b->aux.cap;
+    b->arena = DeviceArena();
+    b->aux = DeviceArena();
+}
+
+void dpps_destroy(dpps_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    batch_free_device(&c->scratch);
+    if (c->pinned) hipHostFree(c->pinned);
+    if (c->staged) hipEventDestroy(c->staged);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int dpps_layout(const dpps_params *p, int32_t n_frames, dpps_frame *frames,
+                const dpps_window *windows, int64_t *total)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!total || n_frames < 0 || (n_frames > 0 && (!frames || !windows)))
+        return fail(DPPS_E_INVALID, "bad layout arguments");
+    bool reduced = (p->out_flags & DPPS_OUT_REDUCED) != 0;
+    int64_t off = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        frames[f].out_off = off;
+        if (frames[f].n_windows < 0 || frames[f].window_off < 0)
+            return fail(DPPS_E_INVALID, "frame %d: bad window slice", f);
+        for (int w = 0; w < frames[f].n_windows; ++w) {
+            const dpps_window &W = windows[frames[f].window_off + w];
+            if (W.nx < 0 || W.ny < 0) return fail(DPPS_E_INVALID, "frame %d: negative window", f);
+            off += (int64_t)W.nx * W.ny * (reduced ? 1 : frames[f].n_variants);
+        }
+    }
+    *total = off;
+    return DPPS_OK;
+}
+
+int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int32_t wg_per_cu)
+{
+    if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
+    if (tile_points) {
+        if (tile_points < 8 || tile_points > 64 || tile_points % 8)
+            return fail(DPPS_E_INVALID, "tile_points must be a multiple of 8 in [8, 64]");
+        c->tile_points = tile_points;
+    }
+    if (waves_per_wg) {
+        if (waves_per_wg != 1 && waves_per_wg != 2 && waves_per_wg != 4 && waves_per_wg != 8)
+            return fail(DPPS_E_INVALID, "waves_per_wg must be 1, 2, 4 or 8");
+        c->waves = waves_per_wg;
+    }
+    if (wg_per_cu) {
+        if (wg_per_cu < 0) {
+            c->persistent = 0;
+        } else {
+            if (wg_per_cu > 32) return fail(DPPS_E_INVALID, "wg_per_cu must be <= 32");
+            c->persistent = 1;
+            c->wg_per_cu = wg_per_cu;
+        }
+    }
+    return DPPS_OK;
+}
+
+int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_wg,
+                    int32_t *wg_per_cu)
+{
+    if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
+    if (tile_points) *tile_points = c->tile_points;
+    if (waves_per_wg) *waves_per_wg = c->waves;
+    if (wg_per_cu) *wg_per_cu = c->persistent ? c->wg_per_cu : -1;
+    return DPPS_OK;
+}
+
+int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_variant *variants, const dpps_outputs *out, void *hip_stream)
+{
+    if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
+    if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
+    HIP_OK(hipSetDevice(c->device));
+    dpps_batch *b = &c->scratch;
+    int rc = build_tables(&c->p, n_frames, frames, robots, windows, variants, c->tile_points, b->T);
+    if (rc) return rc;
+    b->n_frames = n_frames;
+    b->tile_points = c->tile_points;
+    graph_drop(b);
+    Layout L = table_layout(b->T);
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    // the previous call's copy must have left the pinned buffer
+    HIP_OK(hipEventSynchronize(c->staged));
+    if (L.total > c->pinned_cap) {
+        if (c->pinned) HIP_OK(hipHostFree(c->pinned));
+        c->pinned = nullptr;
+        size_t want = align_up(L.total + L.total / 4, 1 << 16);
+        if (hipHostMalloc(&c->pinned, want, hipHostMallocDefault) != hipSuccess) {
+            c->pinned_cap = 0;
+            return fail(DPPS_E_NOMEM, "hipHostMalloc(%zu) failed", want);
+        }
+        c->pinned_cap = want;
+    }
+    rc = batch_reserve(c, b, L);
+    if (rc) return rc;
+    pack_tables(b->T, L, (char *)c->pinned);
+    HIP_OK(hipMemcpyAsync(b->arena.ptr, c->pinned, L.total, hipMemcpyHostToDevice, st));
+    HIP_OK(hipEventRecord(c->staged, st));
+    return run_batch(c, b, out, st, true);
+}
+
+int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,
+                const dpps_window *windows, const dpps_variant *variants,
+                const dpps_outputs *out, dpps_best *h_best)
+{
+    if (!c || !frame || !out || !h_best) return fail(DPPS_E_INVALID, "NULL argument");
+    dpps_outputs o = *out;
+    o.best = nullptr;
+    int rc = dpps_search_batch(c, 1, frame, robots, windows, variants, &o, c->stream);
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(h_best, c->scratch.d_best, sizeof(dpps_best), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return DPPS_OK;
+}
+
+int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_variant *variants, dpps_batch **outb)
+{
+    if (!c || !outb) return fail(DPPS_E_INVALID, "NULL argument");
+    *outb = nullptr;
+    HIP_OK(hipSetDevice(c->device));
+    dpps_batch *b = new (std::nothrow) dpps_batch();
+    if (!b) return fail(DPPS_E_NOMEM, "batch allocation failed");
+    b->ctx = c;
+    int rc = build_tables(&c->p, n_frames, frames, robots, windows, variants, c->tile_points, b->T);
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    b->n_frames = n_frames;
+    b->tile_points = c->tile_points;
+    Layout L = table_layout(b->T);
+    rc = batch_reserve(c, b, L);
+    if (rc) {
+        dpps_batch_destroy(b);
+        return rc;
+    }
+    std::vector<char> host(L.total);
+    pack_tables(b->T, L, host.data());
+    if (hipMemcpy(b->arena.ptr, host.data(), L.total, hipMemcpyHostToDevice) != hipSuccess) {
+        dpps_batch_destroy(b);
+        return fail(DPPS_E_DEVICE, "batch upload failed");
+    }
+    *outb = b;
+    return DPPS_OK;
+}
+
+int dpps_batch_set_robots(dpps_ctx *c, dpps_batch *b, const dpps_robot *robots, void *hip_stream)
+{
+    if (!c || !b || !robots) return fail(DPPS_E_INVALID, "NULL argument");
+    // robots are given in the batch's own packed order (frame by frame)
+    size_t n = b->T.robots.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!isfinite(robots[i].x) || !isfinite(robots[i].y) || !isfinite(robots[i].vx) ||
+            !isfinite(robots[i].vy))
+            return fail(DPPS_E_INVALID, "robot %zu not finite", i);
+    memcpy(b->T.robots.data(), robots, n * sizeof(dpps_robot));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    HIP_OK(hipMemcpyAsync(b->d_robots, b->T.robots.data(), n * sizeof(dpps_robot),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return DPPS_OK;
+}
+
+int dpps_batch_run(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip_stream,
+                   int use_graph)
+{
+    if (!c || !b || !out) return fail(DPPS_E_INVALID, "NULL argument");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (!use_graph) return run_batch(c, b, out, st, true);
+    int cfg[3] = {c->tile_points, c->waves, c->persistent ? c->wg_per_cu : -1};
+    bool same = b->exec && memcmp(&b->graph_out, out, sizeof *out) == 0 &&
+                b->graph_stream == (void *)st && memcmp(cfg, b->graph_cfg, sizeof cfg) == 0;
+    if (!same) {
+        graph_drop(b);
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        int rc = run_batch(c, b, out, st, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(DPPS_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        b->graph = g;
+        HIP_OK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+        b->graph_out = *out;
+        b->graph_stream = (void *)st;
+        memcpy(b->graph_cfg, cfg, sizeof cfg);
+    }
+    HIP_OK(hipGraphLaunch(b->exec, st));
+    c->timed = false;
+    return DPPS_OK;
+}
+
+void dpps_batch_destroy(dpps_batch *b)
+{
+    if (!b) return;
+    if (b->ctx && b->ctx->stream) hipStreamSynchronize(b->ctx->stream);
+    batch_free_device(b);
+    delete b;
+}
+
+int64_t dpps_batch_tiles(const dpps_batch *b) { return b ? (int64_t)b->T.tiles.size() : -1; }
+int64_t dpps_batch_points(const dpps_batch *b) { return b ? b->T.points : -1; }
+
+float dpps_last_kernel_ms(dpps_ctx *c)
+{
+    if (!c || !c->timed) return -1.0f;
+    if (hipEventSynchronize(c->ev1) != hipSuccess) return -1.0f;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) return -1.0f;
+    return ms;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// dpps_internal.h -- structures shared by the host runtime and the HIP kernels
+// of libdpps (not part of the public ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/dpps.h"
+
+namespace dpps {
+
+// Constants derived once per context from dpps_params: reciprocals, the
+// robot model in time units scaled by the acceleration limit, and the
+// coefficients that invert the ball model for the critical kick speed.
+struct DevParams {
+    // geometry
+    float goal_x, half_goal_w, goal_eps, goal_xA;
+    float RA;          // robot radius scaled by amax
+    float V, A, invA, invV;
+    // ball model
+    float a_s, a_r, ratio, cos_th, lam1_inv;  // lam1 = sin(2 th) / g  (carry = lam1 v0^2)
+    // flat inversion: stopped / rolling / sliding regimes
+    float f_cD, f_cA, f_cB, f_alpha4, f_beta, f_beta2, f_hfast, f_pfast;
+    // chip inversion: stopped / rolling / in-flight regimes
+    float c_cD, c_cA, c_cB, c_alpha4, c_beta, c_beta2, c_hfast, c_pfast;
+    float half_ar;
+    // scoring
+    float margin_cap, w_ang_pi, w_dist, inv_dist_norm, w_margin;
+    int32_t K;
+    int32_t out_flags;
+    // float64 copies used by the per-variant finish
+    double a_s_d, a_r_d, ratio_d, cos_d, sin_d, g_d, margin_d;
+    double invK_d;
+};
+
+// One (frame, window) pair of a batch.
+struct WinDev {
+    float h;
+    int32_t i0, j0, nx, ny;
+    float halfNx, halfNy;   // (Nx - 1) / 2, (Ny - 1) / 2 of the full lattice
+    int32_t frame;
+    int32_t npts;           // nx * ny
+    int32_t elem_base;      // frame-relative index of this window's first element
+    int64_t out_base;       // absolute output element of this window's first element
+};
+
+// A tile: up to tile_points consecutive points of one window.
+struct TileDev {
+    int32_t win;
+    int32_t p0;
+};
+
+// Device-side copy of a frame (the public struct plus derived indices).
+struct FrameDev {
+    int32_t n_team, n_opp, passer, robot_off;
+    int32_t n_windows, win_off, n_variants, variant_off;
+    float ball_x, ball_y;
+    int32_t pad0, pad1;
+};
+
+struct LaunchArgs {
+    DevParams P;
+    const FrameDev *frames;
+    const dpps_robot *robots;
+    const dpps_variant *variants;
+    const WinDev *wins;
+    const TileDev *tiles;
+    int32_t n_tiles;
+    int32_t n_frames;
+    int32_t tile_points;
+    int32_t persistent;
+    uint32_t *counter;
+    unsigned long long *keys;
+    uint8_t *mask;
+    float *score;
+    float *t_team;
+    float *t_opp;
+    dpps_best *best;
+};
+
+// host-side launchers (dpps_kernels.hip)
+// ev_start / ev_stop (hipEvent_t or NULL) bracket the search kernel only.
+int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
+                  void *ev_stop);
+
+}  // namespace dpps

@@ -1,0 +1,546 @@
+// dpps_kernels.hip -- HIP kernels (gfx950) of the SBIP-DPPS passing-point search.
+//
+// Work decomposition
+//   One workgroup per tile of candidate points (persistent workgroups pull
+//   tiles from an atomic counter).  A wave evaluates one candidate point at a
+//   time with its 64 lanes spread over the K path samples (K/64 per lane):
+//
+//   1. robot stage   for every interceptor and every sample, the robot's
+//                    arrival time (straight line, bounded acceleration and
+//                    speed, at rest on the sample); the minimum over teammates
+//                    and over opponents is kept per sample.  Sample positions
+//                    depend on the point only, so this stage is shared by all
+//                    pass variants (Sec. 4.2 traverses speeds for fixed paths).
+//   2. critical speed per sample, the kick speed at which the ball reaches the
+//                    sample exactly when the first teammate (opponent) does;
+//                    a slower kick is intercepted there, a faster one is not
+//                    (the ball model of Sec. 4.1 is monotone in the kick speed).
+//   3. first crossing per variant, a ballot of "v0 <= critical speed" over the
+//                    samples; the lowest set bit is the first interception
+//                    (SBIP, Sec. 4.2).
+//   4. finish        lanes become variants: ball time at the crossing sample
+//                    (float64), margin, feasibility and the Eq. (3) score
+//                    (Sec. 4.3); results are staged in LDS and written as full
+//                    rows per tile, and the packed (score, index) key of the
+//                    best pass is reduced per wave and merged with atomicMax.
+//
+// The open goal angle (Sec. 4.3/4.4) is computed with lanes = opponents.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dpps_internal.h"
+
+namespace dpps {
+
+#define MAX_ROB (2 * DPPS_MAX_SIDE)
+#define MAX_VAR DPPS_MAX_VARIANTS
+#define MAX_TILE 64
+
+struct VarConst {
+    double va1, a1, va2, a2, soff2, toff2, split, D, sf_reach;
+};
+
+struct StageLDS {
+    float4 rob[MAX_ROB];      // (x A, y A, vx, vy): team interceptors, then opponents
+    float v0[MAX_VAR];
+    int32_t type[MAX_VAR];
+    VarConst vc[MAX_VAR];
+    int32_t n_tm, n_op, n_var, has_flat, has_chip, frame;
+    float bx, by;
+};
+
+struct OutLDS {
+    float score[MAX_VAR * MAX_TILE];
+    uint8_t mask[MAX_VAR * MAX_TILE];
+};
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float med3(float x, float lo, float hi)
+{
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+}
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float unif(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Stage the frame into LDS: interceptors (passer dropped), scaled by amax so
+// that the robot model runs in units where the acceleration limit is 1; the
+// per-variant ball constants in float64.  Called by all threads of a block.
+__device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
+{
+    const DevParams &P = a.P;
+    const FrameDev F = a.frames[f];
+    int tid = threadIdx.x;
+    int nrob = F.n_team + F.n_opp;
+    if (tid < nrob) {
+        dpps_robot r = a.robots[F.robot_off + tid];
+        int slot;
+        if (tid < F.n_team) {
+            slot = tid < F.passer ? tid : tid - 1;
+        } else {
+            slot = F.n_team - 1 + (tid - F.n_team);
+        }
+        if (tid != F.passer || tid >= F.n_team)
+            S.rob[slot] = make_float4(r.x * P.A, r.y * P.A, r.vx, r.vy);
+    }
+    if (tid < F.n_variants) {
+        dpps_variant v = a.variants[F.variant_off + tid];
+        S.v0[tid] = v.v0;
+        S.type[tid] = v.type;
+        double v0 = (double)v.v0;
+        VarConst c;
+        if (v.type == DPPS_CHIP) {
+            double vh = v0 * P.cos_d, vz = v0 * P.sin_d;
+            double tf = 2.0 * vz / P.g_d;
+            double sf = vh * tf;
+            c.va1 = vh; c.a1 = P.a_r_d;             // never used: split < 0
+            c.va2 = vh; c.a2 = P.a_r_d; c.soff2 = sf; c.toff2 = tf;
+            c.split = -1.0;
+            c.D = sf + vh * vh / (2.0 * P.a_r_d);
+            c.sf_reach = sf;
+        } else {
+            double v1 = P.ratio_d * v0;
+            double t1 = (v0 - v1) / P.a_s_d;
+            double d1 = (v0 * v0 - v1 * v1) / (2.0 * P.a_s_d);
+            c.va1 = v0; c.a1 = P.a_s_d;
+            c.va2 = v1; c.a2 = P.a_r_d; c.soff2 = d1; c.toff2 = t1;
+            c.split = d1;
+            c.D = d1 + v1 * v1 / (2.0 * P.a_r_d);
+            c.sf_reach = 0.0;
+        }
+        S.vc[tid] = c;
+    }
+    if (tid == 0) {
+        S.n_tm = F.n_team - 1;
+        S.n_op = F.n_opp;
+        S.n_var = F.n_variants;
+        int hf = 0, hc = 0;
+        for (int v = 0; v < F.n_variants; ++v) {
+            int t = a.variants[F.variant_off + v].type;
+            hf |= t == DPPS_FLAT;
+            hc |= t == DPPS_CHIP;
+        }
+        S.has_flat = hf;
+        S.has_chip = hc;
+        S.frame = f;
+        S.bx = F.ball_x;
+        S.by = F.ball_y;
+    }
+}
+
+// Arrival time of one robot at one sample, multiplied by amax.  Positions are
+// pre-scaled by amax (so distances d become A d); with that scaling the
+// time-optimal straight-line motion that ends at rest has
+//   A T = R(D') + sigma u,   R(D) = 2 min(sqrt D, V) + max(0, D - V^2) / V,
+// where u is the speed toward the point (clamped to +-V), s = u^2/2 the
+// scaled stopping distance, and either (overshoot: the robot cannot stop
+// before the point, or is already there at rest) D' = s - delta, sigma = +1,
+// or D' = s + delta, sigma = -1 (moving toward) / +1 (moving away).
+__device__ __forceinline__ float robot_time_A(float4 r, float pxA, float pyA, const DevParams &P)
+{
+    float dx = pxA - r.x;
+    float dy = pyA - r.y;
+    float r2 = fmaf(dx, dx, dy * dy);
+    r2 = fmaxf(r2, 1e-30f);
+    float inv = rsq(r2);
+    float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
+    float wd = fmaf(r.z, dx, r.w * dy);
+    float u = med3(wd * inv, -P.V, P.V);
+    float hu = 0.5f * u;
+    float st = hu * u;
+    float ss = hu * fabsf(u);
+    bool over = ss >= del;
+    float Dp = st + (over ? -del : del);
+    float sg = over ? u : -u;
+    float vp = fminf(hsqrt(Dp), P.V);
+    float cr = fmaxf(fmaf(Dp, P.invV, -P.V), 0.0f);
+    return fmaf(2.0f, vp, cr) + sg;
+}
+
+// Kick speed at which the ball covers distance s in exactly time T (the
+// ball's distance at a fixed time grows with the kick speed).  Regimes at
+// time T: stopped (s <= cA T^2), decelerating at the slower rate
+// (quadratic in v0), or still in the fast phase (s >= cB T^2: sliding for a
+// flat kick, in the air for a chip).  Each root is written N / (Pp + sqrt M).
+__device__ __forceinline__ float vcrit(float T, float s, float cD, float cA, float cB,
+                                       float alpha4, float beta, float beta2, float hfast,
+                                       float pfast, float half_ar)
+{
+    float T2 = T * T;
+    float Q = fmaf(half_ar, T2, s);
+    bool stop = s <= cA * T2;
+    bool fast = s >= cB * T2;
+    float N = stop ? s : (fast ? fmaf(hfast, T2, s) : 2.0f * Q);
+    float Pp = stop ? 0.0f : (fast ? pfast * T : beta * T);
+    float M = stop ? s * cD : (fast ? 0.0f : fmaf(alpha4, Q, beta2 * T2));
+    float v = N * hrcp(Pp + hsqrt(fmaxf(M, 0.0f)));
+    return T == INFINITY ? 0.0f : v;
+}
+
+// Ball time (float64) to distance s for staged variant c.
+__device__ __forceinline__ double ball_time64(const VarConst &c, double s)
+{
+    bool ph1 = s <= c.split;
+    double va = ph1 ? c.va1 : c.va2;
+    double ac = ph1 ? c.a1 : c.a2;
+    double so = ph1 ? 0.0 : c.soff2;
+    double to = ph1 ? 0.0 : c.toff2;
+    double x = s - so;
+    double q = fmax(va * va - 2.0 * ac * x, 0.0);
+    return to + 2.0 * x / (va + sqrt(q));
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float wave_sum_f(float x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Open goal angle at c = (cx, cy) against the staged opponents; lanes are
+// opponents.  Returns the same value on every lane.
+__device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, float cy, int n_op,
+                            int n_tm)
+{
+    int l = lane_id();
+    float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
+    // lanes < n_op: direction to the opponent; lanes 62/63: to the goal posts
+    float4 o = S.rob[n_tm + (l < n_op ? l : 0)];
+    float cxA = cx * P.A, cyA = cy * P.A;
+    float ox = o.x - cxA, oy = o.y - cyA;
+    float Y = l < n_op ? oy : (l == 62 ? -P.half_goal_w - cy : P.half_goal_w - cy);
+    float X = l < n_op ? ox : dxg;
+    float ang = atan2f(Y, X);
+    float lo = __shfl(ang, 62, 64);
+    float hi = __shfl(ang, 63, 64);
+    bool valid = l < n_op && o.x < P.goal_xA;
+    float rho2 = fmaf(ox, ox, oy * oy);
+    bool inside = valid && rho2 <= P.RA * P.RA;
+    if (__ballot(inside)) return 0.0f;
+    float al = asinf(fminf(P.RA * rsq(fmaxf(rho2, 1e-30f)), 1.0f));
+    float s = fmaxf(ang - al, lo);
+    float e = fminf(ang + al, hi);
+    bool has = valid && e > s;
+    // union length: each interval contributes what the intervals sorted
+    // before it (by start, then index) have not already covered
+    float M = -INFINITY;
+    for (int k = 0; k < n_op; ++k) {
+        float sk = __shfl(s, k, 64);
+        float ek = __shfl(e, k, 64);
+        int hk = __shfl((int)has, k, 64);
+        bool before = hk && (sk < s || (sk == s && k < l));
+        M = before ? fmaxf(M, ek) : M;
+    }
+    float contrib = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
+    float blocked = wave_sum_f(contrib);
+    return (hi - lo) - blocked;
+}
+
+// Evaluate candidate point (cx, cy) for every staged variant.  On return lane
+// v (< n_var) holds that variant's results.
+template <int KPL>
+__device__ void eval_point(const StageLDS &S, const DevParams &P, float cx, float cy,
+                           double cx64, double cy64, float &o_score, int &o_feas,
+                           float &o_tt, float &o_to)
+{
+    const int l = lane_id();
+    const int K = KPL * 64;
+    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
+    const int has_flat = uni(S.has_flat), has_chip = uni(S.has_chip);
+    const float bx = unif(S.bx), by = unif(S.by);
+    const float ex = cx - bx, ey = cy - by;
+    const float d = hsqrt(fmaf(ex, ex, ey * ey));
+    const float invK = 1.0f / (float)K;
+
+    float pxA[KPL], pyA[KPL], sk[KPL], Tt[KPL], To[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        float f = (float)(q * 64 + l + 1) * invK;
+        pxA[q] = fmaf(f, ex, bx) * P.A;
+        pyA[q] = fmaf(f, ey, by) * P.A;
+        sk[q] = f * d;
+        Tt[q] = INFINITY;
+        To[q] = INFINITY;
+    }
+    // 1. robot stage
+    for (int j = 0; j < n_tm; ++j) {
+        float4 r = S.rob[j];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) Tt[q] = fminf(Tt[q], robot_time_A(r, pxA[q], pyA[q], P));
+    }
+    for (int j = 0; j < n_op; ++j) {
+        float4 r = S.rob[n_tm + j];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) To[q] = fminf(To[q], robot_time_A(r, pxA[q], pyA[q], P));
+    }
+    // 2. critical kick speeds per sample
+    float vtf[KPL], vof[KPL], vtc[KPL], voc[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        float tt = Tt[q] * P.invA, to = To[q] * P.invA;
+        vtf[q] = vof[q] = vtc[q] = voc[q] = 0.0f;
+        if (has_flat) {
+            vtf[q] = vcrit(tt, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta, P.f_beta2,
+                           P.f_hfast, P.f_pfast, P.half_ar);
+            vof[q] = vcrit(to, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta, P.f_beta2,
+                           P.f_hfast, P.f_pfast, P.half_ar);
+        }
+        if (has_chip) {
+            float vair = hsqrt(sk[q] * P.lam1_inv);
+            vtc[q] = fminf(vair, vcrit(tt, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4, P.c_beta,
+                                       P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
+            voc[q] = fminf(vair, vcrit(to, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4, P.c_beta,
+                                       P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
+        }
+    }
+    // 3. first crossing per variant (ballot over samples)
+    int my_kt = K, my_ko = K;
+    for (int v = 0; v < n_var; ++v) {
+        const float v0 = unif(S.v0[v]);
+        const int chip = uni(S.type[v]) == DPPS_CHIP;
+        int kt = K, ko = K;
+#pragma unroll
+        for (int q = KPL - 1; q >= 0; --q) {
+            unsigned long long mt = __ballot(v0 <= (chip ? vtc[q] : vtf[q]));
+            unsigned long long mo = __ballot(v0 <= (chip ? voc[q] : vof[q]));
+            if (mt) kt = q * 64 + __builtin_ctzll(mt);
+            if (mo) ko = q * 64 + __builtin_ctzll(mo);
+        }
+        my_kt = l == v ? kt : my_kt;
+        my_ko = l == v ? ko : my_ko;
+    }
+    // open goal angle (lanes = opponents)
+    const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
+    // 4. finish: lanes = variants
+    o_score = -INFINITY;
+    o_feas = 0;
+    o_tt = INFINITY;
+    o_to = INFINITY;
+    if (l < n_var) {
+        const VarConst c = S.vc[l];
+        double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
+        double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
+        bool reach = d64 >= 1e-9 && d64 <= c.D && d64 >= c.sf_reach;
+        double tt = INFINITY, to = INFINITY;
+        if (reach) {
+            if (my_kt < K) tt = ball_time64(c, (double)(my_kt + 1) * P.invK_d * d64);
+            if (my_ko < K) to = ball_time64(c, (double)(my_ko + 1) * P.invK_d * d64);
+        }
+        bool tfin = tt < INFINITY;
+        double m = !tfin ? -INFINITY : (to < INFINITY ? to - tt : INFINITY);
+        bool feas = reach && tfin && m >= P.margin_d;
+        if (feas) {
+            float gx = cx - P.goal_x;
+            float dg = hsqrt(fmaf(gx, gx, cy * cy));
+            float mc = fminf(fmaxf((float)m, 0.0f), P.margin_cap);
+            o_score = fmaf(P.w_ang_pi, ang, fmaf(P.w_dist, fmaf(-dg, P.inv_dist_norm, 1.0f),
+                                                 P.w_margin * mc));
+        }
+        o_feas = feas;
+        o_tt = (float)tt;
+        o_to = (float)to;
+    }
+}
+
+__global__ void init_kernel(uint32_t *counter, unsigned long long *keys, int n_frames)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0u;
+    if (i < n_frames) keys[i] = 0ull;
+}
+
+template <int KPL>
+__global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
+{
+    __shared__ StageLDS S;
+    __shared__ OutLDS O;
+    __shared__ int s_tile;
+    const DevParams &P = a.P;
+    const int nw = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6;
+    const int l = lane_id();
+    const int TP = a.tile_points;
+    const bool reduced = (P.out_flags & DPPS_OUT_REDUCED) != 0;
+    int iter = 0;
+    int cur_frame = -1;
+    while (true) {
+        int t;
+        if (a.persistent) {
+            if (threadIdx.x == 0) s_tile = (int)atomicAdd(a.counter, 1u);
+            __syncthreads();
+            t = s_tile;
+        } else {
+            t = blockIdx.x + iter * gridDim.x;
+        }
+        ++iter;
+        if (t >= a.n_tiles) break;
+        const TileDev tile = a.tiles[t];
+        const WinDev W = a.wins[tile.win];
+        if (W.frame != cur_frame) {
+            __syncthreads();
+            stage_frame(a, W.frame, S);
+            cur_frame = W.frame;
+        }
+        __syncthreads();
+        const int n_var = S.n_var;
+        const int npts = min(TP, W.npts - tile.p0);
+        unsigned long long best = 0ull;
+        for (int slot = w; slot < npts; slot += nw) {
+            const int p = tile.p0 + slot;
+            const int j = p / W.nx, i = p - j * W.nx;
+            const float mi = (float)(W.i0 + i) - W.halfNx;
+            const float mj = (float)(W.j0 + j) - W.halfNy;
+            const float cx = W.h * mi, cy = W.h * mj;
+            const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
+            float sc, tt, to;
+            int fe;
+            eval_point<KPL>(S, P, cx, cy, cx64, cy64, sc, fe, tt, to);
+            unsigned long long key = 0ull;
+            if (fe) {
+                uint32_t lin = (uint32_t)(W.elem_base + l * W.npts + p);
+                key = ((unsigned long long)__float_as_uint(sc) << 32) |
+                      (unsigned long long)(0xFFFFFFFFu - lin);
+            }
+            best = key > best ? key : best;
+            if (reduced) {
+                unsigned long long pk = wave_max_u64(key);
+                if (l == 0) {
+                    int64_t o = W.out_base + p;
+                    if (a.score)
+                        a.score[o] = pk ? __uint_as_float((uint32_t)(pk >> 32)) : -INFINITY;
+                    if (a.mask) {
+                        uint32_t lin = 0xFFFFFFFFu - (uint32_t)pk;
+                        a.mask[o] = pk ? (uint8_t)((lin - (uint32_t)W.elem_base) / (uint32_t)W.npts)
+                                       : (uint8_t)255;
+                    }
+                }
+            } else if (l < n_var) {
+                O.score[l * MAX_TILE + slot] = sc;
+                O.mask[l * MAX_TILE + slot] = (uint8_t)fe;
+                if (a.t_team) a.t_team[W.out_base + (int64_t)l * W.npts + p] = tt;
+                if (a.t_opp) a.t_opp[W.out_base + (int64_t)l * W.npts + p] = to;
+            }
+        }
+        best = wave_max_u64(best);
+        if (l == 0 && best) atomicMax(a.keys + W.frame, best);
+        __syncthreads();
+        if (!reduced) {
+            const int tot = n_var * npts;
+            for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+                const int v = e / npts, slot = e - v * npts;
+                const int64_t o = W.out_base + (int64_t)v * W.npts + tile.p0 + slot;
+                if (a.score) a.score[o] = O.score[v * MAX_TILE + slot];
+                if (a.mask) a.mask[o] = O.mask[v * MAX_TILE + slot];
+            }
+        }
+    }
+}
+
+// One wave per frame: decode the best key and re-evaluate the chosen point for
+// its interception times.
+template <int KPL>
+__global__ void __launch_bounds__(64) finalize_kernel(LaunchArgs a)
+{
+    __shared__ StageLDS S;
+    const int f = blockIdx.x;
+    const int l = lane_id();
+    const unsigned long long key = a.keys[f];
+    dpps_best b;
+    b.found = 0; b.window = -1; b.variant = -1; b.i = -1; b.j = -1; b.type = -1;
+    b.x = b.y = b.v0 = 0.0f;
+    b.score = -INFINITY; b.t_team = INFINITY; b.t_opp = INFINITY; b.t_ball = INFINITY;
+    b.pad = 0;
+    if (key == 0ull) {
+        if (l == 0) a.best[f] = b;
+        return;
+    }
+    stage_frame(a, f, S);
+    __syncthreads();
+    const FrameDev F = a.frames[f];
+    const uint32_t lin = 0xFFFFFFFFu - (uint32_t)key;
+    int wi = 0;
+    for (int k = 0; k < F.n_windows; ++k) {
+        const WinDev &W = a.wins[F.win_off + k];
+        if ((uint32_t)W.elem_base <= lin) wi = k;
+    }
+    const WinDev W = a.wins[F.win_off + wi];
+    const uint32_t rel = lin - (uint32_t)W.elem_base;
+    const int v = (int)(rel / (uint32_t)W.npts);
+    const int p = (int)(rel - (uint32_t)v * (uint32_t)W.npts);
+    const int j = p / W.nx, i = p - j * W.nx;
+    const float mi = (float)(W.i0 + i) - W.halfNx;
+    const float mj = (float)(W.j0 + j) - W.halfNy;
+    const float cx = W.h * mi, cy = W.h * mj;
+    float sc, tt, to;
+    int fe;
+    eval_point<KPL>(S, a.P, cx, cy, (double)W.h * (double)mi, (double)W.h * (double)mj, sc, fe,
+                    tt, to);
+    if (l == v) {
+        const VarConst c = S.vc[v];
+        double ex64 = (double)W.h * (double)mi - (double)S.bx;
+        double ey64 = (double)W.h * (double)mj - (double)S.by;
+        double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
+        b.found = 1;
+        b.window = wi;
+        b.variant = v;
+        b.i = i;
+        b.j = j;
+        b.type = S.type[v];
+        b.x = cx;
+        b.y = cy;
+        b.v0 = S.v0[v];
+        b.score = __uint_as_float((uint32_t)(key >> 32));
+        b.t_team = tt;
+        b.t_opp = to;
+        b.t_ball = (float)ball_time64(c, d64);
+        a.best[f] = b;
+    }
+}
+
+template <int KPL>
+static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream_t st,
+                      hipEvent_t e0, hipEvent_t e1)
+{
+    int nb = (a.n_frames + 255) / 256;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, st, a.counter, a.keys, a.n_frames);
+    if (e0) (void)hipEventRecord(e0, st);
+    if (a.n_tiles > 0 && grid > 0)
+        hipLaunchKernelGGL(search_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg), 0, st, a);
+    if (e1) (void)hipEventRecord(e1, st);
+    if (a.n_frames > 0 && a.best)
+        hipLaunchKernelGGL(finalize_kernel<KPL>, dim3(a.n_frames), dim3(64), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
+                  void *ev_stop)
+{
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = (hipEvent_t)ev_start, e1 = (hipEvent_t)ev_stop;
+    switch (a.P.K / 64) {
+    case 1: return launch_kpl<1>(a, waves_per_wg, grid, st, e0, e1);
+    case 2: return launch_kpl<2>(a, waves_per_wg, grid, st, e0, e1);
+    case 3: return launch_kpl<3>(a, waves_per_wg, grid, st, e0, e1);
+    case 4: return launch_kpl<4>(a, waves_per_wg, grid, st, e0, e1);
+    default: return -2;
+    }
+}
+
+}  // namespace dpps
