@@ -306,30 +306,38 @@ double orc_open_angle(const orc_params *P, double cx, double cy, int n_opp, cons
 /* ------------------------------------------------------------------------ */
 /* One (point, variant): interception times, feasibility, score.            */
 /* ------------------------------------------------------------------------ */
+/* Parity bands of one side (not part of the search): at every sample up to
+ * and including the side's first interception, the side's earliest arrival
+ * (minimum over its robots) is compared with the ball; a sample whose
+ * decision lies within eps_cross_t in time, or within eps_cross_s in ball
+ * position, marks the entry ambiguous, and so does a chip sample within
+ * eps_land of the landing point that the side could reach. */
 static void side_bands(const orc_params *P, const orc_path *pa, const double *robots,
                        int n, int skip, int k_side, int *amb)
 {
     int K = P->n_samples;
     int klim = k_side < K ? k_side : K - 1;
-    for (int j = 0; j < n; ++j) {
-        if (j == skip) continue;
-        const double *rb = robots + 4 * j;
-        for (int k = 0; k <= klim; ++k) {
-            double f = (double)(k + 1) / (double)K;
-            double s = f * pa->d;
-            double px = pa->bx + f * (pa->cx - pa->bx);
-            double py = pa->by + f * (pa->cy - pa->by);
-            double tr = robot_time_to(P, rb, px, py);
-            if (pa->type == ORC_CHIP && fabs(s - pa->sf) < P->eps_land) {
-                double tb_land = s / (pa->v0 * cos(P->chip_angle));
-                if (tr <= tb_land + P->eps_cross_t) *amb |= ORC_AMB_LAND;
-            }
-            if (pa->type == ORC_CHIP && s < pa->sf) continue;
-            double tb = orc_ball_time(P, pa->type, pa->v0, s);
-            if (fabs(tr - tb) < P->eps_cross_t) *amb |= ORC_AMB_CROSS;
-            double sb = orc_ball_dist(P, pa->type, pa->v0, tr);
-            if (fabs(sb - s) < P->eps_cross_s) *amb |= ORC_AMB_CROSS;
+    for (int k = 0; k <= klim; ++k) {
+        double f = (double)(k + 1) / (double)K;
+        double s = f * pa->d;
+        double px = pa->bx + f * (pa->cx - pa->bx);
+        double py = pa->by + f * (pa->cy - pa->by);
+        double tmin = INFINITY;
+        for (int j = 0; j < n; ++j) {
+            if (j == skip) continue;
+            double tr = robot_time_to(P, robots + 4 * j, px, py);
+            if (tr < tmin) tmin = tr;
         }
+        if (!isfinite(tmin)) return;
+        if (pa->type == ORC_CHIP && fabs(s - pa->sf) < P->eps_land) {
+            double tb_land = s / (pa->v0 * cos(P->chip_angle));
+            if (tmin <= tb_land + P->eps_cross_t) *amb |= ORC_AMB_LAND;
+        }
+        if (pa->type == ORC_CHIP && s < pa->sf) continue;
+        double tb = orc_ball_time(P, pa->type, pa->v0, s);
+        if (fabs(tmin - tb) < P->eps_cross_t) *amb |= ORC_AMB_CROSS;
+        double sb = orc_ball_dist(P, pa->type, pa->v0, tmin);
+        if (fabs(sb - s) < P->eps_cross_s) *amb |= ORC_AMB_CROSS;
     }
 }
 
