@@ -182,6 +182,13 @@ int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_
  * (milliseconds, from HIP events on the launch stream); -1 if unavailable. */
 float dpps_last_kernel_ms(dpps_ctx *c);
 
+/* Kernel timing over many runs: dpps_timing_begin arms a ring of max_runs
+ * event pairs; each later non-graph run records its search kernel into the
+ * next pair (no host synchronisation); dpps_timing_end waits for them and
+ * returns the summed kernel time and the number of runs recorded. */
+int dpps_timing_begin(dpps_ctx *c, int32_t max_runs);
+int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs);
+
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);
 int dpps_version(void);

@@ -88,6 +88,8 @@ def lib():
         L.dpps_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.dpps_last_kernel_ms.argtypes = [vp]
         L.dpps_last_kernel_ms.restype = C.c_float
+        L.dpps_timing_begin.argtypes = [vp, i32]
+        L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
         L.dpps_strerror.restype = C.c_char_p
         L.dpps_last_error.argtypes = []
@@ -264,6 +266,15 @@ class Searcher:
 
     def last_kernel_ms(self) -> float:
         return float(lib().dpps_last_kernel_ms(self.h))
+
+    def timing_begin(self, max_runs: int):
+        _check(lib().dpps_timing_begin(self.h, max_runs))
+
+    def timing_end(self):
+        """(total search-kernel ms, runs recorded) since timing_begin."""
+        ms, n = C.c_float(), C.c_int32()
+        _check(lib().dpps_timing_end(self.h, C.byref(ms), C.byref(n)))
+        return float(ms.value), int(n.value)
 
 
 class Batch:

@@ -309,6 +309,9 @@ struct dpps_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     uint64_t budget_used = 0;
+    // optional ring of event pairs bracketing the search kernel of each run
+    std::vector<hipEvent_t> ring0, ring1;
+    int ring_used = 0;
 };
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -343,10 +346,19 @@ static int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes)
 
 static void graph_drop(dpps_batch *b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+static void ring_free(dpps_ctx *c)
+{
+    for (hipEvent_t e : c->ring0) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ring1) (void)hipEventDestroy(e);
+    c->ring0.clear();
+    c->ring1.clear();
+    c->ring_used = 0;
 }
 
 // Sizes of the table section of the arena.
@@ -428,9 +440,14 @@ static int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStr
     int64_t cap = (int64_t)c->n_cu * c->wg_per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (!c->persistent) grid = a.n_tiles;
-    int rc = launch_search(a, c->waves, grid, (void *)st, timed ? (void *)c->ev0 : nullptr,
-                           timed ? (void *)c->ev1 : nullptr);
-    c->timed = timed;
+    void *e0 = timed ? (void *)c->ev0 : nullptr, *e1 = timed ? (void *)c->ev1 : nullptr;
+    if (timed && c->ring_used < (int)c->ring0.size()) {
+        e0 = (void *)c->ring0[c->ring_used];
+        e1 = (void *)c->ring1[c->ring_used];
+        ++c->ring_used;
+    }
+    int rc = launch_search(a, c->waves, grid, (void *)st, e0, e1);
+    c->timed = timed && e1 == (void *)c->ev1;
     if (rc) {
         hipError_t e = hipGetLastError();
         return fail(DPPS_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -500,8 +517,8 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
 static void batch_free_device(dpps_batch *b)
 {
     graph_drop(b);
-    if (b->arena.ptr) hipFree(b->arena.ptr);
-    if (b->aux.ptr) hipFree(b->aux.ptr);
+    if (b->arena.ptr) (void)hipFree(b->arena.ptr);
+    if (b->aux.ptr) (void)hipFree(b->aux.ptr);
     if (b->ctx) b->ctx->budget_used -= b->arena.cap + b->aux.cap;
     b->arena = DeviceArena();
     b->aux = DeviceArena();
@@ -510,13 +527,14 @@ static void batch_free_device(dpps_batch *b)
 void dpps_destroy(dpps_ctx *c)
 {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    ring_free(c);
     batch_free_device(&c->scratch);
-    if (c->pinned) hipHostFree(c->pinned);
-    if (c->staged) hipEventDestroy(c->staged);
-    if (c->ev0) hipEventDestroy(c->ev0);
-    if (c->ev1) hipEventDestroy(c->ev1);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->staged) (void)hipEventDestroy(c->staged);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -695,7 +713,7 @@ int dpps_batch_run(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hi
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(st, &g);
         if (rc) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return rc;
         }
         if (e != hipSuccess) return fail(DPPS_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -713,13 +731,46 @@ int dpps_batch_run(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hi
 void dpps_batch_destroy(dpps_batch *b)
 {
     if (!b) return;
-    if (b->ctx && b->ctx->stream) hipStreamSynchronize(b->ctx->stream);
+    if (b->ctx && b->ctx->stream) (void)hipStreamSynchronize(b->ctx->stream);
     batch_free_device(b);
     delete b;
 }
 
 int64_t dpps_batch_tiles(const dpps_batch *b) { return b ? (int64_t)b->T.tiles.size() : -1; }
 int64_t dpps_batch_points(const dpps_batch *b) { return b ? b->T.points : -1; }
+
+int dpps_timing_begin(dpps_ctx *c, int32_t max_runs)
+{
+    if (!c || max_runs < 1 || max_runs > 1 << 20) return fail(DPPS_E_INVALID, "bad timing request");
+    HIP_OK(hipSetDevice(c->device));
+    ring_free(c);
+    c->ring0.resize(max_runs, nullptr);
+    c->ring1.resize(max_runs, nullptr);
+    for (int i = 0; i < max_runs; ++i) {
+        if (hipEventCreate(&c->ring0[i]) != hipSuccess || hipEventCreate(&c->ring1[i]) != hipSuccess) {
+            ring_free(c);
+            return fail(DPPS_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    return DPPS_OK;
+}
+
+int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs)
+{
+    if (!c || !total_ms || !n_runs) return fail(DPPS_E_INVALID, "NULL argument");
+    double tot = 0.0;
+    int n = c->ring_used;
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        HIP_OK(hipEventSynchronize(c->ring1[i]));
+        HIP_OK(hipEventElapsedTime(&ms, c->ring0[i], c->ring1[i]));
+        tot += ms;
+    }
+    *total_ms = (float)tot;
+    *n_runs = n;
+    ring_free(c);
+    return DPPS_OK;
+}
 
 float dpps_last_kernel_ms(dpps_ctx *c)
 {

@@ -1,0 +1,70 @@
+"""Work model of the search: pass evaluations and FP32 VALU flops.
+
+One *pass evaluation* is one (candidate point, pass variant) judged against
+every interceptor at all K path samples.
+
+Flops count the operations of the factored search as the kernel performs them,
+per lane: an FMA is 2, every other VALU operation (add, multiply, min/max,
+compare, select, square root, reciprocal) is 1.  The counts are read off the
+formulation, not measured:
+
+* robot stage, per (interceptor, sample): 26 operations of which 5 are FMAs
+  -> 31 flops (offset 2, squared distance 2, clamp 1, rsq 1, distance to reach
+  2, speed along the line 4, clamp 1, stopping distances 3, overshoot test and
+  selects 4, sqrt 1, peak speed 1, cruise 2, total 2, team minimum 1);
+* per sample, independent of speed: 7 (sample position and distance) + 2
+  (time rescale) flops;
+* critical kick speed, per (sample, side, kick type present): 27 operations of
+  which 3 are FMAs -> 30 flops; chips add 2 per sample (airborne limit) and 1
+  per side;
+* first crossing, per (variant, sample): one compare per side -> 2;
+* per (point, variant) finish: 40 flops (two ball times at the crossing,
+  margin, feasibility, score);
+* per point: 40 flops of set-up plus the open goal angle (60 + 12 per
+  opponent).
+"""
+from __future__ import annotations
+
+C_ROBOT = 31
+C_SAMPLE = 9
+C_VCRIT = 30
+C_CHIP_SAMPLE = 4
+C_CROSS = 2
+C_FINISH = 40
+C_POINT = 40
+C_ANGLE = 60
+C_ANGLE_OPP = 12
+
+
+def point_flops(n_int: int, n_opp: int, K: int, n_flat: int, n_chip: int) -> int:
+    """Flops for one candidate point: n_int interceptors (teammates other than
+    the passer plus opponents), K samples, n_flat + n_chip variants."""
+    types = (n_flat > 0) + (n_chip > 0)
+    per_sample = C_SAMPLE + 2 * C_VCRIT * types + (C_CHIP_SAMPLE if n_chip else 0)
+    V = n_flat + n_chip
+    return (n_int * K * C_ROBOT + K * per_sample + V * K * C_CROSS + V * C_FINISH
+            + C_POINT + C_ANGLE + C_ANGLE_OPP * n_opp)
+
+
+def frame_work(frame, K: int) -> tuple[int, int]:
+    """(pass evaluations, flops) of one frame."""
+    n_int = frame.n_team - 1 + frame.n_opp
+    n_flat = sum(1 for v in frame.variants if v[0] == 0)
+    n_chip = len(frame.variants) - n_flat
+    pts = frame.n_points()
+    return pts * len(frame.variants), pts * point_flops(n_int, frame.n_opp, K, n_flat, n_chip)
+
+
+def batch_work(frames, K: int) -> tuple[int, int]:
+    ev = fl = 0
+    for f in frames:
+        e, x = frame_work(f, K)
+        ev += e
+        fl += x
+    return ev, fl
+
+
+# MI355X peaks used for the roofline (256 CUs, 2.4 GHz)
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # published; assumes packed FP32 FMA every cycle
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
