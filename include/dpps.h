@@ -172,8 +172,10 @@ int64_t dpps_batch_tiles(const dpps_batch *b);
 int64_t dpps_batch_points(const dpps_batch *b);
 
 /* Launch shape: points per tile (a multiple of 8, <= 64) and waves per
- * workgroup (1, 2, 4 or 8); 0 keeps the current value.  Persistent grids use
- * `wg_per_cu` workgroups per compute unit (0: default). */
+ * workgroup (1, 2, 4 or 8); 0 keeps the current value.  wg_per_cu: 1..32
+ * persistent workgroups per compute unit, -2 persistent with as many as fit
+ * (the default), -1 one workgroup per tile (no persistence), 0 keep.
+ * dpps_get_launch reports the resolved workgroups per CU (-1: one per tile). */
 int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int32_t wg_per_cu);
 int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_wg,
                     int32_t *wg_per_cu);

@@ -208,6 +208,7 @@ int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frame
             T.variants.push_back(Vv);
         }
         int64_t elem = 0;
+        const int32_t tile_begin = (int32_t)T.tiles.size();
         for (int w = 0; w < F.n_windows; ++w) {
             const dpps_window &Wn = windows[F.window_off + w];
             int32_t Nx, Ny;
@@ -240,6 +241,8 @@ int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frame
             T.points += W.npts;
             T.wins.push_back(W);
         }
+        D.tile_begin = tile_begin;
+        D.tile_count = (int32_t)T.tiles.size() - tile_begin;
         T.frames.push_back(D);
     }
     // full (non-reduced) keys index elements as window base + v * npts + p
@@ -279,9 +282,9 @@ struct dpps_batch {
     dpps_variant *d_variants = nullptr;
     WinDev *d_wins = nullptr;
     TileDev *d_tiles = nullptr;
-    DeviceArena aux;         // counter, keys, best
+    DeviceArena aux;         // work counter, tile records, best
     uint32_t *d_counter = nullptr;
-    unsigned long long *d_keys = nullptr;
+    TileRec *d_tile_rec = nullptr;
     dpps_best *d_best = nullptr;
     // graph cache
     hipGraph_t graph = nullptr;
@@ -298,9 +301,9 @@ struct dpps_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int n_cu = 256;
-    int tile_points = 32;
+    int tile_points = 8;
     int waves = 4;
-    int wg_per_cu = 2;
+    int wg_per_cu = 0;       // 0: as many as fit (occupancy of the search kernel)
     int persistent = 1;
     dpps_batch scratch;      // used by dpps_search / dpps_search_batch
     void *pinned = nullptr;
@@ -400,13 +403,18 @@ static int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
     b->d_wins = (WinDev *)(base + L.off_wins);
     b->d_tiles = (TileDev *)(base + L.off_tiles);
     size_t n = (size_t)(b->n_frames > 0 ? b->n_frames : 1);
-    size_t aux = align_up(sizeof(uint32_t), 256) + align_up(n * 8, 256) + n * sizeof(dpps_best);
+    size_t nt = b->T.tiles.size() > 0 ? b->T.tiles.size() : 1;
+    size_t aux = 256 + align_up(nt * sizeof(TileRec), 256) + n * sizeof(dpps_best);
+    void *old = b->aux.ptr;
     rc = arena_reserve(c, b->aux, aux);
     if (rc) return rc;
     char *ab = (char *)b->aux.ptr;
     b->d_counter = (uint32_t *)ab;
-    b->d_keys = (unsigned long long *)(ab + 256);
-    b->d_best = (dpps_best *)(ab + 256 + align_up(n * 8, 256));
+    b->d_tile_rec = (TileRec *)(ab + 256);
+    b->d_best = (dpps_best *)(ab + 256 + align_up(nt * sizeof(TileRec), 256));
+    // a fresh allocation starts with the work counter at zero; afterwards the
+    // finalize kernel rearms it at the end of every launch
+    if (b->aux.ptr != old) HIP_OK(hipMemset(b->aux.ptr, 0, 256));
     return DPPS_OK;
 }
 
@@ -430,14 +438,15 @@ static int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStr
     a.tile_points = c->tile_points;
     a.persistent = c->persistent;
     a.counter = b->d_counter;
-    a.keys = b->d_keys;
+    a.tile_rec = b->d_tile_rec;
     a.mask = out->mask;
     a.score = out->score;
     bool reduced = (c->p.out_flags & DPPS_OUT_REDUCED) != 0;
     a.t_team = reduced ? nullptr : out->t_team;
     a.t_opp = reduced ? nullptr : out->t_opp;
     a.best = out->best ? out->best : b->d_best;
-    int64_t cap = (int64_t)c->n_cu * c->wg_per_cu;
+    int per_cu = c->wg_per_cu > 0 ? c->wg_per_cu : search_occupancy(c->p.n_samples, c->waves);
+    int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (!c->persistent) grid = a.n_tiles;
     void *e0 = timed ? (void *)c->ev0 : nullptr, *e1 = timed ? (void *)c->ev1 : nullptr;
@@ -575,10 +584,14 @@ int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int3
         c->waves = waves_per_wg;
     }
     if (wg_per_cu) {
-        if (wg_per_cu < 0) {
+        if (wg_per_cu == -1) {
             c->persistent = 0;
+        } else if (wg_per_cu == -2) {
+            c->persistent = 1;
+            c->wg_per_cu = 0;
         } else {
-            if (wg_per_cu > 32) return fail(DPPS_E_INVALID, "wg_per_cu must be <= 32");
+            if (wg_per_cu < 1 || wg_per_cu > 32)
+                return fail(DPPS_E_INVALID, "wg_per_cu must be -2, -1 or in [1, 32]");
             c->persistent = 1;
             c->wg_per_cu = wg_per_cu;
         }
@@ -592,7 +605,10 @@ int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_
     if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
     if (tile_points) *tile_points = c->tile_points;
     if (waves_per_wg) *waves_per_wg = c->waves;
-    if (wg_per_cu) *wg_per_cu = c->persistent ? c->wg_per_cu : -1;
+    if (wg_per_cu)
+        *wg_per_cu = !c->persistent ? -1
+                     : c->wg_per_cu > 0 ? c->wg_per_cu
+                                        : search_occupancy(c->p.n_samples, c->waves);
     return DPPS_OK;
 }
 

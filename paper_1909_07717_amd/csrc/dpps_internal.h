@@ -40,7 +40,7 @@ struct WinDev {
     int32_t frame;
     int32_t npts;           // nx * ny
     int32_t elem_base;      // frame-relative index of this window's first element
-    int64_t out_base;       // absolute output element of this window's first element
+    int64_t out_base;       // absolute output element of this window's first (reduced) element
 };
 
 // A tile: up to tile_points consecutive points of one window.
@@ -49,12 +49,19 @@ struct TileDev {
     int32_t p0;
 };
 
+// Best pass found by one tile: packed key (score bits << 32 | ~element), and
+// the interception times of that pass.
+struct TileRec {
+    unsigned long long key;
+    float t_team, t_opp;
+};
+
 // Device-side copy of a frame (the public struct plus derived indices).
 struct FrameDev {
     int32_t n_team, n_opp, passer, robot_off;
     int32_t n_windows, win_off, n_variants, variant_off;
     float ball_x, ball_y;
-    int32_t pad0, pad1;
+    int32_t tile_begin, tile_count;
 };
 
 struct LaunchArgs {
@@ -68,8 +75,8 @@ struct LaunchArgs {
     int32_t n_frames;
     int32_t tile_points;
     int32_t persistent;
-    uint32_t *counter;
-    unsigned long long *keys;
+    uint32_t *counter;      // persistent work counter; the finalize kernel resets it
+    TileRec *tile_rec;      // one per tile
     uint8_t *mask;
     float *score;
     float *t_team;
@@ -81,5 +88,7 @@ struct LaunchArgs {
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the search kernel only.
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                   void *ev_stop);
+// Resident workgroups per CU of the search kernel for this K and block size.
+int search_occupancy(int K, int waves_per_wg);
 
 }  // namespace dpps

@@ -2,8 +2,9 @@
 //
 // Work decomposition
 //   One workgroup per tile of candidate points (persistent workgroups pull
-//   tiles from an atomic counter).  A wave evaluates one candidate point at a
-//   time with its 64 lanes spread over the K path samples (K/64 per lane):
+//   tiles from an atomic counter, or one workgroup per tile).  A wave
+//   evaluates one candidate point at a time with its 64 lanes spread over the
+//   K path samples (K/64 per lane):
 //
 //   1. robot stage   for every interceptor and every sample, the robot's
 //                    arrival time (straight line, bounded acceleration and
@@ -20,9 +21,9 @@
 //                    (SBIP, Sec. 4.2).
 //   4. finish        lanes become variants: ball time at the crossing sample
 //                    (float64), margin, feasibility and the Eq. (3) score
-//                    (Sec. 4.3); results are staged in LDS and written as full
-//                    rows per tile, and the packed (score, index) key of the
-//                    best pass is reduced per wave and merged with atomicMax.
+//                    (Sec. 4.3); results are staged in LDS and written as whole
+//                    rows per tile.  Each tile records its best pass; a small
+//                    finalize kernel reduces the records of each frame.
 //
 // The open goal angle (Sec. 4.3/4.4) is computed with lanes = opponents.
 #include <hip/hip_runtime.h>
@@ -36,6 +37,7 @@ namespace dpps {
 #define MAX_ROB (2 * DPPS_MAX_SIDE)
 #define MAX_VAR DPPS_MAX_VARIANTS
 #define MAX_TILE 64
+#define MAX_WAVES 8
 
 struct VarConst {
     double va1, a1, va2, a2, soff2, toff2, split, D, sf_reach;
@@ -53,6 +55,7 @@ struct StageLDS {
 struct OutLDS {
     float score[MAX_VAR * MAX_TILE];
     uint8_t mask[MAX_VAR * MAX_TILE];
+    TileRec wbest[MAX_WAVES];
 };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -67,6 +70,40 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ float unif(float x)
 {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ float readlane_f(float x, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ int readlane_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
+// Ball constants of one variant (float64): phase split, speeds and
+// decelerations, offsets, stopping distance D and the minimum reachable
+// distance (the carry of a chip).
+__device__ VarConst var_const(const DevParams &P, int type, float v0f)
+{
+    VarConst c;
+    double v0 = (double)v0f;
+    if (type == DPPS_CHIP) {
+        double vh = v0 * P.cos_d, vz = v0 * P.sin_d;
+        double tf = 2.0 * vz / P.g_d;
+        double sf = vh * tf;
+        c.va1 = vh; c.a1 = P.a_r_d;             // unused: split < 0
+        c.va2 = vh; c.a2 = P.a_r_d; c.soff2 = sf; c.toff2 = tf;
+        c.split = -1.0;
+        c.D = sf + vh * vh / (2.0 * P.a_r_d);
+        c.sf_reach = sf;
+    } else {
+        double v1 = P.ratio_d * v0;
+        double t1 = (v0 - v1) / P.a_s_d;
+        double d1 = (v0 * v0 - v1 * v1) / (2.0 * P.a_s_d);
+        c.va1 = v0; c.a1 = P.a_s_d;
+        c.va2 = v1; c.a2 = P.a_r_d; c.soff2 = d1; c.toff2 = t1;
+        c.split = d1;
+        c.D = d1 + v1 * v1 / (2.0 * P.a_r_d);
+        c.sf_reach = 0.0;
+    }
+    return c;
 }
 
 // Stage the frame into LDS: interceptors (passer dropped), scaled by amax so
@@ -93,28 +130,7 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
         dpps_variant v = a.variants[F.variant_off + tid];
         S.v0[tid] = v.v0;
         S.type[tid] = v.type;
-        double v0 = (double)v.v0;
-        VarConst c;
-        if (v.type == DPPS_CHIP) {
-            double vh = v0 * P.cos_d, vz = v0 * P.sin_d;
-            double tf = 2.0 * vz / P.g_d;
-            double sf = vh * tf;
-            c.va1 = vh; c.a1 = P.a_r_d;             // never used: split < 0
-            c.va2 = vh; c.a2 = P.a_r_d; c.soff2 = sf; c.toff2 = tf;
-            c.split = -1.0;
-            c.D = sf + vh * vh / (2.0 * P.a_r_d);
-            c.sf_reach = sf;
-        } else {
-            double v1 = P.ratio_d * v0;
-            double t1 = (v0 - v1) / P.a_s_d;
-            double d1 = (v0 * v0 - v1 * v1) / (2.0 * P.a_s_d);
-            c.va1 = v0; c.a1 = P.a_s_d;
-            c.va2 = v1; c.a2 = P.a_r_d; c.soff2 = d1; c.toff2 = t1;
-            c.split = d1;
-            c.D = d1 + v1 * v1 / (2.0 * P.a_r_d);
-            c.sf_reach = 0.0;
-        }
-        S.vc[tid] = c;
+        S.vc[tid] = var_const(P, v.type, v.v0);
     }
     if (tid == 0) {
         S.n_tm = F.n_team - 1;
@@ -146,8 +162,9 @@ __device__ __forceinline__ float robot_time_A(float4 r, float pxA, float pyA, co
 {
     float dx = pxA - r.x;
     float dy = pyA - r.y;
-    float r2 = fmaf(dx, dx, dy * dy);
-    r2 = fmaxf(r2, 1e-30f);
+    // the tiny bias keeps rsq finite on the robot's own position; it is below
+    // the resolution of any non-zero squared distance
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
     float inv = rsq(r2);
     float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
     float wd = fmaf(r.z, dx, r.w * dy);
@@ -206,13 +223,6 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
     return x;
 }
 
-__device__ __forceinline__ float wave_sum_f(float x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
 // Open goal angle at c = (cx, cy) against the staged opponents; lanes are
 // opponents.  Returns the same value on every lane.
 __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, float cy, int n_op,
@@ -222,13 +232,12 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
     float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
     // lanes < n_op: direction to the opponent; lanes 62/63: to the goal posts
     float4 o = S.rob[n_tm + (l < n_op ? l : 0)];
-    float cxA = cx * P.A, cyA = cy * P.A;
-    float ox = o.x - cxA, oy = o.y - cyA;
+    float ox = o.x - cx * P.A, oy = o.y - cy * P.A;
     float Y = l < n_op ? oy : (l == 62 ? -P.half_goal_w - cy : P.half_goal_w - cy);
     float X = l < n_op ? ox : dxg;
     float ang = atan2f(Y, X);
-    float lo = __shfl(ang, 62, 64);
-    float hi = __shfl(ang, 63, 64);
+    float lo = readlane_f(ang, 62);
+    float hi = readlane_f(ang, 63);
     bool valid = l < n_op && o.x < P.goal_xA;
     float rho2 = fmaf(ox, ox, oy * oy);
     bool inside = valid && rho2 <= P.RA * P.RA;
@@ -239,34 +248,38 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
     bool has = valid && e > s;
     // union length: each interval contributes what the intervals sorted
     // before it (by start, then index) have not already covered
+    const unsigned long long hm = __ballot(has);
     float M = -INFINITY;
-    for (int k = 0; k < n_op; ++k) {
-        float sk = __shfl(s, k, 64);
-        float ek = __shfl(e, k, 64);
-        int hk = __shfl((int)has, k, 64);
-        bool before = hk && (sk < s || (sk == s && k < l));
+    for (unsigned long long m = hm; m; m &= m - 1) {
+        int k = __builtin_ctzll(m);
+        float sk = readlane_f(s, k);
+        float ek = readlane_f(e, k);
+        bool before = sk < s || (sk == s && k < l);
         M = before ? fmaxf(M, ek) : M;
     }
     float contrib = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
-    float blocked = wave_sum_f(contrib);
+    float blocked = 0.0f;
+    for (unsigned long long m = hm; m; m &= m - 1) blocked += readlane_f(contrib, __builtin_ctzll(m));
     return (hi - lo) - blocked;
 }
 
-// Evaluate candidate point (cx, cy) for every staged variant.  On return lane
-// v (< n_var) holds that variant's results.
+// Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
+// hold lane v's variant (lanes >= n_var: type -1).  On return lane v
+// (< n_var) holds that variant's results.
 template <int KPL>
-__device__ void eval_point(const StageLDS &S, const DevParams &P, float cx, float cy,
-                           double cx64, double cy64, float &o_score, int &o_feas,
-                           float &o_tt, float &o_to)
+__device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, int mytype,
+                           float cx, float cy, double cx64, double cy64, float &o_score,
+                           int &o_feas, float &o_tt, float &o_to)
 {
     const int l = lane_id();
     const int K = KPL * 64;
     const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
-    const int has_flat = uni(S.has_flat), has_chip = uni(S.has_chip);
     const float bx = unif(S.bx), by = unif(S.by);
     const float ex = cx - bx, ey = cy - by;
     const float d = hsqrt(fmaf(ex, ex, ey * ey));
     const float invK = 1.0f / (float)K;
+    const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
+    const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
 
     float pxA[KPL], pyA[KPL], sk[KPL], Tt[KPL], To[KPL];
 #pragma unroll
@@ -289,41 +302,57 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float cx, floa
 #pragma unroll
         for (int q = 0; q < KPL; ++q) To[q] = fminf(To[q], robot_time_A(r, pxA[q], pyA[q], P));
     }
-    // 2. critical kick speeds per sample
-    float vtf[KPL], vof[KPL], vtc[KPL], voc[KPL];
+    // 2-3. critical kick speeds per sample, then the first crossing per
+    // variant by ballot; the crossing of variant v lands on lane v
+    int my_kt = K, my_ko = K;
+    if (flat_m) {
+        float vt[KPL], vo[KPL];
 #pragma unroll
-    for (int q = 0; q < KPL; ++q) {
-        float tt = Tt[q] * P.invA, to = To[q] * P.invA;
-        vtf[q] = vof[q] = vtc[q] = voc[q] = 0.0f;
-        if (has_flat) {
-            vtf[q] = vcrit(tt, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta, P.f_beta2,
-                           P.f_hfast, P.f_pfast, P.half_ar);
-            vof[q] = vcrit(to, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta, P.f_beta2,
-                           P.f_hfast, P.f_pfast, P.half_ar);
+        for (int q = 0; q < KPL; ++q) {
+            vt[q] = vcrit(Tt[q] * P.invA, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
+                          P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
+            vo[q] = vcrit(To[q] * P.invA, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
+                          P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
         }
-        if (has_chip) {
-            float vair = hsqrt(sk[q] * P.lam1_inv);
-            vtc[q] = fminf(vair, vcrit(tt, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4, P.c_beta,
-                                       P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
-            voc[q] = fminf(vair, vcrit(to, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4, P.c_beta,
-                                       P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
+        for (unsigned long long m = flat_m; m; m &= m - 1) {
+            const int v = __builtin_ctzll(m);
+            const float v0 = readlane_f(myv0, v);
+            int kt = K, ko = K;
+#pragma unroll
+            for (int q = KPL - 1; q >= 0; --q) {
+                unsigned long long mt = __ballot(v0 <= vt[q]);
+                unsigned long long mo = __ballot(v0 <= vo[q]);
+                if (mt) kt = q * 64 + __builtin_ctzll(mt);
+                if (mo) ko = q * 64 + __builtin_ctzll(mo);
+            }
+            my_kt = l == v ? kt : my_kt;
+            my_ko = l == v ? ko : my_ko;
         }
     }
-    // 3. first crossing per variant (ballot over samples)
-    int my_kt = K, my_ko = K;
-    for (int v = 0; v < n_var; ++v) {
-        const float v0 = unif(S.v0[v]);
-        const int chip = uni(S.type[v]) == DPPS_CHIP;
-        int kt = K, ko = K;
+    if (chip_m) {
+        float vt[KPL], vo[KPL];
 #pragma unroll
-        for (int q = KPL - 1; q >= 0; --q) {
-            unsigned long long mt = __ballot(v0 <= (chip ? vtc[q] : vtf[q]));
-            unsigned long long mo = __ballot(v0 <= (chip ? voc[q] : vof[q]));
-            if (mt) kt = q * 64 + __builtin_ctzll(mt);
-            if (mo) ko = q * 64 + __builtin_ctzll(mo);
+        for (int q = 0; q < KPL; ++q) {
+            float vair = hsqrt(sk[q] * P.lam1_inv);
+            vt[q] = fminf(vair, vcrit(Tt[q] * P.invA, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
+                                      P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
+            vo[q] = fminf(vair, vcrit(To[q] * P.invA, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
+                                      P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
         }
-        my_kt = l == v ? kt : my_kt;
-        my_ko = l == v ? ko : my_ko;
+        for (unsigned long long m = chip_m; m; m &= m - 1) {
+            const int v = __builtin_ctzll(m);
+            const float v0 = readlane_f(myv0, v);
+            int kt = K, ko = K;
+#pragma unroll
+            for (int q = KPL - 1; q >= 0; --q) {
+                unsigned long long mt = __ballot(v0 <= vt[q]);
+                unsigned long long mo = __ballot(v0 <= vo[q]);
+                if (mt) kt = q * 64 + __builtin_ctzll(mt);
+                if (mo) ko = q * 64 + __builtin_ctzll(mo);
+            }
+            my_kt = l == v ? kt : my_kt;
+            my_ko = l == v ? ko : my_ko;
+        }
     }
     // open goal angle (lanes = opponents)
     const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
@@ -358,15 +387,9 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float cx, floa
     }
 }
 
-__global__ void init_kernel(uint32_t *counter, unsigned long long *keys, int n_frames)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *counter = 0u;
-    if (i < n_frames) keys[i] = 0ull;
-}
-
+// At most 128 VGPRs, so four waves fit on each SIMD.
 template <int KPL>
-__global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
+__global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
     __shared__ OutLDS O;
@@ -379,6 +402,8 @@ __global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
     const bool reduced = (P.out_flags & DPPS_OUT_REDUCED) != 0;
     int iter = 0;
     int cur_frame = -1;
+    float myv0 = 0.0f;
+    int mytype = -1;
     while (true) {
         int t;
         if (a.persistent) {
@@ -395,12 +420,18 @@ __global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
         if (W.frame != cur_frame) {
             __syncthreads();
             stage_frame(a, W.frame, S);
+            __syncthreads();
             cur_frame = W.frame;
+            const int nv = S.n_var;
+            myv0 = l < nv ? S.v0[l] : 0.0f;
+            mytype = l < nv ? S.type[l] : -1;
+        } else {
+            __syncthreads();
         }
-        __syncthreads();
         const int n_var = S.n_var;
         const int npts = min(TP, W.npts - tile.p0);
-        unsigned long long best = 0ull;
+        unsigned long long bkey = 0ull;
+        float btt = INFINITY, bto = INFINITY;
         for (int slot = w; slot < npts; slot += nw) {
             const int p = tile.p0 + slot;
             const int j = p / W.nx, i = p - j * W.nx;
@@ -410,14 +441,18 @@ __global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
             float sc, tt, to;
             int fe;
-            eval_point<KPL>(S, P, cx, cy, cx64, cy64, sc, fe, tt, to);
+            eval_point<KPL>(S, P, myv0, mytype, cx, cy, cx64, cy64, sc, fe, tt, to);
             unsigned long long key = 0ull;
             if (fe) {
                 uint32_t lin = (uint32_t)(W.elem_base + l * W.npts + p);
                 key = ((unsigned long long)__float_as_uint(sc) << 32) |
                       (unsigned long long)(0xFFFFFFFFu - lin);
             }
-            best = key > best ? key : best;
+            if (key > bkey) {
+                bkey = key;
+                btt = tt;
+                bto = to;
+            }
             if (reduced) {
                 unsigned long long pk = wave_max_u64(key);
                 if (l == 0) {
@@ -437,9 +472,27 @@ __global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
                 if (a.t_opp) a.t_opp[W.out_base + (int64_t)l * W.npts + p] = to;
             }
         }
-        best = wave_max_u64(best);
-        if (l == 0 && best) atomicMax(a.keys + W.frame, best);
+        // the wave's best pass (and its times), then the tile's
+        const unsigned long long wk = wave_max_u64(bkey);
+        const unsigned long long who = __ballot(bkey == wk);
+        const int src = who ? __builtin_ctzll(who) : 0;
+        const float wtt = readlane_f(btt, src), wto = readlane_f(bto, src);
+        if (l == 0) {
+            O.wbest[w].key = wk;
+            O.wbest[w].t_team = wtt;
+            O.wbest[w].t_opp = wto;
+        }
         __syncthreads();
+        if (threadIdx.x == 0) {
+            TileRec r = O.wbest[0];
+            for (int k = 1; k < nw; ++k)
+                if (O.wbest[k].key > r.key) r = O.wbest[k];
+            if (r.key == 0ull) {
+                r.t_team = INFINITY;
+                r.t_opp = INFINITY;
+            }
+            a.tile_rec[t] = r;
+        }
         if (!reduced) {
             const int tot = n_var * npts;
             for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -452,80 +505,79 @@ __global__ void __launch_bounds__(512) search_kernel(LaunchArgs a)
     }
 }
 
-// One wave per frame: decode the best key and re-evaluate the chosen point for
-// its interception times.
-template <int KPL>
-__global__ void __launch_bounds__(64) finalize_kernel(LaunchArgs a)
+// One workgroup per frame: reduce the frame's tile records to its best pass;
+// block 0 also rearms the persistent work counter for the next launch.
+__global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
 {
-    __shared__ StageLDS S;
+    __shared__ TileRec red[256];
     const int f = blockIdx.x;
-    const int l = lane_id();
-    const unsigned long long key = a.keys[f];
+    const int tid = threadIdx.x;
+    if (f == 0 && tid == 0 && a.counter) *a.counter = 0u;
+    const FrameDev F = a.frames[f];
+    TileRec r;
+    r.key = 0ull;
+    r.t_team = INFINITY;
+    r.t_opp = INFINITY;
+    for (int k = tid; k < F.tile_count; k += blockDim.x) {
+        const TileRec x = a.tile_rec[F.tile_begin + k];
+        if (x.key > r.key) r = x;
+    }
+    red[tid] = r;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s && red[tid + s].key > red[tid].key) red[tid] = red[tid + s];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const TileRec bestr = red[0];
     dpps_best b;
     b.found = 0; b.window = -1; b.variant = -1; b.i = -1; b.j = -1; b.type = -1;
     b.x = b.y = b.v0 = 0.0f;
     b.score = -INFINITY; b.t_team = INFINITY; b.t_opp = INFINITY; b.t_ball = INFINITY;
     b.pad = 0;
-    if (key == 0ull) {
-        if (l == 0) a.best[f] = b;
-        return;
-    }
-    stage_frame(a, f, S);
-    __syncthreads();
-    const FrameDev F = a.frames[f];
-    const uint32_t lin = 0xFFFFFFFFu - (uint32_t)key;
-    int wi = 0;
-    for (int k = 0; k < F.n_windows; ++k) {
-        const WinDev &W = a.wins[F.win_off + k];
-        if ((uint32_t)W.elem_base <= lin) wi = k;
-    }
-    const WinDev W = a.wins[F.win_off + wi];
-    const uint32_t rel = lin - (uint32_t)W.elem_base;
-    const int v = (int)(rel / (uint32_t)W.npts);
-    const int p = (int)(rel - (uint32_t)v * (uint32_t)W.npts);
-    const int j = p / W.nx, i = p - j * W.nx;
-    const float mi = (float)(W.i0 + i) - W.halfNx;
-    const float mj = (float)(W.j0 + j) - W.halfNy;
-    const float cx = W.h * mi, cy = W.h * mj;
-    float sc, tt, to;
-    int fe;
-    eval_point<KPL>(S, a.P, cx, cy, (double)W.h * (double)mi, (double)W.h * (double)mj, sc, fe,
-                    tt, to);
-    if (l == v) {
-        const VarConst c = S.vc[v];
-        double ex64 = (double)W.h * (double)mi - (double)S.bx;
-        double ey64 = (double)W.h * (double)mj - (double)S.by;
-        double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
+    if (bestr.key != 0ull) {
+        const uint32_t lin = 0xFFFFFFFFu - (uint32_t)bestr.key;
+        int wi = 0;
+        for (int k = 0; k < F.n_windows; ++k)
+            if ((uint32_t)a.wins[F.win_off + k].elem_base <= lin) wi = k;
+        const WinDev W = a.wins[F.win_off + wi];
+        const uint32_t rel = lin - (uint32_t)W.elem_base;
+        const int v = (int)(rel / (uint32_t)W.npts);
+        const int p = (int)(rel - (uint32_t)v * (uint32_t)W.npts);
+        const int j = p / W.nx, i = p - j * W.nx;
+        const float mi = (float)(W.i0 + i) - W.halfNx;
+        const float mj = (float)(W.j0 + j) - W.halfNy;
+        const dpps_variant var = a.variants[F.variant_off + v];
+        const VarConst c = var_const(a.P, var.type, var.v0);
+        double ex64 = (double)W.h * (double)mi - (double)F.ball_x;
+        double ey64 = (double)W.h * (double)mj - (double)F.ball_y;
         b.found = 1;
         b.window = wi;
         b.variant = v;
         b.i = i;
         b.j = j;
-        b.type = S.type[v];
-        b.x = cx;
-        b.y = cy;
-        b.v0 = S.v0[v];
-        b.score = __uint_as_float((uint32_t)(key >> 32));
-        b.t_team = tt;
-        b.t_opp = to;
-        b.t_ball = (float)ball_time64(c, d64);
-        a.best[f] = b;
+        b.type = var.type;
+        b.x = W.h * mi;
+        b.y = W.h * mj;
+        b.v0 = var.v0;
+        b.score = __uint_as_float((uint32_t)(bestr.key >> 32));
+        b.t_team = bestr.t_team;
+        b.t_opp = bestr.t_opp;
+        b.t_ball = (float)ball_time64(c, sqrt(ex64 * ex64 + ey64 * ey64));
     }
+    a.best[f] = b;
 }
 
 template <int KPL>
 static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream_t st,
                       hipEvent_t e0, hipEvent_t e1)
 {
-    int nb = (a.n_frames + 255) / 256;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, st, a.counter, a.keys, a.n_frames);
     if (e0) (void)hipEventRecord(e0, st);
     if (a.n_tiles > 0 && grid > 0)
         hipLaunchKernelGGL(search_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg), 0, st, a);
     if (e1) (void)hipEventRecord(e1, st);
-    if (a.n_frames > 0 && a.best)
-        hipLaunchKernelGGL(finalize_kernel<KPL>, dim3(a.n_frames), dim3(64), 0, st, a);
+    if (a.n_frames > 0)
+        hipLaunchKernelGGL(finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -541,6 +593,21 @@ int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream,
     case 4: return launch_kpl<4>(a, waves_per_wg, grid, st, e0, e1);
     default: return -2;
     }
+}
+
+int search_occupancy(int K, int waves_per_wg)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const int bs = 64 * waves_per_wg;
+    switch (K / 64) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1>, bs, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2>, bs, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3>, bs, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4>, bs, 0); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 }  // namespace dpps
