@@ -180,6 +180,17 @@ int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int3
 int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_wg,
                     int32_t *wg_per_cu);
 
+/* Autotuner: time every launch shape (tile points 8/16/32/64 x waves 1/2/4/8
+ * x persistent / one workgroup per tile) on batch b with `reps` timed runs
+ * each, keep the fastest on the context and re-tile b for it.  With
+ * cache_path, a previous result for the same class (architecture, K, largest
+ * variant and interceptor counts, log2 points per frame, log2 frames, output
+ * mode) is reused without timing, and a new result is appended as one JSON
+ * line.  *best_ms (may be NULL) receives the winner's average search-kernel
+ * time, or -1 when taken from the cache.  Synchronous; overwrites *out. */
+int dpps_autotune(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip_stream,
+                  const char *cache_path, int32_t reps, float *best_ms);
+
 /* Device timing of the last dpps_batch_run / dpps_search_batch main kernel
  * (milliseconds, from HIP events on the launch stream); -1 if unavailable. */
 float dpps_last_kernel_ms(dpps_ctx *c);

@@ -88,6 +88,8 @@ def lib():
         L.dpps_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.dpps_last_kernel_ms.argtypes = [vp]
         L.dpps_last_kernel_ms.restype = C.c_float
+        L.dpps_autotune.argtypes = [vp, vp, C.POINTER(Outputs_C), vp, C.c_char_p, i32,
+                                    C.POINTER(C.c_float)]
         L.dpps_timing_begin.argtypes = [vp, i32]
         L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
@@ -300,6 +302,17 @@ class Batch:
         self._oc = out.c()
         _check(lib().dpps_batch_run(self.s.h, self.h, C.byref(self._oc), _stream_ptr(stream),
                                     int(graph)))
+
+    def autotune(self, out: DeviceOutputs, cache_path: str | None = None, reps: int = 3,
+                 stream=None) -> float:
+        """Pick the fastest launch shape for this batch (see dpps_autotune);
+        returns its average kernel ms, or -1 when it came from the cache."""
+        oc = out.c()
+        ms = C.c_float()
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().dpps_autotune(self.s.h, self.h, C.byref(oc), _stream_ptr(stream), cp, reps,
+                                   C.byref(ms)))
+        return float(ms.value)
 
     def set_robots(self, robots: np.ndarray, stream=None):
         r = np.ascontiguousarray(robots, ROBOT_DT)

@@ -418,6 +418,36 @@ static int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
     return DPPS_OK;
 }
 
+// Regenerate the tile list for b->tile_points (frames and windows unchanged).
+static void retile(HostTables &T, int tile_points)
+{
+    T.tiles.clear();
+    for (FrameDev &F : T.frames) {
+        F.tile_begin = (int32_t)T.tiles.size();
+        for (int w = 0; w < F.n_windows; ++w) {
+            const int32_t widx = F.win_off + w;
+            for (int32_t p0 = 0; p0 < T.wins[widx].npts; p0 += tile_points)
+                T.tiles.push_back({widx, p0});
+        }
+        F.tile_count = (int32_t)T.tiles.size() - F.tile_begin;
+    }
+}
+
+// Synchronous upload of a batch's tables (after creation or a new tile size).
+static int batch_upload(dpps_ctx *c, dpps_batch *b)
+{
+    graph_drop(b);
+    retile(b->T, b->tile_points);
+    Layout L = table_layout(b->T);
+    int rc = batch_reserve(c, b, L);
+    if (rc) return rc;
+    std::vector<char> host(L.total);
+    pack_tables(b->T, L, host.data());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    HIP_OK(hipMemcpy(b->arena.ptr, host.data(), L.total, hipMemcpyHostToDevice));
+    return DPPS_OK;
+}
+
 static int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st,
                      bool timed)
 {
@@ -679,19 +709,131 @@ int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     }
     b->n_frames = n_frames;
     b->tile_points = c->tile_points;
-    Layout L = table_layout(b->T);
-    rc = batch_reserve(c, b, L);
+    rc = batch_upload(c, b);
     if (rc) {
         dpps_batch_destroy(b);
         return rc;
     }
-    std::vector<char> host(L.total);
-    pack_tables(b->T, L, host.data());
-    if (hipMemcpy(b->arena.ptr, host.data(), L.total, hipMemcpyHostToDevice) != hipSuccess) {
-        dpps_batch_destroy(b);
-        return fail(DPPS_E_DEVICE, "batch upload failed");
-    }
     *outb = b;
+    return DPPS_OK;
+}
+
+// ----------------------------------------------------------------------------
+// autotuner: launch shapes timed on the caller's batch, cached per class
+// ----------------------------------------------------------------------------
+
+static std::string tune_key(const dpps_ctx *c, const dpps_batch *b)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    size_t sp = arch.find(':');
+    if (sp != std::string::npos) arch = arch.substr(0, sp);
+    int vmax = 0, rmax = 0;
+    for (const FrameDev &F : b->T.frames) {
+        if (F.n_variants > vmax) vmax = F.n_variants;
+        if (F.n_team - 1 + F.n_opp > rmax) rmax = F.n_team - 1 + F.n_opp;
+    }
+    int64_t pts = b->T.points;
+    int nf = b->n_frames > 0 ? b->n_frames : 1;
+    int lp = 0, lf = 0;
+    for (int64_t x = pts / nf; x > 1; x >>= 1) ++lp;
+    for (int x = nf; x > 1; x >>= 1) ++lf;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s|K%d|V%d|R%d|P2^%d|F2^%d|%s", arch.c_str(), c->p.n_samples, vmax,
+             rmax, lp, lf, (c->p.out_flags & DPPS_OUT_REDUCED) ? "reduced" : "full");
+    return buf;
+}
+
+static bool tune_lookup(const char *path, const std::string &key, int *tp, int *wv, int *pc)
+{
+    FILE *fp = path ? fopen(path, "r") : nullptr;
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    std::string want = "{\"key\": \"" + key + "\",";
+    while (fgets(line, sizeof line, fp)) {
+        if (strncmp(line, want.c_str(), want.size()) != 0) continue;
+        int a, w, p;
+        const char *q = strstr(line, "\"tile_points\":");
+        if (q && sscanf(q, "\"tile_points\": %d, \"waves\": %d, \"wg_per_cu\": %d", &a, &w, &p) == 3) {
+            *tp = a;
+            *wv = w;
+            *pc = p;
+            found = true;  // the last entry for a key wins
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+int dpps_autotune(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip_stream,
+                  const char *cache_path, int32_t reps, float *best_ms)
+{
+    if (!c || !b || !out) return fail(DPPS_E_INVALID, "NULL argument");
+    if (reps < 1 || reps > 100) return fail(DPPS_E_INVALID, "reps must be in [1, 100]");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    const std::string key = tune_key(c, b);
+    int tp = 0, wv = 0, pc = 0;
+    if (tune_lookup(cache_path, key, &tp, &wv, &pc)) {
+        int rc = dpps_set_launch(c, tp, wv, pc);
+        if (rc) return rc;
+        if (b->tile_points != c->tile_points) {
+            b->tile_points = c->tile_points;
+            rc = batch_upload(c, b);
+            if (rc) return rc;
+        }
+        if (best_ms) *best_ms = -1.0f;
+        return DPPS_OK;
+    }
+    const int tps[] = {8, 16, 32, 64};
+    const int wvs[] = {1, 2, 4, 8};
+    const int pcs[] = {-2, -1};
+    float best = 1e30f;
+    int btp = c->tile_points, bwv = c->waves, bpc = c->persistent ? (c->wg_per_cu ? c->wg_per_cu : -2) : -1;
+    for (int t : tps) {
+        c->tile_points = t;
+        b->tile_points = t;
+        int rc = batch_upload(c, b);
+        if (rc) return rc;
+        for (int w : wvs) {
+            for (int pch : pcs) {
+                rc = dpps_set_launch(c, t, w, pch);
+                if (rc) return rc;
+                rc = run_batch(c, b, out, st, true);  // warm-up
+                if (rc) return rc;
+                float tot = 0.0f;
+                for (int r = 0; r < reps; ++r) {
+                    rc = run_batch(c, b, out, st, true);
+                    if (rc) return rc;
+                    float ms = dpps_last_kernel_ms(c);
+                    if (ms < 0.0f) return fail(DPPS_E_DEVICE, "kernel timing failed");
+                    tot += ms;
+                }
+                float avg = tot / (float)reps;
+                if (avg < best) {
+                    best = avg;
+                    btp = t;
+                    bwv = w;
+                    bpc = pch;
+                }
+            }
+        }
+    }
+    int rc = dpps_set_launch(c, btp, bwv, bpc);
+    if (rc) return rc;
+    b->tile_points = btp;
+    rc = batch_upload(c, b);
+    if (rc) return rc;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        FILE *fp = fopen(cache_path, "a");
+        if (!fp) return fail(DPPS_E_INVALID, "cannot write %s", cache_path);
+        fprintf(fp, "{\"key\": \"%s\", \"tile_points\": %d, \"waves\": %d, \"wg_per_cu\": %d, "
+                    "\"kernel_ms\": %.5f}\n", key.c_str(), btp, bwv, bpc, (double)best);
+        fclose(fp);
+    }
     return DPPS_OK;
 }
 
@@ -718,6 +860,13 @@ int dpps_batch_run(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hi
     if (!c || !b || !out) return fail(DPPS_E_INVALID, "NULL argument");
     HIP_OK(hipSetDevice(c->device));
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (b->tile_points != c->tile_points) {
+        // the context's tile size changed since the batch was built
+        HIP_OK(hipStreamSynchronize(st));
+        b->tile_points = c->tile_points;
+        int rc = batch_upload(c, b);
+        if (rc) return rc;
+    }
     if (!use_graph) return run_batch(c, b, out, st, true);
     int cfg[3] = {c->tile_points, c->waves, c->persistent ? c->wg_per_cu : -1};
     bool same = b->exec && memcmp(&b->graph_out, out, sizeof *out) == 0 &&
