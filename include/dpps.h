@@ -129,7 +129,9 @@ typedef struct dpps_best_s {
 } dpps_best;
 
 /* Create a context on HIP device `device` that launches on `hip_stream`
- * (NULL: the context creates its own stream).  Validates and copies *p. */
+ * (NULL: the context creates its own blocking stream, ordered with the
+ * legacy default stream).  Every entry point that takes a stream uses the
+ * context's stream when given NULL.  Validates and copies *p. */
 int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stream);
 
 /* Wait for the context's work and free what it owns (never caller buffers). */
@@ -201,6 +203,66 @@ float dpps_last_kernel_ms(dpps_ctx *c);
  * returns the summed kernel time and the number of runs recorded. */
 int dpps_timing_begin(dpps_ctx *c, int32_t max_runs);
 int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs);
+
+/* ---- learned surrogate ---------------------------------------------------
+ * A multilayer perceptron 66 -> 512 -> 512 -> 512 -> 2806 (GELU) predicts a
+ * frame's exact score map on the 20 cm lattice of the 12 m x 9 m field
+ * (61 x 46 cells, infeasible cells as 0) from its robots and ball: team with
+ * the passer first and the rest by distance to the ball, 8 slots; opponents
+ * by distance to the ball, 8 slots; each (x / 6, y / 4.5, vx / vmax,
+ * vy / vmax), missing slots zero; then the ball (x / 6, y / 4.5).  Weights
+ * and activations are bfloat16 with float32 accumulation on the matrix cores;
+ * master weights, biases, gradients and Adam moments are float32.  The
+ * surrogate search keeps the network's top-k cells and re-scores the 5 cm
+ * points of each cell (4 x 4 around it) with the exact kernel: a production
+ * pattern built on Sec. 4.2-4.3, not part of the paper.
+ *
+ * Parameters on the host are in the real layout W0 [512][66], b0 [512],
+ * W1 [512][512], b1, W2 [512][512], b2, W3 [2806][512], b3 [2806]
+ * (dpps_mlp_param_count() floats).  Frames come from a dpps_batch of the
+ * same context. */
+typedef struct dpps_mlp dpps_mlp;
+
+int64_t dpps_mlp_param_count(void);
+/* max_frames: largest batch; max_k: largest top-k (<= 128); He-uniform
+ * initialisation from `seed`. */
+int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t seed,
+                    dpps_mlp **out);
+void dpps_mlp_destroy(dpps_mlp *m);
+int dpps_mlp_set_params(dpps_mlp *m, const float *host, int64_t n);
+int dpps_mlp_get_params(dpps_mlp *m, float *host, int64_t n);
+/* Parameter gradients of the last dpps_mlp_loss_grad (real layout). */
+int dpps_mlp_get_grads(dpps_mlp *m, float *host, int64_t n);
+int dpps_mlp_get_adam(dpps_mlp *m, float *host_m, float *host_v, int64_t n, int64_t *step);
+int dpps_mlp_set_adam(dpps_mlp *m, const float *host_m, const float *host_v, int64_t n,
+                      int64_t step);
+/* Predicted maps of the batch's frames into d_out [n_frames][ld_out] (f32,
+ * device; NULL keeps them internal for dpps_mlp_topk). */
+int dpps_mlp_forward(dpps_mlp *m, dpps_batch *b, float *d_out, int64_t ld_out, void *hip_stream);
+/* Forward, mean squared error against d_target [n_frames][ld_target] (device
+ * f32 score maps; -inf is read as 0) and backward into the parameter
+ * gradients; *loss (may be NULL) receives the loss (synchronises). */
+int dpps_mlp_loss_grad(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
+                       float *loss, void *hip_stream);
+/* One Adam step on the gradients (bias-corrected; decoupled weight decay
+ * added to the gradient of weights only), refreshing the bfloat16 copies. */
+int dpps_mlp_adam(dpps_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay,
+                  void *hip_stream);
+/* dpps_mlp_loss_grad then Adam (0.9, 0.999, 1e-8, no decay). */
+int dpps_mlp_train_step(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
+                        float lr, float *loss, void *hip_stream);
+/* The network input of each frame as bfloat16 [n_frames][66] (device). */
+int dpps_mlp_features(dpps_mlp *m, dpps_batch *b, uint16_t *d_x, void *hip_stream);
+/* Top-k cells (descending prediction, ties to the lower cell) of the last
+ * forward pass into d_cells [n_frames][k] (device int32). */
+int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, void *hip_stream);
+/* Surrogate search: forward, top-k cells, exact re-score of their 5 cm points
+ * with the frame's variants; best pass per frame into d_best (device).  With
+ * fallback != 0, frames where no proposed point is feasible are searched
+ * exactly on the whole 5 cm lattice (synchronous) and *n_fallback counts
+ * them.  The batch's own windows are not used. */
+int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
+                          int fallback, int32_t *n_fallback, void *hip_stream);
 
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);

@@ -90,6 +90,24 @@ def lib():
         L.dpps_last_kernel_ms.restype = C.c_float
         L.dpps_autotune.argtypes = [vp, vp, C.POINTER(Outputs_C), vp, C.c_char_p, i32,
                                     C.POINTER(C.c_float)]
+        pf = C.POINTER(C.c_float)
+        L.dpps_mlp_param_count.argtypes = []
+        L.dpps_mlp_param_count.restype = i64
+        L.dpps_mlp_create.argtypes = [vp, i32, i32, C.c_uint64, C.POINTER(vp)]
+        L.dpps_mlp_destroy.argtypes = [vp]
+        L.dpps_mlp_destroy.restype = None
+        L.dpps_mlp_set_params.argtypes = [vp, vp, i64]
+        L.dpps_mlp_get_params.argtypes = [vp, vp, i64]
+        L.dpps_mlp_get_grads.argtypes = [vp, vp, i64]
+        L.dpps_mlp_get_adam.argtypes = [vp, vp, vp, i64, C.POINTER(i64)]
+        L.dpps_mlp_set_adam.argtypes = [vp, vp, vp, i64, i64]
+        L.dpps_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
+        L.dpps_mlp_loss_grad.argtypes = [vp, vp, vp, i64, pf, vp]
+        L.dpps_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.dpps_mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, pf, vp]
+        L.dpps_mlp_features.argtypes = [vp, vp, vp, vp]
+        L.dpps_mlp_topk.argtypes = [vp, i32, i32, vp, vp]
+        L.dpps_surrogate_search.argtypes = [vp, vp, vp, i32, vp, C.c_int, C.POINTER(i32), vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
         L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
@@ -328,3 +346,138 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+MLP_OUT = 2806
+MLP_IN = 66
+
+
+class Mlp:
+    """The learned surrogate network on a Searcher's context (dpps_mlp_*)."""
+
+    def __init__(self, s: Searcher, max_frames: int, max_k: int = 64, seed: int = 0):
+        self.s = s
+        self.max_frames = max_frames
+        h = C.c_void_p()
+        _check(lib().dpps_mlp_create(s.h, max_frames, max_k, seed, C.byref(h)))
+        self.h = h
+        self.n = int(lib().dpps_mlp_param_count())
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().dpps_mlp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n, np.float32)
+        _check(lib().dpps_mlp_get_params(self.h, a.ctypes.data, self.n))
+        return a
+
+    def set_params(self, a: np.ndarray):
+        a = np.ascontiguousarray(a, np.float32)
+        _check(lib().dpps_mlp_set_params(self.h, a.ctypes.data, a.size))
+
+    def get_grads(self) -> np.ndarray:
+        a = np.zeros(self.n, np.float32)
+        _check(lib().dpps_mlp_get_grads(self.h, a.ctypes.data, self.n))
+        return a
+
+    def get_adam(self):
+        m = np.zeros(self.n, np.float32)
+        v = np.zeros(self.n, np.float32)
+        st = C.c_int64()
+        _check(lib().dpps_mlp_get_adam(self.h, m.ctypes.data, v.ctypes.data, self.n, C.byref(st)))
+        return m, v, int(st.value)
+
+    def set_adam(self, m, v, step: int):
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        _check(lib().dpps_mlp_set_adam(self.h, m.ctypes.data, v.ctypes.data, self.n, step))
+
+    def forward(self, batch: "Batch", out=None, stream=None):
+        import torch
+        nf = len(batch.pk.frames)
+        if out is None:
+            out = torch.empty((nf, MLP_OUT), dtype=torch.float32, device=self.s.device)
+        _check(lib().dpps_mlp_forward(self.h, batch.h, out.data_ptr(), out.stride(0),
+                                      _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, batch: "Batch", target, stream=None) -> float:
+        loss = C.c_float()
+        _check(lib().dpps_mlp_loss_grad(self.h, batch.h, target.data_ptr(), target.stride(0),
+                                        C.byref(loss), _stream_ptr(stream)))
+        return float(loss.value)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
+        _check(lib().dpps_mlp_adam(self.h, lr, beta1, beta2, eps, weight_decay,
+                                   _stream_ptr(stream)))
+
+    def train_step(self, batch: "Batch", target, lr: float, stream=None) -> float:
+        loss = C.c_float()
+        _check(lib().dpps_mlp_train_step(self.h, batch.h, target.data_ptr(), target.stride(0), lr,
+                                         C.byref(loss), _stream_ptr(stream)))
+        return float(loss.value)
+
+    def features(self, batch: "Batch", stream=None):
+        """bfloat16 network inputs [n_frames][66] as a float32 torch tensor."""
+        import torch
+        nf = len(batch.pk.frames)
+        raw = torch.empty((nf, MLP_IN), dtype=torch.int16, device=self.s.device)
+        _check(lib().dpps_mlp_features(self.h, batch.h, raw.data_ptr(), _stream_ptr(stream)))
+        return raw.view(torch.bfloat16).float()
+
+    def topk(self, n_frames: int, k: int, stream=None):
+        import torch
+        out = torch.empty((n_frames, k), dtype=torch.int32, device=self.s.device)
+        _check(lib().dpps_mlp_topk(self.h, n_frames, k, out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def search(self, batch: "Batch", k: int = 64, fallback: bool = True, best=None, stream=None):
+        """Surrogate search; returns (best records on device as bytes tensor, fallbacks)."""
+        import torch
+        nf = len(batch.pk.frames)
+        if best is None:
+            best = torch.empty(nf * BEST_DT.itemsize, dtype=torch.uint8, device=self.s.device)
+        nfb = C.c_int32()
+        _check(lib().dpps_surrogate_search(self.s.h, self.h, batch.h, k, best.data_ptr(),
+                                           int(fallback), C.byref(nfb), _stream_ptr(stream)))
+        return best, int(nfb.value)
+
+
+def best_records(t) -> np.ndarray:
+    """dpps_best records from a device byte tensor."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), BEST_DT)
+
+
+def pack_uniform(team: np.ndarray, opp: np.ndarray, passer: np.ndarray, windows, variants, p,
+                 out_flags: int = 0) -> Packed:
+    """Vectorised pack of frames that share robot counts, windows and
+    variants (team [n, nt, 4], opp [n, no, 4], passer [n]); the ball sits on
+    the passer."""
+    n, nt, no = team.shape[0], team.shape[1], opp.shape[1]
+    nw, nv = len(windows), len(variants)
+    fr = np.zeros(n, FRAME_DT)
+    idx = np.arange(n)
+    fr["n_team"], fr["n_opp"], fr["passer"] = nt, no, passer
+    fr["robot_off"] = idx * (nt + no)
+    fr["n_windows"], fr["window_off"] = nw, idx * nw
+    fr["n_variants"], fr["variant_off"] = nv, idx * nv
+    fr["ball_x"] = team[idx, passer, 0]
+    fr["ball_y"] = team[idx, passer, 1]
+    r = np.concatenate([team, opp], axis=1).reshape(-1, 4).astype(np.float32)
+    robots = np.zeros(r.shape[0], ROBOT_DT)
+    robots["x"], robots["y"], robots["vx"], robots["vy"] = r[:, 0], r[:, 1], r[:, 2], r[:, 3]
+    win = np.array([tuple(w) for w in windows] * n, WINDOW_DT)
+    var = np.array([(int(v[0]), float(v[1])) for v in variants] * n, VARIANT_DT)
+    total = C.c_int64()
+    pc = params_c(p, out_flags)
+    _check(lib().dpps_layout(C.byref(pc), n, _ptr(fr), _ptr(win), C.byref(total)))
+    ends = np.append(fr["out_off"][1:], total.value)
+    return Packed(fr, robots, win, var, int(total.value), (ends - fr["out_off"]).astype(np.int64))

@@ -28,6 +28,8 @@ COMMON = [
 SOURCES = {
     "dpps_api.hip": [],
     "dpps_kernels.hip": ["-Xarch_device", "-fno-honor-nans", "-Xarch_device", "-mno-amdgpu-ieee"],
+    "mlp_api.hip": [],
+    "mlp_kernels.hip": [],
 }
 
 

@@ -15,15 +15,14 @@
 #include <string>
 #include <vector>
 
-#include "dpps_internal.h"
+#include "runtime.h"
 
 using namespace dpps;
 
-namespace {
+namespace dpps {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -34,13 +33,6 @@ int fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
-
-#define HIP_OK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(DPPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
-    } while (0)
 
 bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
 
@@ -142,16 +134,6 @@ DevParams derive(const dpps_params *p)
     P.invK_d = 1.0 / (double)p->n_samples;
     return P;
 }
-
-// Host-side description of a batch: the device tables before upload.
-struct HostTables {
-    std::vector<FrameDev> frames;
-    std::vector<dpps_robot> robots;
-    std::vector<dpps_variant> variants;
-    std::vector<WinDev> wins;
-    std::vector<TileDev> tiles;
-    int64_t points = 0;
-};
 
 int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
                  const dpps_robot *robots, const dpps_window *windows,
@@ -260,66 +242,15 @@ int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frame
     return DPPS_OK;
 }
 
-}  // namespace
+}  // namespace dpps
 
 // ----------------------------------------------------------------------------
 // contexts and batches
 // ----------------------------------------------------------------------------
 
-struct DeviceArena {
-    void *ptr = nullptr;
-    size_t cap = 0;
-};
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-struct dpps_batch {
-    dpps_ctx *ctx = nullptr;
-    HostTables T;
-    int32_t n_frames = 0;
-    int tile_points = 0;
-    DeviceArena arena;       // frames, robots, variants, wins, tiles
-    FrameDev *d_frames = nullptr;
-    dpps_robot *d_robots = nullptr;
-    dpps_variant *d_variants = nullptr;
-    WinDev *d_wins = nullptr;
-    TileDev *d_tiles = nullptr;
-    DeviceArena aux;         // work counter, tile records, best
-    uint32_t *d_counter = nullptr;
-    TileRec *d_tile_rec = nullptr;
-    dpps_best *d_best = nullptr;
-    // graph cache
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    dpps_outputs graph_out;
-    void *graph_stream = nullptr;
-    int graph_cfg[3] = {0, 0, 0};
-};
-
-struct dpps_ctx {
-    dpps_params p;
-    DevParams P;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int n_cu = 256;
-    int tile_points = 8;
-    int waves = 4;
-    int wg_per_cu = 0;       // 0: as many as fit (occupancy of the search kernel)
-    int persistent = 1;
-    dpps_batch scratch;      // used by dpps_search / dpps_search_batch
-    void *pinned = nullptr;
-    size_t pinned_cap = 0;
-    hipEvent_t staged = nullptr;   // pinned staging consumed
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    bool timed = false;
-    uint64_t budget_used = 0;
-    // optional ring of event pairs bracketing the search kernel of each run
-    std::vector<hipEvent_t> ring0, ring1;
-    int ring_used = 0;
-};
-
-static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-static int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes)
+int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes)
 {
     if (bytes <= A.cap) return DPPS_OK;
     size_t want = align_up(bytes + bytes / 4, 1 << 16);
@@ -347,7 +278,7 @@ static int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes)
     return DPPS_OK;
 }
 
-static void graph_drop(dpps_batch *b)
+void graph_drop(dpps_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -355,7 +286,7 @@ static void graph_drop(dpps_batch *b)
     b->graph = nullptr;
 }
 
-static void ring_free(dpps_ctx *c)
+void ring_free(dpps_ctx *c)
 {
     for (hipEvent_t e : c->ring0) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ring1) (void)hipEventDestroy(e);
@@ -364,12 +295,7 @@ static void ring_free(dpps_ctx *c)
     c->ring_used = 0;
 }
 
-// Sizes of the table section of the arena.
-struct Layout {
-    size_t off_frames, off_robots, off_variants, off_wins, off_tiles, total;
-};
-
-static Layout table_layout(const HostTables &T)
+Layout table_layout(const HostTables &T)
 {
     Layout L;
     size_t o = 0;
@@ -382,7 +308,7 @@ static Layout table_layout(const HostTables &T)
     return L;
 }
 
-static void pack_tables(const HostTables &T, const Layout &L, char *dst)
+void pack_tables(const HostTables &T, const Layout &L, char *dst)
 {
     if (!T.frames.empty()) memcpy(dst + L.off_frames, T.frames.data(), T.frames.size() * sizeof(FrameDev));
     if (!T.robots.empty()) memcpy(dst + L.off_robots, T.robots.data(), T.robots.size() * sizeof(dpps_robot));
@@ -392,7 +318,7 @@ static void pack_tables(const HostTables &T, const Layout &L, char *dst)
     if (!T.tiles.empty()) memcpy(dst + L.off_tiles, T.tiles.data(), T.tiles.size() * sizeof(TileDev));
 }
 
-static int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
+int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
 {
     int rc = arena_reserve(c, b->arena, L.total);
     if (rc) return rc;
@@ -419,7 +345,7 @@ static int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L)
 }
 
 // Regenerate the tile list for b->tile_points (frames and windows unchanged).
-static void retile(HostTables &T, int tile_points)
+void retile(HostTables &T, int tile_points)
 {
     T.tiles.clear();
     for (FrameDev &F : T.frames) {
@@ -434,7 +360,7 @@ static void retile(HostTables &T, int tile_points)
 }
 
 // Synchronous upload of a batch's tables (after creation or a new tile size).
-static int batch_upload(dpps_ctx *c, dpps_batch *b)
+int batch_upload(dpps_ctx *c, dpps_batch *b)
 {
     graph_drop(b);
     retile(b->T, b->tile_points);
@@ -448,7 +374,7 @@ static int batch_upload(dpps_ctx *c, dpps_batch *b)
     return DPPS_OK;
 }
 
-static int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st,
+int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st,
                      bool timed)
 {
     if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
@@ -538,7 +464,9 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        // a blocking stream: ordered with the legacy default stream, so callers
+        // that pass no stream see results in default-stream order
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
             delete c;
             return fail(DPPS_E_DEVICE, "hipStreamCreate failed");
         }

@@ -1,0 +1,41 @@
+// mlp_internal.h -- internal interface of the surrogate kernels (libdpps).
+#pragma once
+
+#include <stdint.h>
+
+#include "dpps_internal.h"
+
+namespace dpps {
+
+enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+#define TOPK_SORT 4096   // cells sorted per frame (>= coarse lattice size)
+#define TOPK_MAX 128     // largest k
+
+struct GemmArgs {
+    const uint16_t *A;   // bf16
+    const uint16_t *B;   // bf16
+    int lda, ldb, ldc;
+    int M, N, K;
+    const float *bias;   // EPI_BIAS, EPI_BIAS_GELU
+    const float *Zin;    // EPI_GELU_GRAD: pre-activation, [M][ldc]
+    float *Cf;           // f32 output
+    uint16_t *Cb;        // bf16 output
+};
+
+int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream);
+int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st);
+int launch_mse(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
+               int outs_pad, uint16_t *dz, float *partial, void *st);
+int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                float eps, float c1, float c2, float wd, uint16_t *wb, uint16_t *wbt, int rows,
+                int cols, void *st);
+int launch_cast(const float *w, int64_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, void *st);
+int launch_featurize(const FrameDev *frames, const dpps_robot *robots, int n_frames, int rows_pad,
+                     int in_pad, float inv_hl, float inv_hw, float inv_v, uint16_t *x, void *st);
+int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out, void *st);
+int launch_rescore_tables(const FrameDev *src, int n_frames, const int32_t *cells, int k,
+                          int coarse_nx, int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
+                          WinDev *wins, TileDev *tiles, void *st);
+
+}  // namespace dpps

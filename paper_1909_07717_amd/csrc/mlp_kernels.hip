@@ -1,0 +1,478 @@
+// mlp_kernels.hip -- kernels of the learned surrogate (gfx950).
+//
+// The surrogate is a multilayer perceptron 66 -> 512 -> 512 -> 512 -> 2806
+// with GELU activations that predicts the exact search's 20 cm score map of
+// a frame; its top-64 cells are then re-scored exactly at 5 cm.  Weights and
+// activations are bfloat16, products accumulate in float32 on the matrix
+// cores (v_mfma_f32_16x16x32_bf16); biases, pre-activations, gradients and
+// the Adam state are float32.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mlp_internal.h"
+
+namespace dpps {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(4))) float f32x4_t;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float x)
+{
+    float cdf = 0.5f * (1.0f + erff(x * 0.70710678118654752f));
+    float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+    return cdf + x * pdf;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M][N] = sum_k A(m, k) B(k, n), bf16 operands, f32 accumulation.
+// A(m, k) = A[m*lda + k] when A_K (k contiguous), else A[k*lda + m].
+// B(k, n) = B[n*ldb + k] when B_K (k contiguous), else B[k*ldb + n].
+// M, N, K are multiples of 8 (vectors of 8 never straddle an edge).
+// Block tile 64 x 64, K step 32, 4 waves each owning a 32 x 32 quarter as
+// 2 x 2 MFMA tiles of 16 x 16.
+// ---------------------------------------------------------------------------
+#define GT 64
+#define GK 32
+#define LDSK (GK + 8)   // padded row (bf16 elements) to spread LDS banks
+
+template <bool A_K, bool B_K>
+__device__ __forceinline__ void load_tiles(const uint16_t *__restrict__ A, int lda,
+                                           const uint16_t *__restrict__ B, int ldb, int M, int N,
+                                           int K, int m0, int n0, int k0, uint16_t *As,
+                                           uint16_t *Bs)
+{
+    const int t = threadIdx.x;  // 256 threads, one vector of 8 for A and one for B
+    // A tile: 64 (m) x 32 (k)
+    if (A_K) {
+        const int m = t >> 2, kk = (t & 3) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (m0 + m < M && k0 + kk < K) v = *(const uint4 *)(A + (size_t)(m0 + m) * lda + k0 + kk);
+        *(uint4 *)(As + m * LDSK + kk) = v;
+    } else {
+        const int kk = t >> 3, m = (t & 7) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (m0 + m < M && k0 + kk < K) v = *(const uint4 *)(A + (size_t)(k0 + kk) * lda + m0 + m);
+        const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) As[(m + j) * LDSK + kk] = e[j];
+    }
+    // B tile: 32 (k) x 64 (n), stored as Bs[n][k]
+    if (B_K) {
+        const int n = t >> 2, kk = (t & 3) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (n0 + n < N && k0 + kk < K) v = *(const uint4 *)(B + (size_t)(n0 + n) * ldb + k0 + kk);
+        *(uint4 *)(Bs + n * LDSK + kk) = v;
+    } else {
+        const int kk = t >> 3, n = (t & 7) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (n0 + n < N && k0 + kk < K) v = *(const uint4 *)(B + (size_t)(k0 + kk) * ldb + n0 + n);
+        const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bs[(n + j) * LDSK + kk] = e[j];
+    }
+}
+
+template <bool A_K, bool B_K, int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[GT * LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT * LDSK];
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    const int fr = l & 15, fk = (l >> 4) * 8;  // fragment row/col and k offset
+    for (int k0 = 0; k0 < g.K; k0 += GK) {
+        __syncthreads();
+        load_tiles<A_K, B_K>(g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, m0, n0, k0, As, Bs);
+        __syncthreads();
+        bf16x8_t af[2], bfr[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            af[a] = *(const bf16x8_t *)(As + (wm + a * 16 + fr) * LDSK + fk);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            bfr[b] = *(const bf16x8_t *)(Bs + (wn + b * 16 + fr) * LDSK + fk);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    // epilogue: lane holds D[(l/16)*4 + i][l%16] of each 16 x 16 tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int n = n0 + wn + b * 16 + (l & 15);
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm + a * 16 + (l >> 4) * 4 + i;
+                if (m >= g.M) continue;
+                float v = acc[a][b][i];
+                const size_t o = (size_t)m * g.ldc + n;
+                if (EPI == EPI_BIAS_GELU) {
+                    v += g.bias[n];
+                    g.Cf[o] = v;                    // pre-activation (f32)
+                    g.Cb[o] = f2bf(gelu(v));        // activation (bf16)
+                } else if (EPI == EPI_BIAS) {
+                    g.Cf[o] = v + g.bias[n];
+                } else if (EPI == EPI_GELU_GRAD) {
+                    // v = dA; dZ = dA * gelu'(Z)
+                    g.Cb[o] = f2bf(v * gelu_grad(g.Zin[o]));
+                } else {
+                    g.Cf[o] = v;
+                }
+            }
+        }
+    }
+}
+
+template <bool A_K, bool B_K, int EPI>
+static void launch_gemm(const GemmArgs &g, hipStream_t st)
+{
+    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
+    hipLaunchKernelGGL((gemm_kernel<A_K, B_K, EPI>), grid, dim3(256), 0, st, g);
+}
+
+int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if ((g.M | g.N | g.K) & 7) return -1;
+#define GEMM_CASE(AK, BK)                                                          \
+    if (a_k == AK && b_k == BK) {                                                  \
+        switch (epi) {                                                             \
+        case EPI_NONE: launch_gemm<AK, BK, EPI_NONE>(g, st); break;                \
+        case EPI_BIAS: launch_gemm<AK, BK, EPI_BIAS>(g, st); break;                \
+        case EPI_BIAS_GELU: launch_gemm<AK, BK, EPI_BIAS_GELU>(g, st); break;      \
+        case EPI_GELU_GRAD: launch_gemm<AK, BK, EPI_GELU_GRAD>(g, st); break;      \
+        default: return -1;                                                        \
+        }                                                                          \
+        return hipGetLastError() == hipSuccess ? 0 : -1;                           \
+    }
+    GEMM_CASE(true, true)
+    GEMM_CASE(false, false)
+    GEMM_CASE(true, false)
+    GEMM_CASE(false, true)
+#undef GEMM_CASE
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// elementwise and reduction kernels
+// ---------------------------------------------------------------------------
+
+// db[n] = sum over the first M rows of dZ[m][n] (bf16), fixed order.
+__global__ void colsum_kernel(const uint16_t *__restrict__ dz, int M, int N, int ld,
+                              float *__restrict__ db)
+{
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) s += bf2f(dz[(size_t)m * ld + n]);
+    db[n] = s;
+}
+
+// Mean squared error over the real outputs of the real rows.  Targets are
+// the exact search's score maps with infeasible cells (-inf) read as 0.
+// Writes dZ = 2 (y - t) / (rows * outs) as bf16 (zero in padding) and one
+// partial sum of squared errors per block.
+__global__ void mse_kernel(const float *__restrict__ y, int ldy, const float *__restrict__ tgt,
+                           int ldt, int rows, int outs, int rows_pad, int outs_pad,
+                           uint16_t *__restrict__ dz, float *__restrict__ partial)
+{
+    __shared__ float red[256];
+    const int r = blockIdx.x;
+    float acc = 0.0f;
+    const float scale = 2.0f / ((float)rows * (float)outs);
+    for (int n = threadIdx.x; n < outs_pad; n += blockDim.x) {
+        float g = 0.0f;
+        if (r < rows && n < outs) {
+            float t = tgt[(size_t)r * ldt + n];
+            t = t > -INFINITY ? t : 0.0f;
+            float d = y[(size_t)r * ldy + n] - t;
+            acc += d * d;
+            g = scale * d;
+        }
+        dz[(size_t)r * outs_pad + n] = f2bf(g);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && r < rows_pad) partial[r] = red[0];
+}
+
+// Adam on one parameter tensor (f32 master), then refresh its bf16 copies:
+// the weight as stored [out][in] and, for matrices, transposed [in][out].
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2, float wd, uint16_t *__restrict__ wb,
+                            uint16_t *__restrict__ wbt, int rows, int cols)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i] + wd * w[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) {
+        uint16_t h = f2bf(wi);
+        wb[i] = h;
+        if (wbt) {
+            int r = (int)(i / cols), c = (int)(i - (int64_t)r * cols);
+            wbt[(size_t)c * rows + r] = h;
+        }
+    }
+}
+
+// bf16 copies of a weight matrix [rows][cols] and its transpose.
+__global__ void cast_kernel(const float *__restrict__ w, int64_t n, uint16_t *__restrict__ wb,
+                            uint16_t *__restrict__ wbt, int rows, int cols)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint16_t h = f2bf(w[i]);
+    wb[i] = h;
+    if (wbt) {
+        int r = (int)(i / cols), c = (int)(i - (int64_t)r * cols);
+        wbt[(size_t)c * rows + r] = h;
+    }
+}
+
+// Feature vector of a frame (one thread per frame): teammates with the passer
+// first and the rest by distance to the ball, zero-padded to 8 slots; then
+// the opponents by distance to the ball in slots 8-15; then the ball.
+// Positions are divided by the field's half length / half width, velocities
+// by 3.25 m/s.  Columns 66..in_pad-1 are zero; rows >= n_frames are zero.
+__global__ void featurize_kernel(const FrameDev *__restrict__ frames,
+                                 const dpps_robot *__restrict__ robots, int n_frames,
+                                 int rows_pad, int in_pad, float inv_hl, float inv_hw, float inv_v,
+                                 uint16_t *__restrict__ x)
+{
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= rows_pad) return;
+    uint16_t *row = x + (size_t)f * in_pad;
+    for (int c = 0; c < in_pad; ++c) row[c] = 0;
+    if (f >= n_frames) return;
+    const FrameDev F = frames[f];
+    const float bx = F.ball_x, by = F.ball_y;
+    for (int side = 0; side < 2; ++side) {
+        const int base = side == 0 ? 0 : F.n_team;
+        const int cnt = side == 0 ? F.n_team : F.n_opp;
+        int order[DPPS_MAX_SIDE];
+        float key[DPPS_MAX_SIDE];
+        int n = 0;
+        for (int r = 0; r < cnt && r < DPPS_MAX_SIDE; ++r) {
+            const dpps_robot R = robots[F.robot_off + base + r];
+            float dx = R.x - bx, dy = R.y - by;
+            float k = dx * dx + dy * dy;
+            if (side == 0 && r == F.passer) k = -1.0f;
+            int j = n++;
+            while (j > 0 && (key[j - 1] > k || (key[j - 1] == k && order[j - 1] > r))) {
+                key[j] = key[j - 1];
+                order[j] = order[j - 1];
+                --j;
+            }
+            key[j] = k;
+            order[j] = r;
+        }
+        for (int s = 0; s < n && s < 8; ++s) {
+            const dpps_robot R = robots[F.robot_off + base + order[s]];
+            uint16_t *o = row + (side * 8 + s) * 4;
+            o[0] = f2bf(R.x * inv_hl);
+            o[1] = f2bf(R.y * inv_hw);
+            o[2] = f2bf(R.vx * inv_v);
+            o[3] = f2bf(R.vy * inv_v);
+        }
+    }
+    row[64] = f2bf(bx * inv_hl);
+    row[65] = f2bf(by * inv_hw);
+}
+
+// Top-k cells of each frame's predicted map (one block per frame): sort
+// (score, index) keys descending with a bitonic network in LDS; ties go to
+// the lower index.  Keys of cells >= n_cells sort last.
+__global__ void __launch_bounds__(256) topk_kernel(const float *__restrict__ y, int ldy,
+                                                   int n_cells, int k, int32_t *__restrict__ out)
+{
+    __shared__ unsigned long long key[TOPK_SORT];
+    const int f = blockIdx.x;
+    for (int i = threadIdx.x; i < TOPK_SORT; i += blockDim.x) {
+        unsigned long long kk = 0ull;
+        if (i < n_cells) {
+            uint32_t u = __float_as_uint(y[(size_t)f * ldy + i]);
+            u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
+            kk = ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        }
+        key[i] = kk;
+    }
+    __syncthreads();
+    for (int size = 2; size <= TOPK_SORT; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < TOPK_SORT; i += blockDim.x) {
+                int j = i ^ stride;
+                if (j > i) {
+                    bool desc = (i & size) == 0;
+                    unsigned long long a = key[i], b = key[j];
+                    if (desc ? (a < b) : (a > b)) {
+                        key[i] = b;
+                        key[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        out[(size_t)f * k + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)key[i]);
+}
+
+// Re-score tables for the top-k cells (one block per frame): each coarse
+// cell (ci, cj) of the coarse lattice becomes the window of fine points
+// {4 ci - 2 .. 4 ci + 1} x {4 cj - 2 .. 4 cj + 1} clipped to the fine
+// lattice, one tile per window.
+__global__ void rescore_tables_kernel(const FrameDev *__restrict__ src, int n_frames,
+                                      const int32_t *__restrict__ cells, int k, int coarse_nx,
+                                      int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
+                                      WinDev *wins, TileDev *tiles)
+{
+    __shared__ int npts_s[TOPK_MAX];
+    __shared__ int base_s[TOPK_MAX];
+    const int f = blockIdx.x;
+    if (f >= n_frames) return;
+    const FrameDev F = src[f];
+    const int t = threadIdx.x;
+    int i0 = 0, j0 = 0, nx = 0, ny = 0;
+    if (t < k) {
+        const int c = cells[(size_t)f * k + t];
+        const int ci = c % coarse_nx, cj = c / coarse_nx;
+        int a0 = 4 * ci - 2, a1 = 4 * ci + 1, b0 = 4 * cj - 2, b1 = 4 * cj + 1;
+        a0 = max(a0, 0); b0 = max(b0, 0);
+        a1 = min(a1, fine_nx - 1); b1 = min(b1, fine_ny - 1);
+        i0 = a0; j0 = b0;
+        nx = max(a1 - a0 + 1, 0);
+        ny = max(b1 - b0 + 1, 0);
+        npts_s[t] = nx * ny;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int e = 0;
+        for (int w = 0; w < k; ++w) {
+            base_s[w] = e;
+            e += npts_s[w] * F.n_variants;
+        }
+    }
+    __syncthreads();
+    if (t < k) {
+        WinDev W;
+        W.h = fine_h;
+        W.i0 = i0; W.j0 = j0; W.nx = nx; W.ny = ny;
+        W.halfNx = 0.5f * (float)(fine_nx - 1);
+        W.halfNy = 0.5f * (float)(fine_ny - 1);
+        W.frame = f;
+        W.npts = nx * ny;
+        W.elem_base = base_s[t];
+        W.out_base = 0;
+        wins[(size_t)f * k + t] = W;
+        TileDev T;
+        T.win = f * k + t;
+        T.p0 = 0;
+        tiles[(size_t)f * k + t] = T;
+    }
+    if (t == 0) {
+        FrameDev G = F;
+        G.n_windows = k;
+        G.win_off = f * k;
+        G.tile_begin = f * k;
+        G.tile_count = k;
+        frames[f] = G;
+    }
+}
+
+// host launchers -------------------------------------------------------------
+
+int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st)
+{
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, (hipStream_t)st, dz, M,
+                       N, ld, db);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_mse(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
+               int outs_pad, uint16_t *dz, float *partial, void *st)
+{
+    hipLaunchKernelGGL(mse_kernel, dim3(rows_pad), dim3(256), 0, (hipStream_t)st, y, ldy, tgt, ldt,
+                       rows, outs, rows_pad, outs_pad, dz, partial);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                float eps, float c1, float c2, float wd, uint16_t *wb, uint16_t *wbt, int rows,
+                int cols, void *st)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)st, w, g, m, v, n, lr, b1, b2, eps, c1, c2, wd, wb, wbt, rows,
+                       cols);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_cast(const float *w, int64_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, void *st)
+{
+    hipLaunchKernelGGL(cast_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)st, w, n, wb, wbt, rows, cols);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_featurize(const FrameDev *frames, const dpps_robot *robots, int n_frames, int rows_pad,
+                     int in_pad, float inv_hl, float inv_hw, float inv_v, uint16_t *x, void *st)
+{
+    hipLaunchKernelGGL(featurize_kernel, dim3((rows_pad + 63) / 64), dim3(64), 0, (hipStream_t)st,
+                       frames, robots, n_frames, rows_pad, in_pad, inv_hl, inv_hw, inv_v, x);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out, void *st)
+{
+    if (n_cells > TOPK_SORT || k > n_cells || k > TOPK_MAX) return -1;
+    hipLaunchKernelGGL(topk_kernel, dim3(n_frames), dim3(256), 0, (hipStream_t)st, y, ldy, n_cells,
+                       k, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_rescore_tables(const FrameDev *src, int n_frames, const int32_t *cells, int k,
+                          int coarse_nx, int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
+                          WinDev *wins, TileDev *tiles, void *st)
+{
+    if (k > TOPK_MAX) return -1;
+    hipLaunchKernelGGL(rescore_tables_kernel, dim3(n_frames), dim3(TOPK_MAX), 0, (hipStream_t)st,
+                       src, n_frames, cells, k, coarse_nx, fine_nx, fine_ny, fine_h, frames, wins,
+                       tiles);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dpps

@@ -1,0 +1,108 @@
+// runtime.h -- host-side internals of libdpps shared by its C ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "dpps_internal.h"
+
+namespace dpps {
+
+// Record a message for dpps_last_error() and return code.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int check_params(const dpps_params *p);
+DevParams derive(const dpps_params *p);
+int lattice_dim(float len, float h, int32_t *n);
+
+// Host-side description of a batch: the device tables before upload.
+struct HostTables {
+    std::vector<FrameDev> frames;
+    std::vector<dpps_robot> robots;
+    std::vector<dpps_variant> variants;
+    std::vector<WinDev> wins;
+    std::vector<TileDev> tiles;
+    int64_t points = 0;
+};
+
+int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
+                 const dpps_robot *robots, const dpps_window *windows,
+                 const dpps_variant *variants, int tile_points, HostTables &T);
+
+}  // namespace dpps
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(DPPS_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+using dpps::fail;
+
+struct DeviceArena {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct dpps_batch {
+    dpps_ctx *ctx = nullptr;
+    dpps::HostTables T;
+    int32_t n_frames = 0;
+    int tile_points = 0;
+    DeviceArena arena;       // frames, robots, variants, wins, tiles
+    dpps::FrameDev *d_frames = nullptr;
+    dpps_robot *d_robots = nullptr;
+    dpps_variant *d_variants = nullptr;
+    dpps::WinDev *d_wins = nullptr;
+    dpps::TileDev *d_tiles = nullptr;
+    DeviceArena aux;         // work counter, tile records, best
+    uint32_t *d_counter = nullptr;
+    dpps::TileRec *d_tile_rec = nullptr;
+    dpps_best *d_best = nullptr;
+    // graph cache
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    dpps_outputs graph_out;
+    void *graph_stream = nullptr;
+    int graph_cfg[3] = {0, 0, 0};
+};
+
+struct dpps_ctx {
+    dpps_params p;
+    dpps::DevParams P;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n_cu = 256;
+    int tile_points = 8;
+    int waves = 4;
+    int wg_per_cu = 0;       // 0: as many as fit (occupancy of the search kernel)
+    int persistent = 1;
+    dpps_batch scratch;      // used by dpps_search / dpps_search_batch
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t staged = nullptr;   // pinned staging consumed
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    uint64_t budget_used = 0;
+    // optional ring of event pairs bracketing the search kernel of each run
+    std::vector<hipEvent_t> ring0, ring1;
+    int ring_used = 0;
+};
+
+// Sizes of the table section of the arena.
+struct Layout {
+    size_t off_frames, off_robots, off_variants, off_wins, off_tiles, total;
+};
+
+size_t align_up(size_t x, size_t a);
+int arena_reserve(dpps_ctx *c, DeviceArena &A, size_t bytes);
+void graph_drop(dpps_batch *b);
+Layout table_layout(const dpps::HostTables &T);
+void pack_tables(const dpps::HostTables &T, const Layout &L, char *dst);
+int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L);
+int batch_upload(dpps_ctx *c, dpps_batch *b);
+int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st, bool timed);

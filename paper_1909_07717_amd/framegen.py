@@ -223,6 +223,41 @@ def config_batch(seed: int, n_frames: int = 4096, n_speeds: int = 8) -> list[Fra
     return [config_batch_frame(rng, n_speeds) for _ in range(n_frames)]
 
 
+def uniform_batch_arrays(seed: int, n: int, n_team: int = 6, n_opp: int = 6,
+                         params: Params = Params(), vdisc: float = 1.5):
+    """n frames of one size drawn at once (for training streams): returns
+    (team [n, n_team, 4], opp [n, n_opp, 4], passer [n]) as float32 / int32.
+    Same distributions as random_frame; draw order: team positions, team
+    velocities, opponent positions, opponent velocities, passers."""
+    rng = np.random.default_rng(seed)
+    hl, hw = params.field_len / 2, params.field_wid / 2
+
+    def pos(m):
+        return np.stack([rng.uniform(-hl, hl, (n, m)), rng.uniform(-hw, hw, (n, m))], -1)
+
+    def vel(m):
+        sp = vdisc * np.sqrt(rng.uniform(0.0, 1.0, (n, m)))
+        hd = 2.0 * np.pi * rng.uniform(0.0, 1.0, (n, m))
+        return np.stack([sp * np.cos(hd), sp * np.sin(hd)], -1)
+
+    tp, tv = pos(n_team), vel(n_team)
+    op, ov = pos(n_opp), vel(n_opp)
+    passer = rng.integers(0, n_team, n).astype(np.int32)
+    team = np.concatenate([tp, tv], -1).astype(np.float32)
+    opp = np.concatenate([op, ov], -1).astype(np.float32)
+    return team, opp, passer
+
+
+def frames_from_arrays(team, opp, passer, windows, variants) -> list:
+    """Frame objects (ball on the passer) from uniform_batch_arrays output."""
+    out = []
+    for i in range(team.shape[0]):
+        t = team[i].copy()
+        out.append(Frame(t, opp[i].copy(), int(passer[i]), t[int(passer[i]), :2].copy(),
+                         list(windows), list(variants)))
+    return out
+
+
 def with_windows(f: Frame, windows) -> Frame:
     g = f.copy()
     g.windows = list(windows)

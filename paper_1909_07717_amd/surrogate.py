@@ -1,0 +1,196 @@
+"""Training and evaluation of the learned surrogate (on the GPU, through the
+library's own kernels).
+
+    python3 -m paper_1909_07717_amd.surrogate train --frames 2000000 --out W.npz
+    python3 -m paper_1909_07717_amd.surrogate eval --weights W.npz --frames 2000
+
+Training frames are 6 v 6 robot states drawn in batches (one generator per
+batch, seed = 1 000 000 + batch index); each frame's label is the exact
+search's 20 cm score map for one flat pass at 4 m/s with K = 64 samples,
+computed by the exact kernel on the same device.  Loss: mean squared error
+with infeasible cells as 0.  Optimiser: Adam with a cosine-decayed rate.
+
+Evaluation compares, on frames from a disjoint seed range (20 000 000 + i),
+the surrogate search (top-k cells re-scored exactly at 5 cm, exact fallback)
+with the exact search of the whole 5 cm lattice: score regret
+(S*_exact - S_chosen) / S*_exact, chosen-point match rate and fallback rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate.npz")
+TRAIN_SEED = 1_000_000
+EVAL_SEED = 20_000_000
+
+
+def _params():
+    from paper_1909_07717_amd.framegen import Params
+    return Params(n_samples=64).as_f32()
+
+
+def _label_setup():
+    from paper_1909_07717_amd.framegen import full_window, variants_for
+    return [full_window(0.2)], variants_for([4.0], flat=True, chip=False)
+
+
+def save_checkpoint(path, net, step: int, extra: dict):
+    m, v, st = net.get_adam()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=net.get_params(), adam_m=m, adam_v=v, adam_step=np.int64(st),
+             data_step=np.int64(step), meta=np.frombuffer(json.dumps(extra).encode(), np.uint8))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    with np.load(path, allow_pickle=False) as z:
+        out = {k: z[k] for k in z.files}
+    out["meta"] = json.loads(out["meta"].tobytes().decode()) if "meta" in out else {}
+    return out
+
+
+def train(frames: int, batch: int, lr: float, out: str, resume: str | None = None,
+          log_every: int = 20, seed: int = 0):
+    import torch
+
+    from paper_1909_07717_amd import binding as B
+    from paper_1909_07717_amd.framegen import uniform_batch_arrays
+
+    p = _params()
+    windows, variants = _label_setup()
+    s = B.Searcher(p)
+    net = B.Mlp(s, batch, seed=seed)
+    steps = max(1, frames // batch)
+    start = 0
+    if resume:
+        ck = load_checkpoint(resume)
+        net.set_params(ck["params"])
+        net.set_adam(ck["adam_m"], ck["adam_v"], int(ck["adam_step"]))
+        start = int(ck["data_step"])
+    st = torch.cuda.Stream()
+    log = []
+    t0 = time.time()
+    for step in range(start, steps):
+        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + step, batch)
+        pk = B.pack_uniform(team, opp, passer, windows, variants, p)
+        bt = s.batch(pk)
+        lab = s.outputs_for(pk, mask=False)
+        with torch.cuda.stream(st):
+            bt.run(lab, stream=st)
+            rate = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
+            loss = net.train_step(bt, lab.score.view(batch, 2806), rate, stream=st)
+        bt.close()
+        if step % log_every == 0 or step == steps - 1:
+            rec = {"step": step, "frames": (step + 1) * batch, "loss": loss, "lr": rate,
+                   "elapsed_s": round(time.time() - t0, 2)}
+            log.append(rec)
+            print(json.dumps(rec), flush=True)
+    meta = {"frames": steps * batch, "batch": batch, "lr": lr, "steps": steps,
+            "train_seed": TRAIN_SEED, "log": log}
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    save_checkpoint(out, net, steps, meta)
+    net.close()
+    s.close()
+    return log
+
+
+def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, random_net=False,
+             seed0: int = EVAL_SEED):
+    """Regret statistics of the surrogate search against the exact 5 cm search."""
+    import torch
+
+    from paper_1909_07717_amd import binding as B
+    from paper_1909_07717_amd.framegen import full_window, uniform_batch_arrays, variants_for
+
+    p = _params()
+    variants = variants_for([4.0], flat=True, chip=False)
+    fine = [full_window(0.05)]
+    s = B.Searcher(p)
+    net = B.Mlp(s, batch, max_k=max(k, 1), seed=12345)
+    if weights and not random_net:
+        net.set_params(load_checkpoint(weights)["params"])
+    regrets, match, fallbacks, found_both, none_exact = [], 0, 0, 0, 0
+    t_exact = t_sur = 0.0
+    n_done = 0
+    bi = 0
+    while n_done < frames:
+        n = min(batch, frames - n_done)
+        team, opp, passer = uniform_batch_arrays(seed0 + bi, n)
+        bi += 1
+        pk = B.pack_uniform(team, opp, passer, fine, variants, p)
+        bt = s.batch(pk)
+        ex = s.outputs_for(pk, mask=False, score=False)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        bt.run(ex)
+        torch.cuda.synchronize()
+        t_exact += time.perf_counter() - a
+        a = time.perf_counter()
+        sb, nfb = net.search(bt, k=k, fallback=True)
+        torch.cuda.synchronize()
+        t_sur += time.perf_counter() - a
+        be = ex.best_host()
+        bs = B.best_records(sb)
+        fallbacks += nfb
+        for i in range(n):
+            if not be[i]["found"]:
+                none_exact += 1
+                continue
+            if not bs[i]["found"]:
+                regrets.append(1.0)
+                continue
+            found_both += 1
+            r = (float(be[i]["score"]) - float(bs[i]["score"])) / float(be[i]["score"])
+            regrets.append(max(r, 0.0))
+            match += int(be[i]["i"] == bs[i]["i"] and be[i]["j"] == bs[i]["j"])
+        bt.close()
+        n_done += n
+    r = np.array(regrets)
+    res = {"frames": frames, "k": k, "frames_with_exact_best": int(r.size),
+           "regret_le_1pct": float(np.mean(r <= 0.01)) if r.size else None,
+           "regret_mean": float(r.mean()) if r.size else None,
+           "regret_p99": float(np.percentile(r, 99)) if r.size else None,
+           "match_rate": match / max(r.size, 1), "fallback_rate": fallbacks / frames,
+           "no_feasible_exact": none_exact,
+           "exact_frames_per_s": frames / t_exact, "surrogate_frames_per_s": frames / t_sur,
+           "network": "random init" if (random_net or not weights) else os.path.basename(weights)}
+    net.close()
+    s.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--frames", type=int, default=2_000_000)
+    t.add_argument("--batch", type=int, default=4096)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--out", default=WEIGHTS)
+    t.add_argument("--resume", default=None)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", default=WEIGHTS)
+    e.add_argument("--frames", type=int, default=2000)
+    e.add_argument("--k", type=int, default=64)
+    e.add_argument("--random", action="store_true")
+    args = ap.parse_args()
+    if args.cmd == "train":
+        train(args.frames, args.batch, args.lr, args.out, args.resume)
+    else:
+        print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random)),
+              flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+"""The surrogate's kernels through the C ABI against the FP64 reference
+(oracle/mlp_ref.py): features, forward pass, loss and parameter gradients
+(BF16 operands, FP32 accumulation: relative L2 tolerances), Adam, top-k, the
+surrogate search against the exact search on the same windows, the
+fallback, and checkpoint/resume determinism of training."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as M
+from oracle import oracle as O
+from paper_1909_07717_amd.framegen import (Params, Frame, config_small, full_window,
+                                           random_frame, variants_for)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = Params(n_samples=64).as_f32()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1909_07717_amd import binding
+    assert torch.cuda.is_available()
+    return binding
+
+
+def _frames(n, base=0):
+    return [config_small(base + i) for i in range(n)]
+
+
+def _labels(B, s, frames):
+    """Exact 20 cm score maps of the frames (device, [n][2806])."""
+    bt = s.batch(frames)
+    out = s.outputs_for(bt.pk, mask=False)
+    bt.run(out)
+    torch.cuda.synchronize()
+    bt.close()
+    return out.score.view(len(frames), 2806)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_features(B):
+    s = B.Searcher(P)
+    frames = _frames(40)
+    net = B.Mlp(s, 64)
+    bt = s.batch(frames)
+    x = net.features(bt).cpu().numpy()
+    for i, f in enumerate(frames):
+        want = torch.tensor(M.features(f)).to(torch.bfloat16).float().numpy()
+        assert np.array_equal(x[i], want), i
+    bt.close(); net.close(); s.close()
+
+
+def test_forward_loss_and_gradients(B):
+    s = B.Searcher(P)
+    frames = _frames(37, 100)
+    net = B.Mlp(s, 64, seed=3)
+    bt = s.batch(frames)
+    T = _labels(B, s, frames)
+    y = net.forward(bt).cpu().numpy()
+    w = net.get_params().astype(np.float64)
+    X = np.stack([M.features(f) for f in frames])
+    Yref, _ = M.forward(w, X)
+    e_fwd = _rel_l2(y, Yref)
+    loss = net.loss_grad(bt, T)
+    g = net.get_grads().astype(np.float64)
+    lref, gref = M.loss_and_grad(w, X, M.targets(T.cpu().numpy()))
+    print(f"[mlp] forward rel L2 {e_fwd:.2e}, loss {loss:.6f} vs {lref:.6f}", flush=True)
+    assert e_fwd <= 2e-2
+    assert abs(loss - lref) <= 2e-2 * lref
+    o = 0
+    for l, (r, c) in enumerate(M.DIMS):
+        for name, n in (("W", r * c), ("b", r)):
+            e = _rel_l2(g[o:o + n], gref[o:o + n])
+            print(f"[mlp] grad {name}{l} rel L2 {e:.2e}", flush=True)
+            assert e <= 3e-2, (name, l, e)
+            o += n
+    # one Adam step from these gradients matches the reference update
+    net.adam(1e-3)
+    w1 = net.get_params().astype(np.float64)
+    wref, _, _ = M.adam(w, g, np.zeros_like(w), np.zeros_like(w), 1, 1e-3)
+    assert np.max(np.abs(w1 - wref)) <= 1e-6
+    m, v, step = net.get_adam()
+    assert step == 1
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-6, atol=1e-12)
+    bt.close(); net.close(); s.close()
+
+
+def test_topk_matches_sort(B):
+    s = B.Searcher(P)
+    frames = _frames(20, 200)
+    net = B.Mlp(s, 32, seed=5)
+    bt = s.batch(frames)
+    y = net.forward(bt).cpu().numpy()
+    cells = net.topk(len(frames), 64).cpu().numpy()
+    for i in range(len(frames)):
+        assert list(cells[i]) == list(M.topk(y[i], 64)), i
+    bt.close(); net.close(); s.close()
+
+
+def _windows_of_cells(cells):
+    wins = []
+    for c in cells:
+        ci, cj = int(c) % 61, int(c) // 61
+        a0, a1 = max(4 * ci - 2, 0), min(4 * ci + 1, 240)
+        b0, b1 = max(4 * cj - 2, 0), min(4 * cj + 1, 180)
+        wins.append((float(np.float32(0.05)), a0, b0, a1 - a0 + 1, b1 - b0 + 1))
+    return wins
+
+
+def test_surrogate_search_equals_exact_search_on_its_windows(B):
+    s = B.Searcher(P)
+    frames = _frames(12, 300)
+    net = B.Mlp(s, 16, seed=7)
+    bt = s.batch(frames)
+    best_t, nfb = net.search(bt, k=64, fallback=False)
+    best = B.best_records(best_t)
+    net.forward(bt)
+    cells = net.topk(len(frames), 64).cpu().numpy()
+    for i, f in enumerate(frames):
+        g = f.copy()
+        g.windows = _windows_of_cells(cells[i])
+        _, ref = s.search(g)
+        assert best[i].tobytes() == ref.tobytes(), i
+    bt.close(); net.close(); s.close()
+
+
+def test_fallback_when_no_proposal_is_feasible(B):
+    s = B.Searcher(P)
+    net = B.Mlp(s, 8, seed=1)
+    net.set_params(np.zeros(net.n, np.float32))  # every cell ties: the first 64 cells win
+    # passer at the centre, one teammate far from the bottom edge, opponents
+    # lined up along it: every proposal (bottom row) is intercepted
+    team = np.array([[0, 0, 0, 0], [3, 3, 0, 0]], np.float32)
+    opp = np.array([[x, -3.8, 0, 0] for x in (-5, -3, -1, 1, 3, 5)], np.float32)
+    f = Frame(team, opp, 0, np.array([0, 0], np.float32), [full_window(0.2)],
+              variants_for([4.0], True, False))
+    bt = s.batch([f])
+    best_t, nfb = net.search(bt, k=64, fallback=True)
+    best = B.best_records(best_t)[0]
+    assert nfb == 1
+    g = f.copy()
+    g.windows = [full_window(0.05)]
+    _, ref = s.search(g)
+    assert ref["found"] == 1 and best.tobytes() == ref.tobytes()
+    bt.close(); net.close(); s.close()
+
+
+def test_training_resume_is_deterministic(B):
+    s = B.Searcher(P)
+    data = [_frames(64, 1000 + 64 * i) for i in range(6)]
+    batches = [s.batch(fr) for fr in data]
+    labels = [_labels(B, s, fr) for fr in data]
+    a = B.Mlp(s, 64, seed=11)
+    losses = [a.train_step(batches[i], labels[i], 1e-3) for i in range(6)]
+    assert losses[-1] < losses[0]
+    b = B.Mlp(s, 64, seed=11)
+    for i in range(3):
+        b.train_step(batches[i], labels[i], 1e-3)
+    w, (m, v, st) = b.get_params(), b.get_adam()
+    c = B.Mlp(s, 64, seed=99)
+    c.set_params(w)
+    c.set_adam(m, v, st)
+    for i in range(3, 6):
+        c.train_step(batches[i], labels[i], 1e-3)
+    assert np.array_equal(c.get_params(), a.get_params())
+    for x in batches:
+        x.close()
+    a.close(); b.close(); c.close(); s.close()
