@@ -239,18 +239,29 @@ int dpps_mlp_set_adam(dpps_mlp *m, const float *host_m, const float *host_v, int
 /* Predicted maps of the batch's frames into d_out [n_frames][ld_out] (f32,
  * device; NULL keeps them internal for dpps_mlp_topk). */
 int dpps_mlp_forward(dpps_mlp *m, dpps_batch *b, float *d_out, int64_t ld_out, void *hip_stream);
-/* Forward, mean squared error against d_target [n_frames][ld_target] (device
- * f32 score maps; -inf is read as 0) and backward into the parameter
- * gradients; *loss (may be NULL) receives the loss (synchronises). */
+/* Forward, loss against d_target [n_frames][ld_target] (device f32 score
+ * maps, -inf where infeasible) and backward into the parameter gradients.
+ * Loss = mean over cells of (1 + pos_weight * t) (y - t)^2 with -inf read as
+ * 0, plus ce_weight times the mean over frames of the cross-entropy between
+ * softmax(t / tau) over the feasible cells and softmax(y / tau) over all
+ * cells.  *loss (may be NULL) receives it (synchronises). */
 int dpps_mlp_loss_grad(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
-                       float *loss, void *hip_stream);
+                       float pos_weight, float ce_weight, float tau, float *loss,
+                       void *hip_stream);
+/* Coarse-cell labels from fine score maps d_fine [n_frames][fine_ny][fine_nx]:
+ * cell (ci, cj) gets the largest fine score over the fine points
+ * {4ci-2 .. 4ci+1} x {4cj-2 .. 4cj+1} (the points its re-score visits), -inf
+ * if none is feasible; d_coarse [n_frames][coarse_ny][coarse_nx]. */
+int dpps_pool_cells(const float *d_fine, int32_t n_frames, int32_t fine_nx, int32_t fine_ny,
+                    float *d_coarse, int32_t coarse_nx, int32_t coarse_ny, void *hip_stream);
 /* One Adam step on the gradients (bias-corrected; decoupled weight decay
  * added to the gradient of weights only), refreshing the bfloat16 copies. */
 int dpps_mlp_adam(dpps_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay,
                   void *hip_stream);
 /* dpps_mlp_loss_grad then Adam (0.9, 0.999, 1e-8, no decay). */
 int dpps_mlp_train_step(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
-                        float lr, float *loss, void *hip_stream);
+                        float lr, float pos_weight, float ce_weight, float tau, float *loss,
+                        void *hip_stream);
 /* The network input of each frame as bfloat16 [n_frames][66] (device). */
 int dpps_mlp_features(dpps_mlp *m, dpps_batch *b, uint16_t *d_x, void *hip_stream);
 /* Top-k cells (descending prediction, ties to the lower cell) of the last

@@ -98,8 +98,13 @@ def targets(score_maps):
     return t
 
 
-def mse(Y, T) -> float:
-    return float(np.mean((Y - T) ** 2))
+def weights(T, pos_weight=0.0):
+    """Per-cell loss weights 1 + pos_weight * target."""
+    return 1.0 + pos_weight * T
+
+
+def mse(Y, T, pos_weight=0.0) -> float:
+    return float(np.mean(weights(T, pos_weight) * (Y - T) ** 2))
 
 
 def backward(flat, cache, dY) -> np.ndarray:
@@ -117,11 +122,55 @@ def backward(flat, cache, dY) -> np.ndarray:
     return join(grads)
 
 
-def loss_and_grad(flat, X, T):
+def cross_entropy(Y, T_raw, tau):
+    """Per-row cross-entropy between the target distribution softmax(t / tau)
+    over the feasible cells (finite t) and softmax(y / tau) over all cells,
+    and its gradient with respect to Y; rows with no feasible cell give 0."""
+    Y = np.asarray(Y, np.float64)
+    T_raw = np.asarray(T_raw, np.float64)
+    ce = np.zeros(Y.shape[0])
+    grad = np.zeros_like(Y)
+    for r in range(Y.shape[0]):
+        feas = np.isfinite(T_raw[r])
+        if not feas.any():
+            continue
+        ly = Y[r] / tau
+        ly = ly - ly.max()
+        logp = ly - np.log(np.exp(ly).sum())
+        lt = np.where(feas, T_raw[r] / tau, -np.inf)
+        lt = lt - lt[feas].max()
+        q = np.where(feas, np.exp(lt), 0.0)
+        q /= q.sum()
+        ce[r] = -(q * logp).sum()
+        grad[r] = (np.exp(logp) - q) / tau
+    return ce, grad
+
+
+def loss_and_grad(flat, X, T_raw, pos_weight=0.0, ce_weight=0.0, tau=0.02):
+    """Training loss (weighted squared error on targets with -inf read as 0,
+    plus ce_weight times the mean cross-entropy) and its flat gradient."""
+    T = targets(T_raw)
     Y, cache = forward(flat, X)
-    loss = mse(Y, T)
-    dY = 2.0 * (Y - T) / Y.size
+    loss = mse(Y, T, pos_weight)
+    dY = 2.0 * weights(T, pos_weight) * (Y - T) / Y.size
+    if ce_weight > 0.0:
+        ce, g = cross_entropy(Y, T_raw, tau)
+        loss += ce_weight * ce.mean()
+        dY = dY + ce_weight * g / Y.shape[0]
     return loss, backward(flat, cache, dY)
+
+
+def pool(fine, fnx=241, fny=181, cnx=61, cny=46):
+    """Coarse labels: cell (ci, cj) takes the largest fine score over the fine
+    points {4ci-2..4ci+1} x {4cj-2..4cj+1} inside the fine lattice."""
+    fine = np.asarray(fine, np.float64).reshape(-1, fny, fnx)
+    out = np.full((fine.shape[0], cny * cnx), -np.inf)
+    for cj in range(cny):
+        for ci in range(cnx):
+            I0, I1 = max(4 * ci - 2, 0), min(4 * ci + 1, fnx - 1)
+            J0, J1 = max(4 * cj - 2, 0), min(4 * cj + 1, fny - 1)
+            out[:, cj * cnx + ci] = fine[:, J0:J1 + 1, I0:I1 + 1].reshape(fine.shape[0], -1).max(1)
+    return out
 
 
 def adam(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

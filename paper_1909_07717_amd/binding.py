@@ -102,9 +102,11 @@ def lib():
         L.dpps_mlp_get_adam.argtypes = [vp, vp, vp, i64, C.POINTER(i64)]
         L.dpps_mlp_set_adam.argtypes = [vp, vp, vp, i64, i64]
         L.dpps_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
-        L.dpps_mlp_loss_grad.argtypes = [vp, vp, vp, i64, pf, vp]
+        f32 = C.c_float
+        L.dpps_mlp_loss_grad.argtypes = [vp, vp, vp, i64, f32, f32, f32, pf, vp]
+        L.dpps_pool_cells.argtypes = [vp, i32, i32, i32, vp, i32, i32, vp]
         L.dpps_mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
-        L.dpps_mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, pf, vp]
+        L.dpps_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, f32, f32, f32, pf, vp]
         L.dpps_mlp_features.argtypes = [vp, vp, vp, vp]
         L.dpps_mlp_topk.argtypes = [vp, i32, i32, vp, vp]
         L.dpps_surrogate_search.argtypes = [vp, vp, vp, i32, vp, C.c_int, C.POINTER(i32), vp]
@@ -409,20 +411,24 @@ class Mlp:
                                       _stream_ptr(stream)))
         return out
 
-    def loss_grad(self, batch: "Batch", target, stream=None) -> float:
+    def loss_grad(self, batch: "Batch", target, pos_weight: float = 0.0, ce_weight: float = 0.0,
+                  tau: float = 0.02, stream=None) -> float:
         loss = C.c_float()
         _check(lib().dpps_mlp_loss_grad(self.h, batch.h, target.data_ptr(), target.stride(0),
-                                        C.byref(loss), _stream_ptr(stream)))
+                                        pos_weight, ce_weight, tau, C.byref(loss),
+                                        _stream_ptr(stream)))
         return float(loss.value)
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
         _check(lib().dpps_mlp_adam(self.h, lr, beta1, beta2, eps, weight_decay,
                                    _stream_ptr(stream)))
 
-    def train_step(self, batch: "Batch", target, lr: float, stream=None) -> float:
+    def train_step(self, batch: "Batch", target, lr: float, pos_weight: float = 0.0,
+                   ce_weight: float = 0.0, tau: float = 0.02, stream=None) -> float:
         loss = C.c_float()
         _check(lib().dpps_mlp_train_step(self.h, batch.h, target.data_ptr(), target.stride(0), lr,
-                                         C.byref(loss), _stream_ptr(stream)))
+                                         pos_weight, ce_weight, tau, C.byref(loss),
+                                         _stream_ptr(stream)))
         return float(loss.value)
 
     def features(self, batch: "Batch", stream=None):
@@ -449,6 +455,19 @@ class Mlp:
         _check(lib().dpps_surrogate_search(self.s.h, self.h, batch.h, k, best.data_ptr(),
                                            int(fallback), C.byref(nfb), _stream_ptr(stream)))
         return best, int(nfb.value)
+
+
+def pool_cells(fine, fine_nx: int, fine_ny: int, coarse_nx: int = 61, coarse_ny: int = 46,
+               out=None, stream=None):
+    """Coarse-cell labels (device [n][coarse_ny*coarse_nx]) from fine score
+    maps (device f32, n * fine_ny * fine_nx elements)."""
+    import torch
+    n = fine.numel() // (fine_nx * fine_ny)
+    if out is None:
+        out = torch.empty((n, coarse_nx * coarse_ny), dtype=torch.float32, device=fine.device)
+    _check(lib().dpps_pool_cells(fine.data_ptr(), n, fine_nx, fine_ny, out.data_ptr(), coarse_nx,
+                                 coarse_ny, _stream_ptr(stream)))
+    return out
 
 
 def best_records(t) -> np.ndarray:

@@ -137,12 +137,18 @@ static int forward(dpps_mlp *m, const dpps_batch *bt, hipStream_t st)
     return DPPS_OK;
 }
 
-// gradients of the mean squared error against targets [nf][ld_t] (after forward)
-static int backward_mse(dpps_mlp *m, int nf, const float *tgt, int64_t ld_t, hipStream_t st)
+struct LossCfg {
+    float pos_weight, ce_weight, tau;
+};
+
+// gradients of the training loss against targets [nf][ld_t] (after forward)
+static int backward_loss(dpps_mlp *m, int nf, const float *tgt, int64_t ld_t, LossCfg lc,
+                         hipStream_t st)
 {
     const int R = rows_pad(nf);
-    if (launch_mse(m->y, OUT_PAD, tgt, (int)ld_t, nf, OUT, R, OUT_PAD, m->dz4, m->partial, (void *)st))
-        return fail(DPPS_E_DEVICE, "mse launch failed");
+    if (launch_loss(m->y, OUT_PAD, tgt, (int)ld_t, nf, OUT, R, OUT_PAD, lc.pos_weight, lc.ce_weight,
+                    lc.tau, m->dz4, m->partial, (void *)st))
+        return fail(DPPS_E_DEVICE, "loss launch failed");
     const uint16_t *dz_top = m->dz4;
     for (int l = NL - 1; l >= 0; --l) {
         const uint16_t *act = l == 0 ? m->x0 : m->a[l - 1];
@@ -181,16 +187,19 @@ static int backward_mse(dpps_mlp *m, int nf, const float *tgt, int64_t ld_t, hip
     return DPPS_OK;
 }
 
-static int read_loss(dpps_mlp *m, int nf, hipStream_t st, float *loss)
+static int read_loss(dpps_mlp *m, int nf, float ce_weight, hipStream_t st, float *loss)
 {
     if (!loss) return DPPS_OK;
     const int R = rows_pad(nf);
-    std::vector<float> part(R);
-    HIP_OK(hipMemcpyAsync(part.data(), m->partial, (size_t)R * 4, hipMemcpyDeviceToHost, st));
+    std::vector<float> part(2 * (size_t)R);
+    HIP_OK(hipMemcpyAsync(part.data(), m->partial, (size_t)R * 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    double s = 0.0;
-    for (int r = 0; r < nf; ++r) s += part[r];
-    *loss = (float)(s / ((double)nf * OUT));
+    double s = 0.0, e = 0.0;
+    for (int r = 0; r < nf; ++r) {
+        s += part[2 * r];
+        e += part[2 * r + 1];
+    }
+    *loss = (float)(s / ((double)nf * OUT) + ce_weight * e / nf);
     return DPPS_OK;
 }
 
@@ -235,7 +244,7 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
         odz[l] = carve(off, R * HID * 2);
     }
     size_t oy = carve(off, R * OUT_PAD * 4), odz4 = carve(off, R * OUT_PAD * 2);
-    size_t opart = carve(off, R * 4);
+    size_t opart = carve(off, R * 8);
     size_t ocells = carve(off, R * max_k * 4);
     size_t orf = carve(off, R * sizeof(FrameDev));
     size_t orw = carve(off, R * max_k * sizeof(WinDev));
@@ -380,18 +389,21 @@ int dpps_mlp_forward(dpps_mlp *m, dpps_batch *b, float *d_out, int64_t ld_out, v
 }
 
 int dpps_mlp_loss_grad(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
-                       float *loss, void *hip_stream)
+                       float pos_weight, float ce_weight, float tau, float *loss, void *hip_stream)
 {
     if (!m || !b || !d_target) return fail(DPPS_E_INVALID, "NULL argument");
+    if (!(pos_weight >= 0.0f) || !isfinite(pos_weight) || !(ce_weight >= 0.0f) ||
+        !isfinite(ce_weight) || !(tau > 0.0f) || !isfinite(tau))
+        return fail(DPPS_E_INVALID, "loss weights must be >= 0 and tau > 0");
     if (b->n_frames < 1) return fail(DPPS_E_INVALID, "empty batch");
     if (ld_target < OUT) return fail(DPPS_E_INVALID, "ld_target must be >= %d", OUT);
     HIP_OK(hipSetDevice(m->ctx->device));
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : m->ctx->stream;
     int rc = forward(m, b, st);
     if (rc) return rc;
-    rc = backward_mse(m, b->n_frames, d_target, ld_target, st);
+    rc = backward_loss(m, b->n_frames, d_target, ld_target, LossCfg{pos_weight, ce_weight, tau}, st);
     if (rc) return rc;
-    return read_loss(m, b->n_frames, st, loss);
+    return read_loss(m, b->n_frames, ce_weight, st, loss);
 }
 
 int dpps_mlp_adam(dpps_mlp *m, float lr, float beta1, float beta2, float eps, float weight_decay,
@@ -416,10 +428,24 @@ int dpps_mlp_adam(dpps_mlp *m, float lr, float beta1, float beta2, float eps, fl
     return DPPS_OK;
 }
 
-int dpps_mlp_train_step(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
-                        float lr, float *loss, void *hip_stream)
+int dpps_pool_cells(const float *d_fine, int32_t n_frames, int32_t fine_nx, int32_t fine_ny,
+                    float *d_coarse, int32_t coarse_nx, int32_t coarse_ny, void *hip_stream)
 {
-    int rc = dpps_mlp_loss_grad(m, b, d_target, ld_target, loss, hip_stream);
+    if (!d_fine || !d_coarse) return fail(DPPS_E_INVALID, "NULL argument");
+    if (n_frames < 0 || fine_nx < 1 || fine_ny < 1 || coarse_nx < 1 || coarse_ny < 1 ||
+        4 * (coarse_nx - 1) > fine_nx + 1 || 4 * (coarse_ny - 1) > fine_ny + 1)
+        return fail(DPPS_E_INVALID, "bad pooling shape");
+    if (launch_pool(d_fine, n_frames, fine_nx, fine_ny, d_coarse, coarse_nx, coarse_ny, hip_stream))
+        return fail(DPPS_E_DEVICE, "pool launch failed");
+    return DPPS_OK;
+}
+
+int dpps_mlp_train_step(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_t ld_target,
+                        float lr, float pos_weight, float ce_weight, float tau, float *loss,
+                        void *hip_stream)
+{
+    int rc = dpps_mlp_loss_grad(m, b, d_target, ld_target, pos_weight, ce_weight, tau, loss,
+                                hip_stream);
     if (rc) return rc;
     return dpps_mlp_adam(m, lr, 0.9f, 0.999f, 1e-8f, 0.0f, hip_stream);
 }

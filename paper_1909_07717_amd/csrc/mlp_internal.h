@@ -25,8 +25,11 @@ struct GemmArgs {
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream);
 int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st);
-int launch_mse(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
-               int outs_pad, uint16_t *dz, float *partial, void *st);
+int launch_loss(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
+                int outs_pad, float pos_weight, float ce_weight, float tau, uint16_t *dz,
+                float *partial, void *st);
+int launch_pool(const float *fine, int n_frames, int fnx, int fny, float *coarse, int cnx, int cny,
+                void *st);
 int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                 float eps, float c1, float c2, float wd, uint16_t *wb, uint16_t *wbt, int rows,
                 int cols, void *st);

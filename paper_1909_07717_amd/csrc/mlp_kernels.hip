@@ -192,36 +192,112 @@ __global__ void colsum_kernel(const uint16_t *__restrict__ dz, int M, int N, int
     db[n] = s;
 }
 
-// Mean squared error over the real outputs of the real rows.  Targets are
-// the exact search's score maps with infeasible cells (-inf) read as 0.
-// Writes dZ = 2 (y - t) / (rows * outs) as bf16 (zero in padding) and one
-// partial sum of squared errors per block.
-__global__ void mse_kernel(const float *__restrict__ y, int ldy, const float *__restrict__ tgt,
-                           int ldt, int rows, int outs, int rows_pad, int outs_pad,
-                           uint16_t *__restrict__ dz, float *__restrict__ partial)
+__device__ __forceinline__ float block_reduce(float v, float *red, bool is_max)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            red[threadIdx.x] = is_max ? fmaxf(red[threadIdx.x], red[threadIdx.x + s])
+                                      : red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
+    float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Training loss of one row (one block per row, 256 threads):
+//   sum_c w_c (y_c - t_c)^2 / (rows * outs)        weighted squared error,
+//   + ce_weight * CE(softmax(t / tau) || softmax(y / tau)) / rows
+// Targets are score maps with infeasible cells (-inf): read as 0 in the
+// squared error, excluded from the target distribution of the cross-entropy
+// (which ranks the best cells first).  w_c = 1 + pos_weight * t_c.  Writes
+// dZ as bf16 (zero in padding) and, per row, the squared-error sum and the
+// cross-entropy.
+__global__ void __launch_bounds__(256) loss_kernel(const float *__restrict__ y, int ldy,
+                                                   const float *__restrict__ tgt, int ldt, int rows,
+                                                   int outs, int rows_pad, int outs_pad,
+                                                   float pos_weight, float ce_weight, float tau,
+                                                   uint16_t *__restrict__ dz,
+                                                   float *__restrict__ partial)
 {
     __shared__ float red[256];
     const int r = blockIdx.x;
-    float acc = 0.0f;
+    const bool real = r < rows;
+    const float itau = 1.0f / tau;
+    float my = -INFINITY, mt = -INFINITY;
+    if (real && ce_weight > 0.0f) {
+        for (int n = threadIdx.x; n < outs; n += blockDim.x) {
+            float t = tgt[(size_t)r * ldt + n];
+            my = fmaxf(my, y[(size_t)r * ldy + n] * itau);
+            if (t > -INFINITY) mt = fmaxf(mt, t * itau);
+        }
+    }
+    my = block_reduce(my, red, true);
+    mt = block_reduce(mt, red, true);
+    const bool ce = real && ce_weight > 0.0f && mt > -INFINITY;
+    float sy = 0.0f, st = 0.0f;
+    if (ce) {
+        for (int n = threadIdx.x; n < outs; n += blockDim.x) {
+            float t = tgt[(size_t)r * ldt + n];
+            sy += expf(y[(size_t)r * ldy + n] * itau - my);
+            if (t > -INFINITY) st += expf(t * itau - mt);
+        }
+    }
+    sy = block_reduce(sy, red, false);
+    st = block_reduce(st, red, false);
+    const float lsy = ce ? logf(sy) : 0.0f;
     const float scale = 2.0f / ((float)rows * (float)outs);
+    const float cscale = ce_weight * itau / (float)rows;
+    float acc = 0.0f, ent = 0.0f;
     for (int n = threadIdx.x; n < outs_pad; n += blockDim.x) {
         float g = 0.0f;
-        if (r < rows && n < outs) {
-            float t = tgt[(size_t)r * ldt + n];
-            t = t > -INFINITY ? t : 0.0f;
-            float d = y[(size_t)r * ldy + n] - t;
-            acc += d * d;
-            g = scale * d;
+        if (real && n < outs) {
+            float traw = tgt[(size_t)r * ldt + n];
+            float t = traw > -INFINITY ? traw : 0.0f;
+            float yy = y[(size_t)r * ldy + n];
+            float wgt = 1.0f + pos_weight * t;
+            float d = yy - t;
+            acc += wgt * d * d;
+            g = scale * wgt * d;
+            if (ce) {
+                float lp = yy * itau - my - lsy;
+                float p = expf(lp);
+                float q = traw > -INFINITY ? expf(traw * itau - mt) / st : 0.0f;
+                ent -= q * lp;
+                g += cscale * (p - q);
+            }
         }
         dz[(size_t)r * outs_pad + n] = f2bf(g);
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+    acc = block_reduce(acc, red, false);
+    ent = block_reduce(ent, red, false);
+    if (threadIdx.x == 0 && r < rows_pad) {
+        partial[2 * r] = acc;
+        partial[2 * r + 1] = ent;
     }
-    if (threadIdx.x == 0 && r < rows_pad) partial[r] = red[0];
+}
+
+// Coarse-cell labels from a fine score map (one thread per coarse cell):
+// cell (ci, cj) takes the largest score of the fine points
+// {4 ci - 2 .. 4 ci + 1} x {4 cj - 2 .. 4 cj + 1} inside the fine lattice
+// (the points a re-score of that cell would visit); -inf if none is feasible.
+__global__ void pool_kernel(const float *__restrict__ fine, int n_frames, int fnx, int fny,
+                            float *__restrict__ coarse, int cnx, int cny)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)cnx * cny;
+    if (i >= per * n_frames) return;
+    const int f = (int)(i / per);
+    const int c = (int)(i - (int64_t)f * per);
+    const int ci = c % cnx, cj = c / cnx;
+    const float *src = fine + (size_t)f * fnx * fny;
+    float m = -INFINITY;
+    for (int J = max(4 * cj - 2, 0); J <= min(4 * cj + 1, fny - 1); ++J)
+        for (int I = max(4 * ci - 2, 0); I <= min(4 * ci + 1, fnx - 1); ++I)
+            m = fmaxf(m, src[(size_t)J * fnx + I]);
+    coarse[i] = m;
 }
 
 // Adam on one parameter tensor (f32 master), then refresh its bf16 copies:
@@ -423,11 +499,22 @@ int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_mse(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
-               int outs_pad, uint16_t *dz, float *partial, void *st)
+int launch_loss(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
+                int outs_pad, float pos_weight, float ce_weight, float tau, uint16_t *dz,
+                float *partial, void *st)
 {
-    hipLaunchKernelGGL(mse_kernel, dim3(rows_pad), dim3(256), 0, (hipStream_t)st, y, ldy, tgt, ldt,
-                       rows, outs, rows_pad, outs_pad, dz, partial);
+    hipLaunchKernelGGL(loss_kernel, dim3(rows_pad), dim3(256), 0, (hipStream_t)st, y, ldy, tgt, ldt,
+                       rows, outs, rows_pad, outs_pad, pos_weight, ce_weight, tau, dz, partial);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pool(const float *fine, int n_frames, int fnx, int fny, float *coarse, int cnx, int cny,
+                void *st)
+{
+    int64_t n = (int64_t)n_frames * cnx * cny;
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(pool_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)st, fine, n_frames, fnx, fny, coarse, cnx, cny);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -61,17 +61,30 @@ def load_checkpoint(path):
 
 
 def train(frames: int, batch: int, lr: float, out: str, resume: str | None = None,
-          log_every: int = 20, seed: int = 0):
+          log_every: int = 20, seed: int = 0, epochs: int = 1, pos_weight: float = 0.0,
+          ce_weight: float = 0.0, tau: float = 0.02, labels: str = "pooled"):
+    """`frames` distinct frames (frames // batch seeded batches) seen `epochs`
+    times, batch order reshuffled every epoch.
+
+    labels = "pooled": each 20 cm cell's label is the best exact score over
+    the 5 cm points its re-score would visit (exact search of the 5 cm
+    lattice, then dpps_pool_cells); "center": the exact score at the cell's
+    centre (the 20 cm search).  Labels are computed once per batch by the
+    exact kernel and kept in device memory for later epochs."""
     import torch
 
     from paper_1909_07717_amd import binding as B
-    from paper_1909_07717_amd.framegen import uniform_batch_arrays
+    from paper_1909_07717_amd.framegen import full_window, uniform_batch_arrays
 
     p = _params()
     windows, variants = _label_setup()
+    fine = [full_window(0.05)]
     s = B.Searcher(p)
     net = B.Mlp(s, batch, seed=seed)
-    steps = max(1, frames // batch)
+    n_batches = max(1, frames // batch)
+    order = np.concatenate([np.random.default_rng(seed + e).permutation(n_batches)
+                            for e in range(epochs)])
+    steps = len(order)
     start = 0
     if resume:
         ck = load_checkpoint(resume)
@@ -79,25 +92,43 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
         net.set_adam(ck["adam_m"], ck["adam_v"], int(ck["adam_step"]))
         start = int(ck["data_step"])
     st = torch.cuda.Stream()
+    cache = torch.empty((n_batches, batch, 2806), dtype=torch.float32, device=s.device)
+    have = np.zeros(n_batches, bool)
+    fine_out = None
     log = []
     t0 = time.time()
     for step in range(start, steps):
-        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + step, batch)
+        bi = int(order[step])
+        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi, batch)
         pk = B.pack_uniform(team, opp, passer, windows, variants, p)
         bt = s.batch(pk)
-        lab = s.outputs_for(pk, mask=False)
         with torch.cuda.stream(st):
-            bt.run(lab, stream=st)
+            if not have[bi]:
+                if labels == "pooled":
+                    pkf = B.pack_uniform(team, opp, passer, fine, variants, p)
+                    btf = s.batch(pkf)
+                    if fine_out is None:
+                        fine_out = s.outputs_for(pkf, mask=False)
+                    btf.run(fine_out, stream=st)
+                    B.pool_cells(fine_out.score, 241, 181, out=cache[bi], stream=st)
+                    st.synchronize()
+                    btf.close()
+                else:
+                    lab = s.outputs_for(pk, mask=False)
+                    bt.run(lab, stream=st)
+                    cache[bi].copy_(lab.score.view(batch, 2806))
+                have[bi] = True
             rate = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
-            loss = net.train_step(bt, lab.score.view(batch, 2806), rate, stream=st)
+            loss = net.train_step(bt, cache[bi], rate, pos_weight, ce_weight, tau, stream=st)
         bt.close()
         if step % log_every == 0 or step == steps - 1:
-            rec = {"step": step, "frames": (step + 1) * batch, "loss": loss, "lr": rate,
+            rec = {"step": step, "presented": (step + 1) * batch, "loss": loss, "lr": rate,
                    "elapsed_s": round(time.time() - t0, 2)}
             log.append(rec)
             print(json.dumps(rec), flush=True)
-    meta = {"frames": steps * batch, "batch": batch, "lr": lr, "steps": steps,
-            "train_seed": TRAIN_SEED, "log": log}
+    meta = {"frames": n_batches * batch, "epochs": epochs, "batch": batch, "lr": lr,
+            "pos_weight": pos_weight, "ce_weight": ce_weight, "tau": tau, "labels": labels,
+            "steps": steps, "train_seed": TRAIN_SEED, "log": log}
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     save_checkpoint(out, net, steps, meta)
     net.close()
@@ -179,6 +210,12 @@ def main():
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--out", default=WEIGHTS)
     t.add_argument("--resume", default=None)
+    t.add_argument("--epochs", type=int, default=1)
+    t.add_argument("--pos-weight", type=float, default=0.0)
+    t.add_argument("--ce-weight", type=float, default=0.0)
+    t.add_argument("--tau", type=float, default=0.02)
+    t.add_argument("--labels", choices=["pooled", "center"], default="pooled")
+    t.add_argument("--seed", type=int, default=0)
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--frames", type=int, default=2000)
@@ -186,7 +223,9 @@ def main():
     e.add_argument("--random", action="store_true")
     args = ap.parse_args()
     if args.cmd == "train":
-        train(args.frames, args.batch, args.lr, args.out, args.resume)
+        train(args.frames, args.batch, args.lr, args.out, args.resume, seed=args.seed,
+              epochs=args.epochs, pos_weight=args.pos_weight, ce_weight=args.ce_weight,
+              tau=args.tau, labels=args.labels)
     else:
         print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random)),
               flush=True)

@@ -65,9 +65,10 @@ def test_forward_loss_and_gradients(B):
     X = np.stack([M.features(f) for f in frames])
     Yref, _ = M.forward(w, X)
     e_fwd = _rel_l2(y, Yref)
-    loss = net.loss_grad(bt, T)
+    kw = dict(pos_weight=4.0, ce_weight=0.05, tau=0.05)
+    loss = net.loss_grad(bt, T, **kw)
     g = net.get_grads().astype(np.float64)
-    lref, gref = M.loss_and_grad(w, X, M.targets(T.cpu().numpy()))
+    lref, gref = M.loss_and_grad(w, X, T.cpu().numpy(), **kw)
     print(f"[mlp] forward rel L2 {e_fwd:.2e}, loss {loss:.6f} vs {lref:.6f}", flush=True)
     assert e_fwd <= 2e-2
     assert abs(loss - lref) <= 2e-2 * lref
@@ -87,6 +88,21 @@ def test_forward_loss_and_gradients(B):
     assert step == 1
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-6, atol=1e-12)
     bt.close(); net.close(); s.close()
+
+
+def test_pooled_labels(B):
+    s = B.Searcher(P)
+    frames = _frames(3, 400)
+    for f in frames:
+        f.windows = [full_window(0.05)]
+    bt = s.batch(frames)
+    out = s.outputs_for(bt.pk, mask=False)
+    bt.run(out)
+    c = B.pool_cells(out.score, 241, 181)
+    torch.cuda.synchronize()
+    want = M.pool(out.score.cpu().numpy())
+    assert np.array_equal(c.cpu().numpy().astype(np.float64), want)
+    bt.close(); s.close()
 
 
 def test_topk_matches_sort(B):

@@ -54,6 +54,53 @@ def test_gradient_matches_finite_differences():
         assert abs(g[i] - fd) <= 1e-6 * max(abs(fd), 1e-4), (i, g[i], fd)
 
 
+def test_weighted_and_ranking_loss_gradient_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    flat = _small_params(2)
+    X = rng.normal(0, 1, (2, M.IN))
+    T = rng.uniform(0.06, 1.0, (2, M.OUT))
+    T[rng.uniform(size=T.shape) < 0.7] = -np.inf
+    T[1, :] = -np.inf                       # a row with nothing feasible: no ranking term
+    kw = dict(pos_weight=6.0, ce_weight=0.05, tau=0.05)
+    _, g = M.loss_and_grad(flat, X, T, **kw)
+    h = 1e-6
+    for i in rng.choice(flat.size, 40, replace=False):
+        e = np.zeros_like(flat)
+        e[i] = h
+        fp = M.loss_and_grad(flat + e, X, T, **kw)[0]
+        fm = M.loss_and_grad(flat - e, X, T, **kw)[0]
+        fd = (fp - fm) / (2 * h)
+        # central-difference round-off is about eps * loss / h ~ 1e-10 here
+        assert abs(g[i] - fd) <= 1e-6 * abs(fd) + 2e-9, (i, g[i], fd)
+
+
+def test_cross_entropy_limits():
+    # identical scaled maps over the feasible cells: the loss is the entropy
+    # of the target, and its gradient vanishes when every cell is feasible
+    t = np.array([[0.1, 0.3, 0.2]])
+    ce, g = M.cross_entropy(t, t, 0.1)
+    p = np.exp(t / 0.1) / np.exp(t / 0.1).sum()
+    assert ce[0] == pytest.approx(-(p * np.log(p)).sum(), abs=1e-12)
+    np.testing.assert_allclose(g, 0.0, atol=1e-12)
+
+
+def test_pooling_takes_the_max_of_each_cells_fine_points():
+    rng = np.random.default_rng(5)
+    fine = rng.uniform(0, 1, (2, 181, 241))
+    fine[fine < 0.6] = -np.inf
+    c = M.pool(fine)
+    for (f, cj, ci) in [(0, 0, 0), (1, 45, 60), (0, 22, 30), (1, 10, 59)]:
+        pts = [fine[f, J, I] for J in range(4 * cj - 2, 4 * cj + 2) for I in range(4 * ci - 2, 4 * ci + 2)
+               if 0 <= J < 181 and 0 <= I < 241]
+        assert c[f, cj * 61 + ci] == max(pts)
+    # the fine windows of the 61 x 46 cells cover the fine lattice exactly once
+    cover = np.zeros((181, 241), int)
+    for cj in range(46):
+        for ci in range(61):
+            cover[max(4 * cj - 2, 0):min(4 * cj + 1, 180) + 1, max(4 * ci - 2, 0):min(4 * ci + 1, 240) + 1] += 1
+    assert (cover == 1).all()
+
+
 def test_adam_first_step_is_lr_times_sign():
     w = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -1e-3, 0.0])
