@@ -121,8 +121,40 @@ def batch_bench(n_frames: int, steps: int, tune_cache: str, st):
     return rec
 
 
+def surrogate_bench(frames: int, weights: str):
+    """Surrogate + top-64 exact re-score (5 cm) against the exact 5 cm search
+    on 6v6 frames with one flat pass at 4 m/s, K = 64 (the network's
+    training setting): regret, match and fallback rates, frames/s of both."""
+    if not os.path.exists(weights):
+        return {"note": f"no trained weights at {os.path.relpath(weights, ROOT)}"}
+    from paper_1909_07717_amd.surrogate import evaluate
+    res = evaluate(weights, frames, k=64, batch=min(frames, 1024))
+    res["speedup_vs_exact"] = res["surrogate_frames_per_s"] / res["exact_frames_per_s"]
+    return res
+
+
+def serving_bench(duration: float, weights: str):
+    """64 simulated matches at 60 Hz (mixed 20/10/5 cm grids, 4-16 flat
+    speeds, K = 128), continuous batching over 4 slots, exact and surrogate
+    paths one after the other."""
+    from paper_1909_07717_amd.serve import run_serving
+    out = {}
+    for kind in ("exact", "surrogate"):
+        if kind == "surrogate" and not os.path.exists(weights):
+            out[kind] = None
+            continue
+        st, _ = run_serving(kind, duration=duration, n_matches=64, slots=4, max_batch=64,
+                            weights=weights if kind == "surrogate" else None)
+        out[kind] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--surrogate-frames", type=int, default=1000)
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1909_07717_amd", "weights",
+                                                      "surrogate.npz"))
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
@@ -209,6 +241,8 @@ def main() -> int:
     batch = None
     if args.batch_frames > 0:
         batch = batch_bench(args.batch_frames, args.batch_steps, args.tune_cache, st)
+    sur = surrogate_bench(args.surrogate_frames, args.weights) if args.surrogate_frames > 0 else None
+    serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
 
     achieved = fl / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
@@ -236,7 +270,8 @@ def main() -> int:
                        "frames": int(lat.size), "path": "exact, dpps_search from host inputs"},
         "graph_ms_per_step": round(graph_ms, 5),
         "batch": batch,
-        "surrogate": None,
+        "surrogate": sur,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
     bt.close()
