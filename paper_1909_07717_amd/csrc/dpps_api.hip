@@ -86,6 +86,7 @@ DevParams derive(const dpps_params *p)
     P.A = p->amax;
     P.invA = (float)(1.0 / A);
     P.invV = (float)(1.0 / V);
+    P.Vh = (float)(V / sqrt(2.0));
     P.a_s = p->slide_decel;
     P.a_r = p->roll_decel;
     P.ratio = p->slide_ratio;

@@ -16,6 +16,7 @@ struct DevParams {
     float goal_x, half_goal_w, goal_eps, goal_xA;
     float RA;          // robot radius scaled by amax
     float V, A, invA, invV;
+    float Vh;          // vmax / sqrt(2): speed limit in the kernel's velocity units
     // ball model
     float a_s, a_r, ratio, cos_th, lam1_inv;  // lam1 = sin(2 th) / g  (carry = lam1 v0^2)
     // flat inversion: stopped / rolling / sliding regimes

@@ -49,6 +49,7 @@ struct StageLDS {
     int32_t type[MAX_VAR];
     VarConst vc[MAX_VAR];
     int32_t n_tm, n_op, n_var, has_flat, has_chip, frame;
+    int32_t vel_ok;           // every robot's speed is at most vmax
     float bx, by;
 };
 
@@ -124,7 +125,8 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
             slot = F.n_team - 1 + (tid - F.n_team);
         }
         if (tid != F.passer || tid >= F.n_team)
-            S.rob[slot] = make_float4(r.x * P.A, r.y * P.A, r.vx, r.vy);
+            S.rob[slot] = make_float4(r.x * P.A, r.y * P.A, r.vx * 0.70710678118654752f,
+                                      r.vy * 0.70710678118654752f);
     }
     if (tid < F.n_variants) {
         dpps_variant v = a.variants[F.variant_off + tid];
@@ -144,6 +146,12 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
         }
         S.has_flat = hf;
         S.has_chip = hc;
+        int ok = 1;
+        for (int r = 0; r < nrob; ++r) {
+            const dpps_robot R = a.robots[F.robot_off + r];
+            ok &= fmaf(R.vx, R.vx, R.vy * R.vy) <= P.V * P.V;
+        }
+        S.vel_ok = ok;
         S.frame = f;
         S.bx = F.ball_x;
         S.by = F.ball_y;
@@ -151,13 +159,17 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
 }
 
 // Arrival time of one robot at one sample, multiplied by amax.  Positions are
-// pre-scaled by amax (so distances d become A d); with that scaling the
-// time-optimal straight-line motion that ends at rest has
-//   A T = R(D') + sigma u,   R(D) = 2 min(sqrt D, V) + max(0, D - V^2) / V,
-// where u is the speed toward the point (clamped to +-V), s = u^2/2 the
-// scaled stopping distance, and either (overshoot: the robot cannot stop
-// before the point, or is already there at rest) D' = s - delta, sigma = +1,
-// or D' = s + delta, sigma = -1 (moving toward) / +1 (moving away).
+// pre-scaled by amax (so distances d become A d) and velocities by 1/sqrt(2);
+// with that scaling the time-optimal straight-line motion that ends at rest
+// has
+//   A T = R(D') + sigma sqrt(2) u',  R(D) = 2 min(sqrt D, V) + max(0, D - V^2) / V,
+// where u' is the (scaled) speed toward the point, s = u'^2 the scaled
+// stopping distance, and either (overshoot: the robot cannot stop before the
+// point, or is already there at rest) D' = s - delta, sigma = +1, or
+// D' = s + delta, sigma = -1 (moving toward) / +1 (moving away).  With CLAMP
+// the speed along the line is limited to vmax; without it the caller knows
+// every robot's speed is at most vmax, so the projection already is.
+template <bool CLAMP>
 __device__ __forceinline__ float robot_time_A(float4 r, float pxA, float pyA, const DevParams &P)
 {
     float dx = pxA - r.x;
@@ -168,16 +180,61 @@ __device__ __forceinline__ float robot_time_A(float4 r, float pxA, float pyA, co
     float inv = rsq(r2);
     float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
     float wd = fmaf(r.z, dx, r.w * dy);
-    float u = med3(wd * inv, -P.V, P.V);
-    float hu = 0.5f * u;
-    float st = hu * u;
-    float ss = hu * fabsf(u);
+    float u = wd * inv;
+    if (CLAMP) u = med3(u, -P.Vh, P.Vh);
+    float st = u * u;
+    float ss = u * fabsf(u);
     bool over = ss >= del;
     float Dp = st + (over ? -del : del);
     float sg = over ? u : -u;
     float vp = fminf(hsqrt(Dp), P.V);
     float cr = fmaxf(fmaf(Dp, P.invV, -P.V), 0.0f);
-    return fmaf(2.0f, vp, cr) + sg;
+    return fmaf(1.41421356237309505f, sg, fmaf(2.0f, vp, cr));
+}
+
+// Earliest arrival of robots [j0, j0 + n) at each of the lane's samples.
+template <int KPL, bool CLAMP>
+__device__ __forceinline__ void robot_stage(const StageLDS &S, const DevParams &P, int j0, int n,
+                                            const float (&pxA)[KPL], const float (&pyA)[KPL],
+                                            float (&T)[KPL])
+{
+    for (int j = j0; j < j0 + n; ++j) {
+        const float4 r = S.rob[j];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_A<CLAMP>(r, pxA[q], pyA[q], P));
+    }
+}
+
+// First crossing of every variant in `vm` (lane mask of variants of one kick
+// type, lane v holding variant v's speed in myv0): the lowest sample k whose
+// critical speed is at least v0, for the team (vt) and the opponents (vo);
+// K when there is none.  Sample groups are scanned in order and each side
+// stops at its first hit.  The results land on lane v.
+template <int KPL>
+__device__ __forceinline__ void first_crossings(unsigned long long vm, float myv0,
+                                                const float (&vt)[KPL], const float (&vo)[KPL],
+                                                int &my_kt, int &my_ko)
+{
+    const int l = lane_id();
+    const int K = KPL * 64;
+    for (unsigned long long m = vm; m; m &= m - 1) {
+        const int v = __builtin_ctzll(m);
+        const float v0 = readlane_f(myv0, v);
+        int kt = K, ko = K;
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+            if (kt == K) {
+                const unsigned long long mt = __ballot(v0 <= vt[q]);
+                if (mt) kt = q * 64 + __builtin_ctzll(mt);
+            }
+            if (ko == K) {
+                const unsigned long long mo = __ballot(v0 <= vo[q]);
+                if (mo) ko = q * 64 + __builtin_ctzll(mo);
+            }
+        }
+        my_kt = l == v ? kt : my_kt;
+        my_ko = l == v ? ko : my_ko;
+    }
 }
 
 // Kick speed at which the ball covers distance s in exactly time T (the
@@ -292,15 +349,12 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, in
         To[q] = INFINITY;
     }
     // 1. robot stage
-    for (int j = 0; j < n_tm; ++j) {
-        float4 r = S.rob[j];
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) Tt[q] = fminf(Tt[q], robot_time_A(r, pxA[q], pyA[q], P));
-    }
-    for (int j = 0; j < n_op; ++j) {
-        float4 r = S.rob[n_tm + j];
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) To[q] = fminf(To[q], robot_time_A(r, pxA[q], pyA[q], P));
+    if (uni(S.vel_ok)) {
+        robot_stage<KPL, false>(S, P, 0, n_tm, pxA, pyA, Tt);
+        robot_stage<KPL, false>(S, P, n_tm, n_op, pxA, pyA, To);
+    } else {
+        robot_stage<KPL, true>(S, P, 0, n_tm, pxA, pyA, Tt);
+        robot_stage<KPL, true>(S, P, n_tm, n_op, pxA, pyA, To);
     }
     // 2-3. critical kick speeds per sample, then the first crossing per
     // variant by ballot; the crossing of variant v lands on lane v
@@ -314,20 +368,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, in
             vo[q] = vcrit(To[q] * P.invA, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
                           P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
         }
-        for (unsigned long long m = flat_m; m; m &= m - 1) {
-            const int v = __builtin_ctzll(m);
-            const float v0 = readlane_f(myv0, v);
-            int kt = K, ko = K;
-#pragma unroll
-            for (int q = KPL - 1; q >= 0; --q) {
-                unsigned long long mt = __ballot(v0 <= vt[q]);
-                unsigned long long mo = __ballot(v0 <= vo[q]);
-                if (mt) kt = q * 64 + __builtin_ctzll(mt);
-                if (mo) ko = q * 64 + __builtin_ctzll(mo);
-            }
-            my_kt = l == v ? kt : my_kt;
-            my_ko = l == v ? ko : my_ko;
-        }
+        first_crossings<KPL>(flat_m, myv0, vt, vo, my_kt, my_ko);
     }
     if (chip_m) {
         float vt[KPL], vo[KPL];
@@ -339,20 +380,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, in
             vo[q] = fminf(vair, vcrit(To[q] * P.invA, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
                                       P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
         }
-        for (unsigned long long m = chip_m; m; m &= m - 1) {
-            const int v = __builtin_ctzll(m);
-            const float v0 = readlane_f(myv0, v);
-            int kt = K, ko = K;
-#pragma unroll
-            for (int q = KPL - 1; q >= 0; --q) {
-                unsigned long long mt = __ballot(v0 <= vt[q]);
-                unsigned long long mo = __ballot(v0 <= vo[q]);
-                if (mt) kt = q * 64 + __builtin_ctzll(mt);
-                if (mo) ko = q * 64 + __builtin_ctzll(mo);
-            }
-            my_kt = l == v ? kt : my_kt;
-            my_ko = l == v ? ko : my_ko;
-        }
+        first_crossings<KPL>(chip_m, myv0, vt, vo, my_kt, my_ko);
     }
     // open goal angle (lanes = opponents)
     const float ang = open_angle(S, P, cx, cy, n_op, n_tm);

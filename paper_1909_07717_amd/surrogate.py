@@ -5,10 +5,17 @@ library's own kernels).
     python3 -m paper_1909_07717_amd.surrogate eval --weights W.npz --frames 2000
 
 Training frames are 6 v 6 robot states drawn in batches (one generator per
-batch, seed = 1 000 000 + batch index); each frame's label is the exact
-search's 20 cm score map for one flat pass at 4 m/s with K = 64 samples,
-computed by the exact kernel on the same device.  Loss: mean squared error
-with infeasible cells as 0.  Optimiser: Adam with a cosine-decayed rate.
+batch, seed = 1 000 000 + batch index), one flat pass at 4 m/s with K = 64
+samples.  A frame's label is a 61 x 46 map over the 20 cm cells: by default
+("pooled") each cell holds the best exact score among the 5 cm points that
+the re-score of that cell visits, from the exact search of the whole 5 cm
+lattice on the same device; "center" labels take the exact 20 cm map
+instead.  Infeasible points count as score 0.  Loss: squared error weighted
+by (1 + pos_weight * label), plus ce_weight times the cross-entropy between
+the softmax of the labels and of the outputs at temperature tau (a listwise
+term that rewards ranking the best cells first).  Optimiser: Adam with a
+cosine-decayed rate.  Labels are computed once per batch and kept in device
+memory for later epochs.
 
 Evaluation compares, on frames from a disjoint seed range (20 000 000 + i),
 the surrogate search (top-k cells re-scored exactly at 5 cm, exact fallback)
