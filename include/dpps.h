@@ -206,8 +206,11 @@ int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs);
 
 /* ---- learned surrogate ---------------------------------------------------
  * A multilayer perceptron 66 -> 512 -> 512 -> 512 -> 2806 (GELU) predicts a
- * frame's exact score map on the 20 cm lattice of the 12 m x 9 m field
- * (61 x 46 cells, infeasible cells as 0) from its robots and ball: team with
+ * coarse map of a frame over the 20 cm cells of the 12 m x 9 m field
+ * (61 x 46 cells; what it is trained towards is the caller's choice, e.g.
+ * the exact score at each cell, or the best exact score among the 5 cm
+ * points a re-score of the cell visits (dpps_pool_cells); infeasible as 0)
+ * from its robots and ball: team with
  * the passer first and the rest by distance to the ball, 8 slots; opponents
  * by distance to the ball, 8 slots; each (x / 6, y / 4.5, vx / vmax,
  * vy / vmax), missing slots zero; then the ball (x / 6, y / 4.5).  Weights

@@ -1,8 +1,10 @@
 // mlp_kernels.hip -- kernels of the learned surrogate (gfx950).
 //
 // The surrogate is a multilayer perceptron 66 -> 512 -> 512 -> 512 -> 2806
-// with GELU activations that predicts the exact search's 20 cm score map of
-// a frame; its top-64 cells are then re-scored exactly at 5 cm.  Weights and
+// with GELU activations that predicts a coarse 61 x 46 map of a frame: for
+// each 20 cm cell, the best exact score among the 5 cm points that a
+// re-score of that cell visits.  Its top-64 cells are then re-scored exactly
+// at 5 cm.  Weights and
 // activations are bfloat16, products accumulate in float32 on the matrix
 // cores (v_mfma_f32_16x16x32_bf16); biases, pre-activations, gradients and
 // the Adam state are float32.

@@ -52,11 +52,17 @@ def _label_setup():
     return [full_window(0.2)], variants_for([4.0], flat=True, chip=False)
 
 
-def save_checkpoint(path, net, step: int, extra: dict):
-    m, v, st = net.get_adam()
+def save_checkpoint(path, net, step: int, extra: dict, params_only: bool = False):
+    """Parameters, Adam state and data position (for resume); with
+    params_only, the parameters and the metadata alone (8 MB)."""
     tmp = path + ".tmp.npz"
-    np.savez(tmp, params=net.get_params(), adam_m=m, adam_v=v, adam_step=np.int64(st),
-             data_step=np.int64(step), meta=np.frombuffer(json.dumps(extra).encode(), np.uint8))
+    meta = np.frombuffer(json.dumps(extra).encode(), np.uint8)
+    if params_only:
+        np.savez(tmp, params=net.get_params(), data_step=np.int64(step), meta=meta)
+    else:
+        m, v, st = net.get_adam()
+        np.savez(tmp, params=net.get_params(), adam_m=m, adam_v=v, adam_step=np.int64(st),
+                 data_step=np.int64(step), meta=meta)
     os.replace(tmp, path)
 
 
@@ -69,7 +75,8 @@ def load_checkpoint(path):
 
 def train(frames: int, batch: int, lr: float, out: str, resume: str | None = None,
           log_every: int = 20, seed: int = 0, epochs: int = 1, pos_weight: float = 0.0,
-          ce_weight: float = 0.0, tau: float = 0.02, labels: str = "pooled"):
+          ce_weight: float = 0.0, tau: float = 0.02, labels: str = "pooled",
+          params_only: bool = False):
     """`frames` distinct frames (frames // batch seeded batches) seen `epochs`
     times, batch order reshuffled every epoch.
 
@@ -137,15 +144,20 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
             "pos_weight": pos_weight, "ce_weight": ce_weight, "tau": tau, "labels": labels,
             "steps": steps, "train_seed": TRAIN_SEED, "log": log}
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
-    save_checkpoint(out, net, steps, meta)
+    save_checkpoint(out, net, steps, meta, params_only)
     net.close()
     s.close()
     return log
 
 
 def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, random_net=False,
-             seed0: int = EVAL_SEED):
-    """Regret statistics of the surrogate search against the exact 5 cm search."""
+             seed0: int = EVAL_SEED, dump: str | None = None):
+    """Regret statistics of the surrogate search against the exact 5 cm search.
+
+    With `dump`, also writes per-frame arrays (npz): the exact best score,
+    the surrogate's best re-scored score before any fallback (-inf when no
+    proposal is feasible), and the network's largest and k-th largest
+    predicted cell values."""
     import torch
 
     from paper_1909_07717_amd import binding as B
@@ -159,6 +171,7 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
     if weights and not random_net:
         net.set_params(load_checkpoint(weights)["params"])
     regrets, match, fallbacks, found_both, none_exact = [], 0, 0, 0, 0
+    rows = []
     t_exact = t_sur = 0.0
     n_done = 0
     bi = 0
@@ -181,6 +194,15 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
         be = ex.best_host()
         bs = B.best_records(sb)
         fallbacks += nfb
+        if dump:
+            raw, _ = net.search(bt, k=k, fallback=False)
+            br = B.best_records(raw)
+            y = net.forward(bt)
+            top = torch.topk(y, k, dim=1).values.cpu().numpy()
+            rows.append(np.stack([
+                np.where(be["found"] != 0, be["score"], -np.inf),
+                np.where(br["found"] != 0, br["score"], -np.inf),
+                top[:, 0], top[:, k - 1]], 1).astype(np.float64))
         for i in range(n):
             if not be[i]["found"]:
                 none_exact += 1
@@ -203,6 +225,9 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
            "no_feasible_exact": none_exact,
            "exact_frames_per_s": frames / t_exact, "surrogate_frames_per_s": frames / t_sur,
            "network": "random init" if (random_net or not weights) else os.path.basename(weights)}
+    if dump:
+        a = np.concatenate(rows, 0)
+        np.savez(dump, exact=a[:, 0], raw=a[:, 1], pred_top=a[:, 2], pred_kth=a[:, 3])
     net.close()
     s.close()
     return res
@@ -223,19 +248,21 @@ def main():
     t.add_argument("--tau", type=float, default=0.02)
     t.add_argument("--labels", choices=["pooled", "center"], default="pooled")
     t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--params-only", action="store_true")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--frames", type=int, default=2000)
     e.add_argument("--k", type=int, default=64)
     e.add_argument("--random", action="store_true")
+    e.add_argument("--dump", default=None)
     args = ap.parse_args()
     if args.cmd == "train":
         train(args.frames, args.batch, args.lr, args.out, args.resume, seed=args.seed,
               epochs=args.epochs, pos_weight=args.pos_weight, ce_weight=args.ce_weight,
-              tau=args.tau, labels=args.labels)
+              tau=args.tau, labels=args.labels, params_only=args.params_only)
     else:
-        print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random)),
-              flush=True)
+        print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random,
+                                  dump=args.dump)), flush=True)
 
 
 if __name__ == "__main__":
