@@ -272,11 +272,24 @@ int dpps_mlp_features(dpps_mlp *m, dpps_batch *b, uint16_t *d_x, void *hip_strea
 int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, void *hip_stream);
 /* Surrogate search: forward, top-k cells, exact re-score of their 5 cm points
  * with the frame's variants; best pass per frame into d_best (device).  With
- * fallback != 0, frames where no proposed point is feasible are searched
- * exactly on the whole 5 cm lattice (synchronous) and *n_fallback counts
- * them.  The batch's own windows are not used. */
+ * fallback != 0, frames where no proposed point is feasible, or whose best
+ * re-scored pass scores below fallback_below (-INFINITY: infeasible frames
+ * only), are searched exactly on the whole 5 cm lattice (synchronous) and
+ * *n_fallback counts them.  The batch's own windows are not used.  A NaN
+ * fallback_below is DPPS_E_INVALID. */
 int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
-                          int fallback, int32_t *n_fallback, void *hip_stream);
+                          int fallback, float fallback_below, int32_t *n_fallback,
+                          void *hip_stream);
+/* The same from host frames (layout as for dpps_search_batch; the windows are
+ * validated but not searched): the tables go through the context's pinned
+ * staging into device memory the context keeps, so a steady stream of
+ * requests allocates nothing.  n_frames must not exceed the network's
+ * max_frames. */
+int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
+                                 const dpps_frame *frames, const dpps_robot *robots,
+                                 const dpps_window *windows, const dpps_variant *variants,
+                                 int32_t k, dpps_best *d_best, int fallback, float fallback_below,
+                                 int32_t *n_fallback, void *hip_stream);
 
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);

@@ -109,7 +109,10 @@ def lib():
         L.dpps_mlp_train_step.argtypes = [vp, vp, vp, i64, f32, f32, f32, f32, pf, vp]
         L.dpps_mlp_features.argtypes = [vp, vp, vp, vp]
         L.dpps_mlp_topk.argtypes = [vp, i32, i32, vp, vp]
-        L.dpps_surrogate_search.argtypes = [vp, vp, vp, i32, vp, C.c_int, C.POINTER(i32), vp]
+        L.dpps_surrogate_search.argtypes = [vp, vp, vp, i32, vp, C.c_int, C.c_float,
+                                            C.POINTER(i32), vp]
+        L.dpps_surrogate_search_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp, i32, vp, C.c_int,
+                                                   C.c_float, C.POINTER(i32), vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
         L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
@@ -445,15 +448,36 @@ class Mlp:
         _check(lib().dpps_mlp_topk(self.h, n_frames, k, out.data_ptr(), _stream_ptr(stream)))
         return out
 
-    def search(self, batch: "Batch", k: int = 64, fallback: bool = True, best=None, stream=None):
-        """Surrogate search; returns (best records on device as bytes tensor, fallbacks)."""
+    def search(self, batch: "Batch", k: int = 64, fallback: bool = True, best=None, stream=None,
+               fallback_below: float = float("-inf")):
+        """Surrogate search; returns (best records on device as bytes tensor, fallbacks).
+        With fallback, frames with no feasible proposal or a best re-scored
+        score below `fallback_below` are searched exactly."""
         import torch
         nf = len(batch.pk.frames)
         if best is None:
             best = torch.empty(nf * BEST_DT.itemsize, dtype=torch.uint8, device=self.s.device)
         nfb = C.c_int32()
         _check(lib().dpps_surrogate_search(self.s.h, self.h, batch.h, k, best.data_ptr(),
-                                           int(fallback), C.byref(nfb), _stream_ptr(stream)))
+                                           int(fallback), float(fallback_below), C.byref(nfb),
+                                           _stream_ptr(stream)))
+        return best, int(nfb.value)
+
+    def search_frames(self, frames, k: int = 64, fallback: bool = True, best=None, stream=None,
+                      fallback_below: float = float("-inf")):
+        """Surrogate search of host frames (a Packed request or framegen
+        frames) through the context's own staging; same results as search()
+        on a batch of the same frames."""
+        import torch
+        pk = frames if isinstance(frames, Packed) else pack(frames, self.s.params)
+        nf = len(pk.frames)
+        if best is None:
+            best = torch.empty(nf * BEST_DT.itemsize, dtype=torch.uint8, device=self.s.device)
+        nfb = C.c_int32()
+        _check(lib().dpps_surrogate_search_frames(
+            self.s.h, self.h, nf, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
+            _ptr(pk.variants), k, best.data_ptr(), int(fallback), float(fallback_below),
+            C.byref(nfb), _stream_ptr(stream)))
         return best, int(nfb.value)
 
 
@@ -479,9 +503,11 @@ def pack_uniform(team: np.ndarray, opp: np.ndarray, passer: np.ndarray, windows,
                  out_flags: int = 0) -> Packed:
     """Vectorised pack of frames that share robot counts, windows and
     variants (team [n, nt, 4], opp [n, no, 4], passer [n]); the ball sits on
-    the passer."""
+    the passer.  `windows` is a list shared by every frame, or an array
+    [n, nw, 5] of (h, i0, j0, nx, ny) per frame."""
     n, nt, no = team.shape[0], team.shape[1], opp.shape[1]
-    nw, nv = len(windows), len(variants)
+    per_frame = isinstance(windows, np.ndarray) and windows.ndim == 3
+    nw, nv = (windows.shape[1] if per_frame else len(windows)), len(variants)
     fr = np.zeros(n, FRAME_DT)
     idx = np.arange(n)
     fr["n_team"], fr["n_opp"], fr["passer"] = nt, no, passer
@@ -493,7 +519,14 @@ def pack_uniform(team: np.ndarray, opp: np.ndarray, passer: np.ndarray, windows,
     r = np.concatenate([team, opp], axis=1).reshape(-1, 4).astype(np.float32)
     robots = np.zeros(r.shape[0], ROBOT_DT)
     robots["x"], robots["y"], robots["vx"], robots["vy"] = r[:, 0], r[:, 1], r[:, 2], r[:, 3]
-    win = np.array([tuple(w) for w in windows] * n, WINDOW_DT)
+    if per_frame:
+        wa = windows.reshape(-1, 5)
+        win = np.zeros(wa.shape[0], WINDOW_DT)
+        win["h"] = wa[:, 0]
+        for c, name in enumerate(("i0", "j0", "nx", "ny")):
+            win[name] = wa[:, c + 1].astype(np.int32)
+    else:
+        win = np.array([tuple(w) for w in windows] * n, WINDOW_DT)
     var = np.array([(int(v[0]), float(v[1])) for v in variants] * n, VARIANT_DT)
     total = C.c_int64()
     pc = params_c(p, out_flags)

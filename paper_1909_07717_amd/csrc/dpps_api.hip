@@ -80,13 +80,16 @@ DevParams derive(const dpps_params *p)
     P.goal_x = p->goal_x;
     P.half_goal_w = 0.5f * p->goal_width;
     P.goal_eps = p->goal_eps;
-    P.goal_xA = (float)(p->goal_x * A);
+    P.R = p->robot_radius;
     P.RA = (float)(p->robot_radius * A);
     P.V = p->vmax;
     P.A = p->amax;
-    P.invA = (float)(1.0 / A);
     P.invV = (float)(1.0 / V);
     P.Vh = (float)(V / sqrt(2.0));
+    P.V2 = (float)(V * V);
+    P.inv2V = (float)(0.5 / V);
+    P.halfV = (float)(0.5 * V);
+    P.invA2 = (float)(2.0 / A);
     P.a_s = p->slide_decel;
     P.a_r = p->roll_decel;
     P.ratio = p->slide_ratio;
@@ -455,6 +458,7 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
     c->P = derive(p);
     c->device = device;
     c->scratch.ctx = c;
+    c->fallback.ctx = c;
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return fail(DPPS_E_DEVICE, "hipSetDevice(%d) failed", device);
@@ -498,6 +502,7 @@ void dpps_destroy(dpps_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     ring_free(c);
     batch_free_device(&c->scratch);
+    batch_free_device(&c->fallback);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staged) (void)hipEventDestroy(c->staged);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -571,21 +576,22 @@ int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_
     return DPPS_OK;
 }
 
-int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
-                      const dpps_robot *robots, const dpps_window *windows,
-                      const dpps_variant *variants, const dpps_outputs *out, void *hip_stream)
+}  // extern "C"
+
+// Validate host frames and copy their tables into a batch the context owns
+// (c->scratch or c->fallback), through the pinned staging buffer and an
+// asynchronous copy on st; device memory grows only when a request is larger
+// than any before.
+int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *frames,
+                const dpps_robot *robots, const dpps_window *windows,
+                const dpps_variant *variants, hipStream_t st)
 {
-    if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
-    if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
-    HIP_OK(hipSetDevice(c->device));
-    dpps_batch *b = &c->scratch;
     int rc = build_tables(&c->p, n_frames, frames, robots, windows, variants, c->tile_points, b->T);
     if (rc) return rc;
     b->n_frames = n_frames;
     b->tile_points = c->tile_points;
     graph_drop(b);
     Layout L = table_layout(b->T);
-    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
     // the previous call's copy must have left the pinned buffer
     HIP_OK(hipEventSynchronize(c->staged));
     if (L.total > c->pinned_cap) {
@@ -603,7 +609,22 @@ int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     pack_tables(b->T, L, (char *)c->pinned);
     HIP_OK(hipMemcpyAsync(b->arena.ptr, c->pinned, L.total, hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(c->staged, st));
-    return run_batch(c, b, out, st, true);
+    return DPPS_OK;
+}
+
+extern "C" {
+
+int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_variant *variants, const dpps_outputs *out, void *hip_stream)
+{
+    if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");
+    if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    int rc = stage_batch(c, &c->scratch, n_frames, frames, robots, windows, variants, st);
+    if (rc) return rc;
+    return run_batch(c, &c->scratch, out, st, true);
 }
 
 int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,

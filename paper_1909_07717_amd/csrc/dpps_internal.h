@@ -13,10 +13,12 @@ namespace dpps {
 // coefficients that invert the ball model for the critical kick speed.
 struct DevParams {
     // geometry
-    float goal_x, half_goal_w, goal_eps, goal_xA;
-    float RA;          // robot radius scaled by amax
-    float V, A, invA, invV;
+    float goal_x, half_goal_w, goal_eps;
+    float R, RA;       // robot radius, and scaled by amax
+    float V, A, invV;
     float Vh;          // vmax / sqrt(2): speed limit in the kernel's velocity units
+    float V2, inv2V, halfV;  // vmax^2, 1 / (2 vmax), vmax / 2
+    float invA2;       // 2 / amax: robot stage units (A T / 2) to seconds
     // ball model
     float a_s, a_r, ratio, cos_th, lam1_inv;  // lam1 = sin(2 th) / g  (carry = lam1 v0^2)
     // flat inversion: stopped / rolling / sliding regimes

@@ -44,9 +44,10 @@ struct VarConst {
 };
 
 struct StageLDS {
-    float4 rob[MAX_ROB];      // (x A, y A, vx, vy): team interceptors, then opponents
+    float4 rob[MAX_ROB];      // (x, y, vx, vy): team interceptors, then opponents
     float v0[MAX_VAR];
     int32_t type[MAX_VAR];
+    int32_t vidx[MAX_VAR];    // the caller's index of each staged variant
     VarConst vc[MAX_VAR];
     int32_t n_tm, n_op, n_var, has_flat, has_chip, frame;
     int32_t vel_ok;           // every robot's speed is at most vmax
@@ -124,15 +125,22 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
         } else {
             slot = F.n_team - 1 + (tid - F.n_team);
         }
-        if (tid != F.passer || tid >= F.n_team)
-            S.rob[slot] = make_float4(r.x * P.A, r.y * P.A, r.vx * 0.70710678118654752f,
-                                      r.vy * 0.70710678118654752f);
+        if (tid != F.passer || tid >= F.n_team) S.rob[slot] = make_float4(r.x, r.y, r.vx, r.vy);
     }
     if (tid < F.n_variants) {
-        dpps_variant v = a.variants[F.variant_off + tid];
-        S.v0[tid] = v.v0;
-        S.type[tid] = v.type;
-        S.vc[tid] = var_const(P, v.type, v.v0);
+        // staged in order of kick type, then speed (stable): within a type
+        // the first crossing never moves earlier as the speed grows
+        const dpps_variant v = a.variants[F.variant_off + tid];
+        int rank = 0;
+        for (int j = 0; j < F.n_variants; ++j) {
+            const dpps_variant u = a.variants[F.variant_off + j];
+            rank += u.type < v.type ||
+                    (u.type == v.type && (u.v0 < v.v0 || (u.v0 == v.v0 && j < tid)));
+        }
+        S.v0[rank] = v.v0;
+        S.type[rank] = v.type;
+        S.vidx[rank] = tid;
+        S.vc[rank] = var_const(P, v.type, v.v0);
     }
     if (tid == 0) {
         S.n_tm = F.n_team - 1;
@@ -158,82 +166,130 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
     }
 }
 
-// Arrival time of one robot at one sample, multiplied by amax.  Positions are
-// pre-scaled by amax (so distances d become A d) and velocities by 1/sqrt(2);
-// with that scaling the time-optimal straight-line motion that ends at rest
-// has
-//   A T = R(D') + sigma sqrt(2) u',  R(D) = 2 min(sqrt D, V) + max(0, D - V^2) / V,
+// Arrival time of one robot at one sample.  Lengths are scaled by amax (a
+// distance d becomes A d) and speeds by 1/sqrt(2); with that scaling the
+// time-optimal straight-line motion that ends at rest takes
+//   A T = R(D') + sigma sqrt(2) u',
+//   R(D) = 2 sqrt(D) if D <= V^2, else D / V + V (cruising at vmax = V),
 // where u' is the (scaled) speed toward the point, s = u'^2 the scaled
-// stopping distance, and either (overshoot: the robot cannot stop before the
-// point, or is already there at rest) D' = s - delta, sigma = +1, or
-// D' = s + delta, sigma = -1 (moving toward) / +1 (moving away).  With CLAMP
-// the speed along the line is limited to vmax; without it the caller knows
-// every robot's speed is at most vmax, so the projection already is.
+// stopping distance, delta the scaled distance still to cover, and either
+// (overshoot: the robot cannot stop before the point, or is already there at
+// rest) D' = s - delta, sigma = +1, or D' = s + delta, sigma = -1 (moving
+// toward) / +1 (moving away).  The function returns A T / 2.
+//
+// The sample and the robot are given in the path frame of the candidate
+// point: the sample lies at distance fq * LA along the path from the ball;
+// r = (t, q^2, w.e, q w.n) holds the robot's own coordinate along the path
+// (t) and across it (q), and its scaled velocity w projected on the path
+// direction e and on the normal n.  The offset from the robot to the sample
+// is then h e + q n with h = fq LA - t, its length sqrt(h^2 + q^2), and the
+// speed toward the sample (h w.e + q w.n) / length.  With CLAMP that speed is
+// limited to vmax; without it the caller knows that no robot is faster.
 template <bool CLAMP>
-__device__ __forceinline__ float robot_time_A(float4 r, float pxA, float pyA, const DevParams &P)
+__device__ __forceinline__ float robot_time_h(float4 r, float fq, float LA, const DevParams &P)
 {
-    float dx = pxA - r.x;
-    float dy = pyA - r.y;
-    // the tiny bias keeps rsq finite on the robot's own position; it is below
-    // the resolution of any non-zero squared distance
-    float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
-    float inv = rsq(r2);
-    float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
-    float wd = fmaf(r.z, dx, r.w * dy);
-    float u = wd * inv;
+    const float h = fmaf(fq, LA, -r.x);
+    const float r2 = fmaf(h, h, r.y);
+    const float inv = rsq(r2);
+    const float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
+    float u = fmaf(h, r.z, r.w) * inv;
     if (CLAMP) u = med3(u, -P.Vh, P.Vh);
-    float st = u * u;
-    float ss = u * fabsf(u);
-    bool over = ss >= del;
-    float Dp = st + (over ? -del : del);
-    float sg = over ? u : -u;
-    float vp = fminf(hsqrt(Dp), P.V);
-    float cr = fmaxf(fmaf(Dp, P.invV, -P.V), 0.0f);
-    return fmaf(1.41421356237309505f, sg, fmaf(2.0f, vp, cr));
+    const float st = u * u;
+    const float ss = u * fabsf(u);
+    const bool over = ss >= del;
+    const float Dp = st + (over ? -del : del);
+    const float sg = over ? u : -u;
+    const float rh = Dp > P.V2 ? fmaf(Dp, P.inv2V, P.halfV) : hsqrt(Dp);
+    return fmaf(sg, 0.70710678118654752f, rh);
 }
 
-// Earliest arrival of robots [j0, j0 + n) at each of the lane's samples.
+// Earliest arrival (A T / 2) of robots [j0, j0 + n) of the point's path
+// frame `pr` at each of the lane's samples.
 template <int KPL, bool CLAMP>
-__device__ __forceinline__ void robot_stage(const StageLDS &S, const DevParams &P, int j0, int n,
-                                            const float (&pxA)[KPL], const float (&pyA)[KPL],
-                                            float (&T)[KPL])
+__device__ __forceinline__ void robot_stage(const float4 *pr, const DevParams &P, int j0, int n,
+                                            const float (&fs)[KPL], float LA, float (&T)[KPL])
 {
     for (int j = j0; j < j0 + n; ++j) {
-        const float4 r = S.rob[j];
+        const float4 r = pr[j];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_A<CLAMP>(r, pxA[q], pyA[q], P));
+        for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_h<CLAMP>(r, fs[q], LA, P));
     }
 }
 
-// First crossing of every variant in `vm` (lane mask of variants of one kick
-// type, lane v holding variant v's speed in myv0): the lowest sample k whose
-// critical speed is at least v0, for the team (vt) and the opponents (vo);
-// K when there is none.  Sample groups are scanned in order and each side
-// stops at its first hit.  The results land on lane v.
+// Path frame of candidate point c for the staged robots (lanes = robots),
+// in float64 and then rounded once: for robot j with offset a = ball - x_j,
+// path direction e = (c - ball) / |c - ball| and normal n = (-e_y, e_x):
+// t = -a.e and q = a.n (scaled by amax), w = velocity / sqrt(2), and pr[j] =
+// (t, q^2, w.e, q w.n).  A point on the ball gets e = (1, 0); it is never
+// reachable.  1 / |c - ball| is the hardware estimate refined by one Newton
+// step (relative error far below the float32 rounding that follows).
+// Returns |c - ball| A.
+__device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &P, float4 *pr,
+                                            int n_rob, double cx64, double cy64, double bx,
+                                            double by)
+{
+    const int l = lane_id();
+    const double ex = cx64 - bx, ey = cy64 - by;
+    const double L2 = ex * ex + ey * ey;
+    double iL = __builtin_amdgcn_rsq(L2);
+    iL = iL * (1.5 - 0.5 * L2 * iL * iL);
+    const bool pos = L2 > 0.0;
+    const double L = pos ? L2 * iL : 0.0;
+    const double ux = pos ? ex * iL : 1.0, uy = pos ? ey * iL : 0.0;
+    if (l < n_rob) {
+        const float4 r = S.rob[l];
+        const double A = (double)P.A;
+        const double ax = bx - (double)r.x, ay = by - (double)r.y;
+        const double t = -(ax * ux + ay * uy) * A;
+        const double q = (ay * ux - ax * uy) * A;
+        const double we = ((double)r.z * ux + (double)r.w * uy) * 0.70710678118654752;
+        const double wn = ((double)r.w * ux - (double)r.z * uy) * 0.70710678118654752;
+        pr[l] = make_float4((float)t, (float)(q * q + 1e-30), (float)we, (float)(q * wn));
+    }
+    // the row is written and read by this wave only
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return (float)(L * (double)P.A);
+}
+
+// First crossing of every variant in `vm` (lane mask of the variants of one
+// kick type, staged by increasing speed; lane v holds variant v's speed in
+// myv0): the lowest sample k whose critical speed is at least v0, for the
+// team (vt) and the opponents (vo); K when there is none.  Sample groups are
+// scanned in order and each side stops at its first hit.  A faster kick
+// never crosses earlier (every sample it passes, a slower kick passes too),
+// so each variant's scan starts at the group where the previous one crossed.
+// Lane 0 stores kt | ko << 16 into xr[v] (this wave's row).
 template <int KPL>
 __device__ __forceinline__ void first_crossings(unsigned long long vm, float myv0,
                                                 const float (&vt)[KPL], const float (&vo)[KPL],
-                                                int &my_kt, int &my_ko)
+                                                uint32_t *xr)
 {
-    const int l = lane_id();
     const int K = KPL * 64;
+    const bool lead = lane_id() == 0;
+    int qt = 0, qo = 0;  // group where the previous variant crossed (KPL: none)
     for (unsigned long long m = vm; m; m &= m - 1) {
         const int v = __builtin_ctzll(m);
         const float v0 = readlane_f(myv0, v);
         int kt = K, ko = K;
+        int gt = qt, go = qo;  // next group to scan (KPL: done)
 #pragma unroll
         for (int q = 0; q < KPL; ++q) {
-            if (kt == K) {
+            if (gt == q) {
                 const unsigned long long mt = __ballot(v0 <= vt[q]);
-                if (mt) kt = q * 64 + __builtin_ctzll(mt);
+                kt = mt ? q * 64 + __builtin_ctzll(mt) : K;
+                gt = mt ? KPL : q + 1;
             }
-            if (ko == K) {
+            if (go == q) {
                 const unsigned long long mo = __ballot(v0 <= vo[q]);
-                if (mo) ko = q * 64 + __builtin_ctzll(mo);
+                ko = mo ? q * 64 + __builtin_ctzll(mo) : K;
+                go = mo ? KPL : q + 1;
             }
         }
-        my_kt = l == v ? kt : my_kt;
-        my_ko = l == v ? ko : my_ko;
+        qt = kt >> 6;
+        qo = ko >> 6;
+        if (lead) xr[v] = (uint32_t)kt | ((uint32_t)ko << 16);
     }
 }
 
@@ -242,19 +298,61 @@ __device__ __forceinline__ void first_crossings(unsigned long long vm, float myv
 // time T: stopped (s <= cA T^2), decelerating at the slower rate
 // (quadratic in v0), or still in the fast phase (s >= cB T^2: sliding for a
 // flat kick, in the air for a chip).  Each root is written N / (Pp + sqrt M).
+// In the fast phase a flat kick slides (N = s + hfast T^2, Pp = T) and a
+// chip flies (N = s, Pp = pfast T).  T must be finite (a side with no robot
+// has no crossing; the caller skips it).  Every regime's terms are formed
+// first and then picked by plain selects, so that the lanes of a wave
+// (samples in different regimes) do not split into branches.
+template <bool CHIP>
 __device__ __forceinline__ float vcrit(float T, float s, float cD, float cA, float cB,
                                        float alpha4, float beta, float beta2, float hfast,
                                        float pfast, float half_ar)
 {
-    float T2 = T * T;
-    float Q = fmaf(half_ar, T2, s);
-    bool stop = s <= cA * T2;
-    bool fast = s >= cB * T2;
-    float N = stop ? s : (fast ? fmaf(hfast, T2, s) : 2.0f * Q);
-    float Pp = stop ? 0.0f : (fast ? pfast * T : beta * T);
-    float M = stop ? s * cD : (fast ? 0.0f : fmaf(alpha4, Q, beta2 * T2));
-    float v = N * hrcp(Pp + hsqrt(fmaxf(M, 0.0f)));
-    return T == INFINITY ? 0.0f : v;
+    const float T2 = T * T;
+    const float Q = fmaf(half_ar, T2, s);
+    const bool stop = s <= cA * T2;
+    const bool fast = s >= cB * T2;
+    const float n_slow = Q + Q;
+    const float m_slow = fmaf(alpha4, Q, beta2 * T2);
+    const float m_stop = s * cD;
+    const float p_slow = beta * T;
+    float N, Pp;
+    if (CHIP) {
+        N = (fast || stop) ? s : n_slow;
+        Pp = fast ? pfast * T : p_slow;
+    } else {
+        N = fast ? fmaf(hfast, T2, s) : n_slow;
+        N = stop ? s : N;
+        Pp = fast ? T : p_slow;
+    }
+    float M = fast ? 0.0f : m_slow;
+    Pp = stop ? 0.0f : Pp;
+    M = stop ? m_stop : M;
+    return N * hrcp(Pp + hsqrt(fmaxf(M, 0.0f)));
+}
+
+// Critical speeds of one side at the lane's samples for one kick type (0 for
+// every sample when the side has no robot).
+template <int KPL, bool CHIP>
+__device__ __forceinline__ void side_vcrit(const DevParams &P, int n_side, const float (&T)[KPL],
+                                           const float (&sk)[KPL], const float (&vair)[KPL],
+                                           float (&v)[KPL])
+{
+    if (n_side == 0) {
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) v[q] = 0.0f;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        if (CHIP)
+            v[q] = fminf(vair[q], vcrit<true>(T[q], sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
+                                              P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast,
+                                              P.half_ar));
+        else
+            v[q] = vcrit<false>(T[q], sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
+                                P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
+    }
 }
 
 // Ball time (float64) to distance s for staged variant c.
@@ -289,17 +387,17 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
     float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
     // lanes < n_op: direction to the opponent; lanes 62/63: to the goal posts
     float4 o = S.rob[n_tm + (l < n_op ? l : 0)];
-    float ox = o.x - cx * P.A, oy = o.y - cy * P.A;
+    float ox = o.x - cx, oy = o.y - cy;
     float Y = l < n_op ? oy : (l == 62 ? -P.half_goal_w - cy : P.half_goal_w - cy);
     float X = l < n_op ? ox : dxg;
     float ang = atan2f(Y, X);
     float lo = readlane_f(ang, 62);
     float hi = readlane_f(ang, 63);
-    bool valid = l < n_op && o.x < P.goal_xA;
+    bool valid = l < n_op && o.x < P.goal_x;
     float rho2 = fmaf(ox, ox, oy * oy);
-    bool inside = valid && rho2 <= P.RA * P.RA;
+    bool inside = valid && rho2 <= P.R * P.R;
     if (__ballot(inside)) return 0.0f;
-    float al = asinf(fminf(P.RA * rsq(fmaxf(rho2, 1e-30f)), 1.0f));
+    float al = asinf(fminf(P.R * rsq(fmaxf(rho2, 1e-30f)), 1.0f));
     float s = fmaxf(ang - al, lo);
     float e = fminf(ang + al, hi);
     bool has = valid && e > s;
@@ -324,9 +422,9 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
 // hold lane v's variant (lanes >= n_var: type -1).  On return lane v
 // (< n_var) holds that variant's results.
 template <int KPL>
-__device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, int mytype,
-                           float cx, float cy, double cx64, double cy64, float &o_score,
-                           int &o_feas, float &o_tt, float &o_to)
+__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
+                           float myv0, int mytype, float cx, float cy, double cx64,
+                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to)
 {
     const int l = lane_id();
     const int K = KPL * 64;
@@ -338,49 +436,53 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float myv0, in
     const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
     const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
 
-    float pxA[KPL], pyA[KPL], sk[KPL], Tt[KPL], To[KPL];
+    float fs[KPL], sk[KPL], Tt[KPL], To[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-        float f = (float)(q * 64 + l + 1) * invK;
-        pxA[q] = fmaf(f, ex, bx) * P.A;
-        pyA[q] = fmaf(f, ey, by) * P.A;
-        sk[q] = f * d;
+        fs[q] = (float)(q * 64 + l + 1) * invK;
+        sk[q] = fs[q] * d;
         Tt[q] = INFINITY;
         To[q] = INFINITY;
     }
-    // 1. robot stage
+    // 1. robot stage, in the path frame of the point
+    const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
     if (uni(S.vel_ok)) {
-        robot_stage<KPL, false>(S, P, 0, n_tm, pxA, pyA, Tt);
-        robot_stage<KPL, false>(S, P, n_tm, n_op, pxA, pyA, To);
+        robot_stage<KPL, false>(pr, P, 0, n_tm, fs, LA, Tt);
+        robot_stage<KPL, false>(pr, P, n_tm, n_op, fs, LA, To);
     } else {
-        robot_stage<KPL, true>(S, P, 0, n_tm, pxA, pyA, Tt);
-        robot_stage<KPL, true>(S, P, n_tm, n_op, pxA, pyA, To);
+        robot_stage<KPL, true>(pr, P, 0, n_tm, fs, LA, Tt);
+        robot_stage<KPL, true>(pr, P, n_tm, n_op, fs, LA, To);
     }
     // 2-3. critical kick speeds per sample, then the first crossing per
-    // variant by ballot; the crossing of variant v lands on lane v
-    int my_kt = K, my_ko = K;
+    // variant by ballot, through xr to lane v
+    // (a side with no robot never intercepts: critical speed 0)
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        Tt[q] *= P.invA2;  // seconds
+        To[q] *= P.invA2;
+    }
     if (flat_m) {
         float vt[KPL], vo[KPL];
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-            vt[q] = vcrit(Tt[q] * P.invA, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
-                          P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
-            vo[q] = vcrit(To[q] * P.invA, sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
-                          P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
-        }
-        first_crossings<KPL>(flat_m, myv0, vt, vo, my_kt, my_ko);
+        side_vcrit<KPL, false>(P, n_tm, Tt, sk, sk, vt);
+        side_vcrit<KPL, false>(P, n_op, To, sk, sk, vo);
+        first_crossings<KPL>(flat_m, myv0, vt, vo, xr);
     }
     if (chip_m) {
-        float vt[KPL], vo[KPL];
+        float vt[KPL], vo[KPL], vair[KPL];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-            float vair = hsqrt(sk[q] * P.lam1_inv);
-            vt[q] = fminf(vair, vcrit(Tt[q] * P.invA, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
-                                      P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
-            vo[q] = fminf(vair, vcrit(To[q] * P.invA, sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
-                                      P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast, P.half_ar));
-        }
-        first_crossings<KPL>(chip_m, myv0, vt, vo, my_kt, my_ko);
+        for (int q = 0; q < KPL; ++q) vair[q] = hsqrt(sk[q] * P.lam1_inv);
+        side_vcrit<KPL, true>(P, n_tm, Tt, sk, vair, vt);
+        side_vcrit<KPL, true>(P, n_op, To, sk, vair, vo);
+        first_crossings<KPL>(chip_m, myv0, vt, vo, xr);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int my_kt = K, my_ko = K;
+    if ((mytype == DPPS_FLAT) | (mytype == DPPS_CHIP)) {
+        const uint32_t x = xr[l];
+        my_kt = (int)(x & 0xFFFFu);
+        my_ko = (int)(x >> 16);
     }
     // open goal angle (lanes = opponents)
     const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
@@ -421,6 +523,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
     __shared__ OutLDS O;
+    __shared__ float4 PR[MAX_WAVES][MAX_ROB];  // each wave's path frame of its point
+    __shared__ uint32_t XR[MAX_WAVES][64];     // each wave's first crossings per variant
     __shared__ int s_tile;
     const DevParams &P = a.P;
     const int nw = blockDim.x >> 6;
@@ -432,6 +536,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     int cur_frame = -1;
     float myv0 = 0.0f;
     int mytype = -1;
+    int myvid = 0;  // the caller's index of lane l's variant
     while (true) {
         int t;
         if (a.persistent) {
@@ -453,6 +558,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int nv = S.n_var;
             myv0 = l < nv ? S.v0[l] : 0.0f;
             mytype = l < nv ? S.type[l] : -1;
+            myvid = l < nv ? S.vidx[l] : 0;
         } else {
             __syncthreads();
         }
@@ -469,10 +575,11 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
             float sc, tt, to;
             int fe;
-            eval_point<KPL>(S, P, myv0, mytype, cx, cy, cx64, cy64, sc, fe, tt, to);
+            eval_point<KPL>(S, P, PR[w], XR[w], myv0, mytype, cx, cy, cx64, cy64, sc, fe, tt,
+                            to);
             unsigned long long key = 0ull;
             if (fe) {
-                uint32_t lin = (uint32_t)(W.elem_base + l * W.npts + p);
+                uint32_t lin = (uint32_t)(W.elem_base + myvid * W.npts + p);
                 key = ((unsigned long long)__float_as_uint(sc) << 32) |
                       (unsigned long long)(0xFFFFFFFFu - lin);
             }
@@ -494,10 +601,10 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                     }
                 }
             } else if (l < n_var) {
-                O.score[l * MAX_TILE + slot] = sc;
-                O.mask[l * MAX_TILE + slot] = (uint8_t)fe;
-                if (a.t_team) a.t_team[W.out_base + (int64_t)l * W.npts + p] = tt;
-                if (a.t_opp) a.t_opp[W.out_base + (int64_t)l * W.npts + p] = to;
+                O.score[myvid * MAX_TILE + slot] = sc;
+                O.mask[myvid * MAX_TILE + slot] = (uint8_t)fe;
+                if (a.t_team) a.t_team[W.out_base + (int64_t)myvid * W.npts + p] = tt;
+                if (a.t_opp) a.t_opp[W.out_base + (int64_t)myvid * W.npts + p] = to;
             }
         }
         // the wave's best pass (and its times), then the tile's

@@ -477,9 +477,11 @@ int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, vo
 }
 
 int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
-                          int fallback, int32_t *n_fallback, void *hip_stream)
+                          int fallback, float fallback_below, int32_t *n_fallback,
+                          void *hip_stream)
 {
     if (!c || !m || !b || !d_best) return fail(DPPS_E_INVALID, "NULL argument");
+    if (fallback_below != fallback_below) return fail(DPPS_E_INVALID, "fallback_below is NaN");
     if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
     if (k < 1 || k > m->k_cap) return fail(DPPS_E_INVALID, "k must be in [1, %d]", m->k_cap);
     HIP_OK(hipSetDevice(c->device));
@@ -523,7 +525,7 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     HIP_OK(hipStreamSynchronize(st));
     std::vector<int> redo;
     for (int f = 0; f < nf; ++f)
-        if (!hb[f].found) redo.push_back(f);
+        if (!hb[f].found || hb[f].score < fallback_below) redo.push_back(f);
     if (n_fallback) *n_fallback = (int32_t)redo.size();
     if (redo.empty()) return DPPS_OK;
     std::vector<dpps_frame> fr(redo.size());
@@ -552,25 +554,35 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
         win[i].nx = m->fine_nx;
         win[i].ny = m->fine_ny;
     }
-    dpps_batch *fb = nullptr;
-    rc = dpps_batch_create(c, (int32_t)redo.size(), fr.data(), rob.data(), win.data(), var.data(), &fb);
+    // the context's own fallback batch: no allocation once it is large enough
+    dpps_batch *fb = &c->fallback;
+    rc = stage_batch(c, fb, (int32_t)redo.size(), fr.data(), rob.data(), win.data(), var.data(), st);
     if (rc) return rc;
-    std::vector<dpps_best> out_b(redo.size());
     dpps_outputs o;
     memset(&o, 0, sizeof o);
-    rc = dpps_batch_run(c, fb, &o, (void *)st, 0);
-    if (!rc) {
-        if (hipMemcpyAsync(out_b.data(), fb->d_best, redo.size() * sizeof(dpps_best),
-                           hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            rc = fail(DPPS_E_DEVICE, "fallback copy failed");
-    }
-    dpps_batch_destroy(fb);
+    rc = run_batch(c, fb, &o, st, false);
     if (rc) return rc;
     for (size_t i = 0; i < redo.size(); ++i)
-        HIP_OK(hipMemcpyAsync(d_best + redo[i], &out_b[i], sizeof(dpps_best), hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(d_best + redo[i], fb->d_best + i, sizeof(dpps_best),
+                              hipMemcpyDeviceToDevice, st));
     HIP_OK(hipStreamSynchronize(st));
     return DPPS_OK;
+}
+
+int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
+                                 const dpps_frame *frames, const dpps_robot *robots,
+                                 const dpps_window *windows, const dpps_variant *variants,
+                                 int32_t k, dpps_best *d_best, int fallback, float fallback_below,
+                                 int32_t *n_fallback, void *hip_stream)
+{
+    if (!c || !m) return fail(DPPS_E_INVALID, "NULL argument");
+    if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    int rc = stage_batch(c, &c->scratch, n_frames, frames, robots, windows, variants, st);
+    if (rc) return rc;
+    return dpps_surrogate_search(c, m, &c->scratch, k, d_best, fallback, fallback_below,
+                                 n_fallback, hip_stream);
 }
 
 }  // extern "C"

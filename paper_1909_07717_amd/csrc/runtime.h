@@ -81,7 +81,8 @@ struct dpps_ctx {
     int waves = 4;
     int wg_per_cu = 0;       // 0: as many as fit (occupancy of the search kernel)
     int persistent = 1;
-    dpps_batch scratch;      // used by dpps_search / dpps_search_batch
+    dpps_batch scratch;      // used by dpps_search / dpps_search_batch / host-frame surrogate
+    dpps_batch fallback;     // exact searches of surrogate frames without a feasible proposal
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;   // pinned staging consumed
@@ -106,3 +107,6 @@ void pack_tables(const dpps::HostTables &T, const Layout &L, char *dst);
 int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L);
 int batch_upload(dpps_ctx *c, dpps_batch *b);
 int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st, bool timed);
+int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *frames,
+                const dpps_robot *robots, const dpps_window *windows,
+                const dpps_variant *variants, hipStream_t st);

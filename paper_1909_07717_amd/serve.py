@@ -222,7 +222,6 @@ class SurrogateExecutor(ExactExecutor):
         if weights:
             from paper_1909_07717_amd.surrogate import load_checkpoint
             self.net.set_params(load_checkpoint(weights)["params"])
-        self.bt = None
         self.n_primary = 0
 
     def start(self, batch, now):
@@ -235,8 +234,8 @@ class SurrogateExecutor(ExactExecutor):
         sz = B.BEST_DT.itemsize
         with torch.cuda.stream(self.stream):
             if prim:
-                self.bt = self.s.batch(B.pack([r.frame for r in prim], self.s.params))
-                best, _ = self.net.search(self.bt, k=self.k, fallback=False, stream=self.stream)
+                best, _ = self.net.search_frames(B.pack([r.frame for r in prim], self.s.params),
+                                                 k=self.k, fallback=False, stream=self.stream)
                 self.host[:len(prim) * sz].copy_(best, non_blocking=True)
             if foll:
                 pk = B.pack([r.frame for r in foll], self.s.params)
@@ -252,9 +251,6 @@ class SurrogateExecutor(ExactExecutor):
         out = super().poll(now)
         if out is None:
             return None
-        if self.bt is not None:
-            self.bt.close()
-            self.bt = None
         return [(r, rec if (rec["found"] or i >= self.n_primary) else None)
                 for i, (r, rec) in enumerate(out)]
 

@@ -144,6 +144,24 @@ def test_surrogate_search_equals_exact_search_on_its_windows(B):
     bt.close(); net.close(); s.close()
 
 
+def test_surrogate_search_of_host_frames_equals_batch_search(B):
+    # two calls in a row through the context's own staging (the second
+    # smaller), with and without fallback, against batches of the same frames
+    s = B.Searcher(P)
+    net = B.Mlp(s, 16, seed=5)
+    for n, base, fb in ((12, 700, True), (5, 900, False), (9, 1100, True)):
+        frames = _frames(n, base)
+        got_t, nfb_a = net.search_frames(frames, k=64, fallback=fb)
+        got = B.best_records(got_t).copy()
+        bt = s.batch(frames)
+        ref_t, nfb_b = net.search(bt, k=64, fallback=fb)
+        ref = B.best_records(ref_t)
+        bt.close()
+        assert nfb_a == nfb_b
+        assert got.tobytes() == ref.tobytes()
+    net.close(); s.close()
+
+
 def test_fallback_when_no_proposal_is_feasible(B):
     s = B.Searcher(P)
     net = B.Mlp(s, 8, seed=1)
@@ -162,6 +180,33 @@ def test_fallback_when_no_proposal_is_feasible(B):
     g.windows = [full_window(0.05)]
     _, ref = s.search(g)
     assert ref["found"] == 1 and best.tobytes() == ref.tobytes()
+    bt.close(); net.close(); s.close()
+
+
+def test_fallback_below_a_score_threshold(B):
+    s = B.Searcher(P)
+    frames = _frames(12, 500)
+    net = B.Mlp(s, 16, seed=3)
+    bt = s.batch(frames)
+    raw = B.best_records(net.search(bt, k=64, fallback=False)[0]).copy()
+    found = raw["found"] != 0
+    assert found.any()
+    thr = float(np.median(raw["score"][found]))
+    got_t, nfb = net.search(bt, k=64, fallback=True, fallback_below=thr)
+    got = B.best_records(got_t)
+    redo = 0
+    for i, f in enumerate(frames):
+        if raw[i]["found"] and raw[i]["score"] >= thr:
+            assert got[i].tobytes() == raw[i].tobytes(), i
+            continue
+        redo += 1
+        g = f.copy()
+        g.windows = [full_window(0.05)]
+        _, ref = s.search(g)
+        assert got[i].tobytes() == ref.tobytes(), i
+    assert nfb == redo and 0 < redo < len(frames)
+    with pytest.raises(B.DppsError):
+        net.search(bt, k=64, fallback=True, fallback_below=float("nan"))
     bt.close(); net.close(); s.close()
 
 
