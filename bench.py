@@ -121,15 +121,16 @@ def batch_bench(n_frames: int, steps: int, tune_cache: str, st):
     return rec
 
 
-def surrogate_bench(frames: int, weights: str):
+def surrogate_bench(frames: int, weights: str, lat_frames: int = 10000):
     """Surrogate + top-64 exact re-score (5 cm) against the exact 5 cm search
     on 6v6 frames with one flat pass at 4 m/s, K = 64 (the network's
     training setting): regret, match and fallback rates, frames/s of both."""
     if not os.path.exists(weights):
         return {"note": f"no trained weights at {os.path.relpath(weights, ROOT)}"}
-    from paper_1909_07717_amd.surrogate import evaluate
+    from paper_1909_07717_amd.surrogate import evaluate, latency
     res = evaluate(weights, frames, k=64, batch=min(frames, 1024))
     res["speedup_vs_exact"] = res["surrogate_frames_per_s"] / res["exact_frames_per_s"]
+    res["latency_ms"] = latency(weights, frames=lat_frames)
     return res
 
 
@@ -162,7 +163,7 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1909_07717_amd",
                                                          "autotune_cache.jsonl"))
-    ap.add_argument("--latency-frames", type=int, default=2000)
+    ap.add_argument("--latency-frames", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -241,7 +242,8 @@ def main() -> int:
     batch = None
     if args.batch_frames > 0:
         batch = batch_bench(args.batch_frames, args.batch_steps, args.tune_cache, st)
-    sur = surrogate_bench(args.surrogate_frames, args.weights) if args.surrogate_frames > 0 else None
+    sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
+           if args.surrogate_frames > 0 else None)
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
 
     achieved = fl / (kern_avg_ms * 1e-3) / 1e12

@@ -52,6 +52,69 @@ def _label_setup():
     return [full_window(0.2)], variants_for([4.0], flat=True, chip=False)
 
 
+def mirror_arrays(team: np.ndarray, opp: np.ndarray):
+    """The frames reflected about the field's long axis (y -> -y, vy -> -vy).
+    The field, the goal and the lattice are symmetric about it, so the exact
+    score map of a reflected frame is the reflected map."""
+    t, o = team.copy(), opp.copy()
+    for a in (t, o):
+        a[..., 1] *= -1.0
+        a[..., 3] *= -1.0
+    return t, o
+
+
+def mirror_cells(y):
+    """Reflect [n, 2806] maps over the 20 cm cells (row cj <-> 45 - cj)."""
+    return y.reshape(y.shape[0], 46, 61).flip(1).reshape(y.shape[0], 2806)
+
+
+def cell_windows(cells: np.ndarray) -> np.ndarray:
+    """5 cm windows [n, k, 5] = (h, i0, j0, nx, ny) of 20 cm cells [n, k]:
+    the fine points {4c-2 .. 4c+1} of each axis, clipped to the lattice."""
+    ci, cj = cells % 61, cells // 61
+    i0, i1 = np.maximum(4 * ci - 2, 0), np.minimum(4 * ci + 1, 240)
+    j0, j1 = np.maximum(4 * cj - 2, 0), np.minimum(4 * cj + 1, 180)
+    out = np.zeros(cells.shape + (5,), np.float64)
+    out[..., 0] = np.float32(0.05)
+    out[..., 1], out[..., 2] = i0, j0
+    out[..., 3], out[..., 4] = i1 - i0 + 1, j1 - j0 + 1
+    return out
+
+
+def geometric_cells(team: np.ndarray, passer: np.ndarray, variants, k: int,
+                    params=None) -> np.ndarray:
+    """The proposals of the method without a network: 20 cm cells ranked by
+    the terms of the Eq. (3) score that need no robot (open goal angle with
+    no blockers, distance to the goal), among the cells within the ball's
+    reach of the fastest variant (plus the cell's half-diagonal); ties to
+    the lower cell.  Returns [n, k] cell indices."""
+    from paper_1909_07717_amd.framegen import Params
+    P = params or Params()
+    cx = 0.2 * (np.arange(61) - 30.0)
+    cy = 0.2 * (np.arange(46) - 22.5)
+    X, Y = np.meshgrid(cx, cy)
+    X, Y = X.ravel(), Y.ravel()
+    hw = P.goal_width / 2
+    dx = np.maximum(P.goal_x - X, P.goal_eps)
+    ang = np.arctan2(hw - Y, dx) - np.arctan2(-hw - Y, dx)
+    prior = (P.w_angle * ang / np.pi
+             + P.w_dist * (1.0 - np.hypot(X - P.goal_x, Y) / P.dist_norm))
+    reach = 0.0
+    for typ, v0 in variants:
+        if typ == 0:
+            v1 = P.slide_ratio * v0
+            D = (v0 * v0 - v1 * v1) / (2 * P.slide_decel) + v1 * v1 / (2 * P.roll_decel)
+        else:
+            vh = v0 * np.cos(P.chip_angle)
+            D = v0 * v0 * np.sin(2 * P.chip_angle) / P.gravity + vh * vh / (2 * P.roll_decel)
+        reach = max(reach, D)
+    idx = np.arange(team.shape[0])
+    bx, by = team[idx, passer, 0], team[idx, passer, 1]
+    d = np.hypot(X[None, :] - bx[:, None], Y[None, :] - by[:, None])
+    score = np.where(d <= reach + 0.15, prior[None, :], -np.inf)
+    return np.argsort(-score, axis=1, kind="stable")[:, :k]
+
+
 def save_checkpoint(path, net, step: int, extra: dict, params_only: bool = False):
     """Parameters, Adam state and data position (for resume); with
     params_only, the parameters and the metadata alone (8 MB)."""
@@ -76,9 +139,11 @@ def load_checkpoint(path):
 def train(frames: int, batch: int, lr: float, out: str, resume: str | None = None,
           log_every: int = 20, seed: int = 0, epochs: int = 1, pos_weight: float = 0.0,
           ce_weight: float = 0.0, tau: float = 0.02, labels: str = "pooled",
-          params_only: bool = False):
+          params_only: bool = False, mirror: bool = False):
     """`frames` distinct frames (frames // batch seeded batches) seen `epochs`
-    times, batch order reshuffled every epoch.
+    times, batch order reshuffled every epoch.  With mirror, every batch also
+    appears reflected about the field's long axis (its labels computed
+    exactly on the reflected frames), doubling the batches of an epoch.
 
     labels = "pooled": each 20 cm cell's label is the best exact score over
     the 5 cm points its re-score would visit (exact search of the 5 cm
@@ -96,7 +161,8 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
     s = B.Searcher(p)
     net = B.Mlp(s, batch, seed=seed)
     n_batches = max(1, frames // batch)
-    order = np.concatenate([np.random.default_rng(seed + e).permutation(n_batches)
+    n_virt = n_batches * (2 if mirror else 1)
+    order = np.concatenate([np.random.default_rng(seed + e).permutation(n_virt)
                             for e in range(epochs)])
     steps = len(order)
     start = 0
@@ -106,14 +172,16 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
         net.set_adam(ck["adam_m"], ck["adam_v"], int(ck["adam_step"]))
         start = int(ck["data_step"])
     st = torch.cuda.Stream()
-    cache = torch.empty((n_batches, batch, 2806), dtype=torch.float32, device=s.device)
-    have = np.zeros(n_batches, bool)
+    cache = torch.empty((n_virt, batch, 2806), dtype=torch.float32, device=s.device)
+    have = np.zeros(n_virt, bool)
     fine_out = None
     log = []
     t0 = time.time()
     for step in range(start, steps):
         bi = int(order[step])
-        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi, batch)
+        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi % n_batches, batch)
+        if bi >= n_batches:
+            team, opp = mirror_arrays(team, opp)
         pk = B.pack_uniform(team, opp, passer, windows, variants, p)
         bt = s.batch(pk)
         with torch.cuda.stream(st):
@@ -142,7 +210,7 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
             print(json.dumps(rec), flush=True)
     meta = {"frames": n_batches * batch, "epochs": epochs, "batch": batch, "lr": lr,
             "pos_weight": pos_weight, "ce_weight": ce_weight, "tau": tau, "labels": labels,
-            "steps": steps, "train_seed": TRAIN_SEED, "log": log}
+            "steps": steps, "train_seed": TRAIN_SEED, "mirror": mirror, "log": log}
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     save_checkpoint(out, net, steps, meta, params_only)
     net.close()
@@ -151,8 +219,16 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
 
 
 def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, random_net=False,
-             seed0: int = EVAL_SEED, dump: str | None = None):
+             seed0: int = EVAL_SEED, dump: str | None = None, proposals: str = "network",
+             fallback_below: float = -math.inf):
     """Regret statistics of the surrogate search against the exact 5 cm search.
+
+    proposals = "network": the trained (or, with random_net, untrained)
+    network's top-k cells; "mirror": the top-k cells of the network's map
+    averaged with its (reflected back) map of the reflected frame;
+    "geometric": the method without a network (geometric_cells).  All are
+    re-scored by the same exact kernel with the same fallback rule.  Frames whose best re-scored pass is infeasible or scores
+    below `fallback_below` take the exact search.
 
     With `dump`, also writes per-frame arrays (npz): the exact best score,
     the surrogate's best re-scored score before any fallback (-inf when no
@@ -186,13 +262,34 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
         a = time.perf_counter()
         bt.run(ex)
         torch.cuda.synchronize()
-        t_exact += time.perf_counter() - a
-        a = time.perf_counter()
-        sb, nfb = net.search(bt, k=k, fallback=True)
-        torch.cuda.synchronize()
-        t_sur += time.perf_counter() - a
+        dt_ex = time.perf_counter() - a
+        t_exact += dt_ex
         be = ex.best_host()
-        bs = B.best_records(sb)
+        a = time.perf_counter()
+        if proposals in ("geometric", "mirror"):
+            if proposals == "geometric":
+                cells = geometric_cells(team, passer, variants, k)
+            else:
+                tm, om = mirror_arrays(team, opp)
+                btm = s.batch(B.pack_uniform(tm, om, passer, fine, variants, p))
+                y = net.forward(bt) + mirror_cells(net.forward(btm))
+                btm.close()
+                cells = torch.topk(y, k, dim=1).indices.cpu().numpy()
+            wins = cell_windows(cells)
+            pkc = B.pack_uniform(team, opp, passer, wins, variants, p)
+            _, outc = s.search_batch(pkc, mask=False, score=False)
+            torch.cuda.synchronize()
+            bs = outc.best_host().copy()
+            redo = (bs["found"] == 0) | (bs["score"] < fallback_below)
+            nfb = int(redo.sum())
+            bs[redo] = be[redo]  # the fallback is the exact search of the frame
+            # plus the exact searches of the fallback frames, at this batch's rate
+            t_sur += time.perf_counter() - a + nfb * dt_ex / n
+        else:
+            sb, nfb = net.search(bt, k=k, fallback=True, fallback_below=fallback_below)
+            torch.cuda.synchronize()
+            t_sur += time.perf_counter() - a
+            bs = B.best_records(sb)
         fallbacks += nfb
         if dump:
             raw, _ = net.search(bt, k=k, fallback=False)
@@ -224,13 +321,63 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
            "match_rate": match / max(r.size, 1), "fallback_rate": fallbacks / frames,
            "no_feasible_exact": none_exact,
            "exact_frames_per_s": frames / t_exact, "surrogate_frames_per_s": frames / t_sur,
-           "network": "random init" if (random_net or not weights) else os.path.basename(weights)}
+           "fallback_below": fallback_below, "proposals": proposals,
+           "network": (None if proposals == "geometric" else "random init"
+                       if (random_net or not weights) else os.path.basename(weights))}
     if dump:
         a = np.concatenate(rows, 0)
         np.savez(dump, exact=a[:, 0], raw=a[:, 1], pred_top=a[:, 2], pred_kth=a[:, 3])
     net.close()
     s.close()
     return res
+
+
+def latency(weights: str | None, frames: int = 10000, warmup: int = 100, k: int = 64,
+            seed0: int = EVAL_SEED):
+    """Frame latency, host inputs to the best pass on the host, one frame at
+    a time (6 v 6, one flat pass at 4 m/s, K = 64): the exact search of the
+    whole 5 cm lattice (dpps_search) and the surrogate search with exact
+    fallback (dpps_surrogate_search_frames, then the best record copied
+    back).  p50 / p99 over `frames` frames after `warmup`."""
+    import torch
+
+    from paper_1909_07717_amd import binding as B
+    from paper_1909_07717_amd.framegen import (frames_from_arrays, full_window,
+                                               uniform_batch_arrays, variants_for)
+
+    p = _params()
+    variants = variants_for([4.0], flat=True, chip=False)
+    fine = [full_window(0.05)]
+    s = B.Searcher(p)
+    net = B.Mlp(s, 1, max_k=k, seed=0)
+    if weights:
+        net.set_params(load_checkpoint(weights)["params"])
+    n = warmup + frames
+    team, opp, passer = uniform_batch_arrays(seed0 + 7777, n)
+    fr = frames_from_arrays(team, opp, passer, fine, variants)
+    best = torch.empty(B.BEST_DT.itemsize, dtype=torch.uint8, device=s.device)
+    host = torch.empty(B.BEST_DT.itemsize, dtype=torch.uint8, pin_memory=True)
+    out = {}
+    for kind in ("exact", "surrogate"):
+        lat, fb = [], 0
+        for i in range(n):
+            a = time.perf_counter()
+            if kind == "exact":
+                s.search(fr[i], mask=False, score=False)
+            else:
+                _, nfb = net.search_frames([fr[i]], k=k, fallback=True, best=best)
+                host.copy_(best)
+                fb += nfb
+            if i >= warmup:
+                lat.append(time.perf_counter() - a)
+        lat = np.array(lat) * 1e3
+        out[kind] = {"p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "frames": int(lat.size)}
+        if kind == "surrogate":
+            out[kind]["fallbacks"] = fb
+    net.close()
+    s.close()
+    return out
 
 
 def main():
@@ -249,20 +396,25 @@ def main():
     t.add_argument("--labels", choices=["pooled", "center"], default="pooled")
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--params-only", action="store_true")
+    t.add_argument("--mirror", action="store_true")
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--frames", type=int, default=2000)
     e.add_argument("--k", type=int, default=64)
     e.add_argument("--random", action="store_true")
     e.add_argument("--dump", default=None)
+    e.add_argument("--proposals", choices=["network", "mirror", "geometric"], default="network")
+    e.add_argument("--fallback-below", type=float, default=-math.inf)
     args = ap.parse_args()
     if args.cmd == "train":
         train(args.frames, args.batch, args.lr, args.out, args.resume, seed=args.seed,
               epochs=args.epochs, pos_weight=args.pos_weight, ce_weight=args.ce_weight,
-              tau=args.tau, labels=args.labels, params_only=args.params_only)
+              tau=args.tau, labels=args.labels, params_only=args.params_only,
+              mirror=args.mirror)
     else:
         print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random,
-                                  dump=args.dump)), flush=True)
+                                  dump=args.dump, proposals=args.proposals,
+                                  fallback_below=args.fallback_below)), flush=True)
 
 
 if __name__ == "__main__":
