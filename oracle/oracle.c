@@ -505,4 +505,197 @@ int64_t orc_argmax(int64_t n, const double *score)
     return best;
 }
 
-int orc_abi_version(void) { return 1; }
+/* ------------------------------------------------------------------------ */
+/* The paper's own DPPS form (Sec. 4.2, Fig. "dynamic passing points         */
+/* searching process"): from the passer's point of view, every kick          */
+/* direction and every kick power.                                           */
+/*                                                                           */
+/* Readings (the paper gives the sweep sizes but not these details):         */
+/*   - directions theta_d = 2 pi d / n_dirs from +x, counterclockwise;        */
+/*   - the ball path runs along the direction from the ball until the ball    */
+/*     stops (D of the power) or leaves the field; the K samples are uniform  */
+/*     in distance over the part inside the field, s_k = (k+1) L / K, shared  */
+/*     by all powers, and a power only uses the samples its ball reaches      */
+/*     (s_k <= D; chips also only samples at or past the landing point);      */
+/*   - SBIP per robot as above; the pass is received at the first teammate's  */
+/*     interception (the passer excluded), which is the passing point;        */
+/*   - feasible when a teammate intercepts and the first opponent comes at    */
+/*     least margin_s later (or never);                                       */
+/*   - score (Eq. 3 with the five features of Sec. 4.3): open goal angle at   */
+/*     the passing point / pi, 1 - its distance to the goal centre /          */
+/*     dist_norm, the margin clipped to [0, margin_cap_s], minus w_time times */
+/*     the teammate's interception time (seconds, not normalised) and minus   */
+/*     w_refract times the refraction angle / pi, the angle between the       */
+/*     ball's direction and the shot from the passing point to the goal       */
+/*     centre (0 when the ball already heads there);                          */
+/*   - best: largest score, ties to the lowest (direction, variant) index.    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_dirs, pad;
+    double w_time, w_refract;
+} orc_ray_params;
+
+typedef struct {
+    int32_t feasible, k_team, k_opp, ambig;
+    double t_team, t_opp, margin, score, s_recv, x, y, open_angle, refract, length;
+} orc_ray_result;
+
+/* Distance from (bx, by) along (ux, uy) to the edge of the field rectangle
+ * (0 when the ball is on or outside the edge and the ray leaves). */
+double orc_ray_length(const orc_params *P, double bx, double by, double ux, double uy)
+{
+    double hl = 0.5 * P->field_len, hw = 0.5 * P->field_wid;
+    double L = INFINITY;
+    if (ux > 0.0) L = fmin(L, (hl - bx) / ux);
+    if (ux < 0.0) L = fmin(L, (-hl - bx) / ux);
+    if (uy > 0.0) L = fmin(L, (hw - by) / uy);
+    if (uy < 0.0) L = fmin(L, (-hw - by) / uy);
+    return L > 0.0 ? L : 0.0;
+}
+
+/* First interception of one robot along the ray (sample index, or K). */
+static int ray_sbip_robot(const orc_params *P, int type, double v0, double D, double sf,
+                          double bx, double by, double ux, double uy, double L,
+                          const double *rb)
+{
+    int K = P->n_samples;
+    for (int k = 0; k < K; ++k) {
+        double s = (double)(k + 1) / (double)K * L;
+        if (s > D) break; /* the ball never gets there */
+        if (type == ORC_CHIP && s < sf) continue; /* still in the air */
+        double tb = orc_ball_time(P, type, v0, s);
+        double tr = robot_time_to(P, rb, bx + s * ux, by + s * uy);
+        if (tr <= tb) return k;
+    }
+    return K;
+}
+
+/* Bands of one side along the ray (parity tests only): at each sample the
+ * ball reaches, up to the side's first interception, the side's earliest
+ * arrival within eps_cross_t of the ball or the ball's position at that
+ * arrival within eps_cross_s of the sample; a sample within eps_reach of the
+ * stopping distance or within eps_land of a chip's landing point. */
+static void ray_side_bands(const orc_params *P, int type, double v0, double D, double sf,
+                           double bx, double by, double ux, double uy, double L,
+                           const double *robots, int n, int skip, int k_side, int *amb)
+{
+    int K = P->n_samples;
+    int klim = k_side < K ? k_side : K - 1;
+    for (int k = 0; k <= klim; ++k) {
+        double s = (double)(k + 1) / (double)K * L;
+        if (fabs(s - D) < P->eps_reach) *amb |= ORC_AMB_REACH;
+        if (s > D) break;
+        double tmin = INFINITY;
+        for (int j = 0; j < n; ++j) {
+            if (j == skip) continue;
+            double tr = robot_time_to(P, robots + 4 * j, bx + s * ux, by + s * uy);
+            if (tr < tmin) tmin = tr;
+        }
+        if (!isfinite(tmin)) return;
+        if (type == ORC_CHIP && fabs(s - sf) < P->eps_land) {
+            double tb_land = s / (v0 * cos(P->chip_angle));
+            if (tmin <= tb_land + P->eps_cross_t) *amb |= ORC_AMB_LAND;
+        }
+        if (type == ORC_CHIP && s < sf) continue;
+        double tb = orc_ball_time(P, type, v0, s);
+        if (fabs(tmin - tb) < P->eps_cross_t) *amb |= ORC_AMB_CROSS;
+        double sb = orc_ball_dist(P, type, v0, tmin);
+        if (fabs(sb - s) < P->eps_cross_s) *amb |= ORC_AMB_CROSS;
+    }
+}
+
+void orc_ray_eval(const orc_params *P, const orc_ray_params *R, const orc_world *W, int dir,
+                  int type, double v0, int bands, orc_ray_result *out)
+{
+    int K = P->n_samples;
+    double th = 2.0 * M_PI * (double)dir / (double)R->n_dirs;
+    double ux = cos(th), uy = sin(th);
+    double bx = W->ball_x, by = W->ball_y;
+    double L = orc_ray_length(P, bx, by, ux, uy);
+    double D, sf;
+    orc_ball_range(P, type, v0, &D, &sf);
+    memset(out, 0, sizeof(*out));
+    out->length = L;
+
+    int k_team = K, k_opp = K;
+    for (int j = 0; j < W->n_team; ++j) {
+        if (j == W->passer) continue;
+        int k = ray_sbip_robot(P, type, v0, D, sf, bx, by, ux, uy, L, W->team + 4 * j);
+        if (k < k_team) k_team = k;
+    }
+    for (int j = 0; j < W->n_opp; ++j) {
+        int k = ray_sbip_robot(P, type, v0, D, sf, bx, by, ux, uy, L, W->opp + 4 * j);
+        if (k < k_opp) k_opp = k;
+    }
+    double s_team = (double)(k_team + 1) / (double)K * L;
+    double s_opp = (double)(k_opp + 1) / (double)K * L;
+    double t_team = k_team < K ? orc_ball_time(P, type, v0, s_team) : INFINITY;
+    double t_opp = k_opp < K ? orc_ball_time(P, type, v0, s_opp) : INFINITY;
+    double m;
+    if (!isfinite(t_team)) m = -INFINITY;
+    else if (!isfinite(t_opp)) m = INFINITY;
+    else m = t_opp - t_team;
+    int feasible = isfinite(t_team) && m >= P->margin_s;
+    out->k_team = k_team;
+    out->k_opp = k_opp;
+    out->t_team = t_team;
+    out->t_opp = t_opp;
+    out->margin = m;
+    out->feasible = feasible;
+    out->s_recv = isfinite(t_team) ? s_team : INFINITY;
+    out->score = -INFINITY;
+    if (feasible) {
+        double px = bx + s_team * ux, py = by + s_team * uy;
+        double gx = P->goal_x - px, gy = -py;
+        double dg = sqrt(gx * gx + gy * gy);
+        double ang = orc_open_angle(P, px, py, W->n_opp, W->opp);
+        double refr = dg > 0.0 ? atan2(fabs(ux * gy - uy * gx), ux * gx + uy * gy) : 0.0;
+        double mc = m < 0.0 ? 0.0 : (m > P->margin_cap_s ? P->margin_cap_s : m);
+        out->x = px;
+        out->y = py;
+        out->open_angle = ang;
+        out->refract = refr;
+        out->score = P->w_angle * ang / M_PI + P->w_dist * (1.0 - dg / P->dist_norm)
+                   + P->w_margin * mc - R->w_time * t_team - R->w_refract * refr / M_PI;
+    }
+    int amb = 0;
+    if (bands) {
+        ray_side_bands(P, type, v0, D, sf, bx, by, ux, uy, L, W->team, W->n_team, W->passer,
+                       k_team, &amb);
+        ray_side_bands(P, type, v0, D, sf, bx, by, ux, uy, L, W->opp, W->n_opp, -1, k_opp,
+                       &amb);
+        if (isfinite(t_team) && isfinite(m) && fabs(m - P->margin_s) < P->eps_margin)
+            amb |= ORC_AMB_MARGIN;
+    }
+    out->ambig = amb;
+}
+
+/* Every (direction, variant) of one frame, outputs [dir][variant]; any output
+ * pointer may be NULL.  Returns the number of evaluations. */
+int64_t orc_ray_search(const orc_params *P, const orc_ray_params *R, const orc_world *W,
+                       int n_var, const int32_t *var_type, const double *var_v0, int bands,
+                       uint8_t *mask, double *score, double *t_team, double *t_opp,
+                       double *s_recv, uint8_t *ambig)
+{
+#ifdef _OPENMP
+    int nt = P->n_threads > 0 ? P->n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+    for (int d = 0; d < R->n_dirs; ++d) {
+        for (int v = 0; v < n_var; ++v) {
+            orc_ray_result r;
+            orc_ray_eval(P, R, W, d, var_type[v], var_v0[v], bands, &r);
+            int64_t o = (int64_t)d * n_var + v;
+            if (mask) mask[o] = (uint8_t)r.feasible;
+            if (score) score[o] = r.score;
+            if (t_team) t_team[o] = r.t_team;
+            if (t_opp) t_opp[o] = r.t_opp;
+            if (s_recv) s_recv[o] = r.s_recv;
+            if (ambig) ambig[o] = (uint8_t)r.ambig;
+        }
+    }
+    return (int64_t)R->n_dirs * n_var;
+}
+
+int orc_abi_version(void) { return 2; }

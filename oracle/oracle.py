@@ -52,6 +52,18 @@ class OrcResult(C.Structure):
                 ("margin", C.c_double), ("score", C.c_double), ("open_angle", C.c_double)]
 
 
+class OrcRayParams(C.Structure):
+    _fields_ = [("n_dirs", C.c_int32), ("pad", C.c_int32), ("w_time", C.c_double),
+                ("w_refract", C.c_double)]
+
+
+class OrcRayResult(C.Structure):
+    _fields_ = [("feasible", C.c_int32), ("k_team", C.c_int32), ("k_opp", C.c_int32),
+                ("ambig", C.c_int32)] + [(n, C.c_double) for n in (
+                    "t_team", "t_opp", "margin", "score", "s_recv", "x", "y", "open_angle",
+                    "refract", "length")]
+
+
 # Parity bands (widths of the ambiguity regions computed by the oracle).
 DEFAULT_BANDS = dict(eps_reach=1e-4, eps_land=1e-5, eps_cross_t=1e-5, eps_cross_s=1e-5,
                      eps_margin=1e-3)
@@ -90,6 +102,14 @@ def lib():
                                         pu8, pd, pd, pd, pd, pu8]
         L.orc_argmax.argtypes = [i64, pd]
         L.orc_argmax.restype = i64
+        RP = C.POINTER(OrcRayParams)
+        L.orc_ray_length.argtypes = [P, d, d, d, d]
+        L.orc_ray_length.restype = d
+        L.orc_ray_eval.argtypes = [P, RP, Wp, C.c_int, C.c_int, d, C.c_int,
+                                   C.POINTER(OrcRayResult)]
+        L.orc_ray_search.argtypes = [P, RP, Wp, C.c_int, pi32, pd, C.c_int, pu8, pd, pd, pd, pd,
+                                     pu8]
+        L.orc_ray_search.restype = i64
         _lib = L
     return _lib
 
@@ -241,3 +261,56 @@ def open_angle(params, cx, cy, opp):
     if n == 0:
         o = np.zeros((1, 4))
     return lib().orc_open_angle(C.byref(make_params(params)), cx, cy, n, _ptr(o, C.c_double))
+
+
+# ---------------------------------------------------------------------------
+# the paper's own DPPS form: every kick direction x every kick power
+# ---------------------------------------------------------------------------
+
+def _ray_params(n_dirs: int, w_time: float, w_refract: float) -> OrcRayParams:
+    r = OrcRayParams()
+    r.n_dirs, r.w_time, r.w_refract = int(n_dirs), float(w_time), float(w_refract)
+    return r
+
+
+def ray_length(params, bx, by, ux, uy) -> float:
+    return float(lib().orc_ray_length(C.byref(make_params(params)), bx, by, ux, uy))
+
+
+def ray_search(frame, params, n_dirs: int, w_time: float, w_refract: float,
+               bands: bool = False, n_threads: int = 0, **band_eps):
+    """Every (direction, variant) of a frame; arrays shaped (n_dirs, n_variants),
+    plus ``best`` (flat index dir * V + v, or -1) and ``best_score``."""
+    L = lib()
+    P = make_params(params, n_threads, **band_eps)
+    R = _ray_params(n_dirs, w_time, w_refract)
+    wh = _WorldHolder(frame)
+    vt = np.array([v[0] for v in frame.variants], dtype=np.int32)
+    vv = np.array([v[1] for v in frame.variants], dtype=np.float64)
+    V = len(vt)
+    out = dict(mask=np.zeros((n_dirs, V), np.uint8), score=np.zeros((n_dirs, V)),
+               t_team=np.zeros((n_dirs, V)), t_opp=np.zeros((n_dirs, V)),
+               s_recv=np.zeros((n_dirs, V)), ambig=np.zeros((n_dirs, V), np.uint8))
+    L.orc_ray_search(C.byref(P), C.byref(R), C.byref(wh.w), V, _ptr(vt, C.c_int32),
+                     _ptr(vv, C.c_double), int(bands), _ptr(out["mask"], C.c_uint8),
+                     _ptr(out["score"], C.c_double), _ptr(out["t_team"], C.c_double),
+                     _ptr(out["t_opp"], C.c_double), _ptr(out["s_recv"], C.c_double),
+                     _ptr(out["ambig"], C.c_uint8))
+    flat = np.ascontiguousarray(out["score"].reshape(-1))
+    best = int(L.orc_argmax(flat.size, _ptr(flat, C.c_double)))
+    out["best"] = best
+    out["best_score"] = float(flat[best]) if best >= 0 else float("-inf")
+    return out
+
+
+def ray_eval(frame, params, n_dirs: int, w_time: float, w_refract: float, direction: int,
+             vtype: int, v0: float, bands: bool = False, **band_eps):
+    """One (direction, variant): every field of the oracle's result."""
+    L = lib()
+    P = make_params(params, **band_eps)
+    R = _ray_params(n_dirs, w_time, w_refract)
+    wh = _WorldHolder(frame)
+    r = OrcRayResult()
+    L.orc_ray_eval(C.byref(P), C.byref(R), C.byref(wh.w), direction, vtype, v0, int(bands),
+                   C.byref(r))
+    return {k: getattr(r, k) for k, _ in OrcRayResult._fields_}
