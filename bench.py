@@ -121,6 +121,73 @@ def batch_bench(n_frames: int, steps: int, tune_cache: str, st):
     return rec
 
 
+def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
+    """The paper's own DPPS form: 8v8 frames, 128 kick directions x 64 flat
+    powers in [1, 6.5] m/s, K = 256 samples per ray.  Batched: n_frames frames
+    per call (host inputs staged by the library), timed over `steps` calls;
+    latency: one frame per call, host inputs to the best pass on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07717_amd import binding as Bn
+    from paper_1909_07717_amd import flops as FL
+    from paper_1909_07717_amd.framegen import Params, random_frame, speeds_linear, variants_for
+
+    n_dirs, speeds = 128, 64
+    p = Params(n_samples=256).as_f32()
+    var = variants_for(speeds_linear(speeds), flat=True, chip=False)
+    frames = []
+    for i in range(n_frames):
+        f = random_frame(np.random.default_rng(500 + i), 8, 8, Params())
+        f.variants = var
+        frames.append(f)
+    s = Bn.Searcher(p, device=0)
+    pk = Bn.pack(frames, p)
+    with torch.cuda.stream(st):
+        out = s.ray_search(pk, n_dirs, stream=st)
+    torch.cuda.synchronize()
+    n_feas = out.mask.view(n_frames, -1).sum(1).cpu().numpy()
+    evals = fl = 0
+    for f, nf in zip(frames, n_feas):
+        e, x = FL.ray_frame_work(f, p.n_samples, n_dirs, int(nf))
+        evals += e
+        fl += x
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            s.ray_search(pk, n_dirs, stream=st, out=out)
+        e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # latency, one frame at a time
+    one = s.ray_search(frames[:1], n_dirs, stream=st, mask=False, score=False, times=False,
+                       recv=False)
+    host = torch.empty(Bn.RAY_BEST_DT.itemsize, dtype=torch.uint8, pin_memory=True)
+    lat = []
+    for i in range(100 + lat_frames):
+        a = time.perf_counter()
+        with torch.cuda.stream(st):
+            s.ray_search([frames[i % n_frames]], n_dirs, stream=st, out=one)
+            host.copy_(one.best[:Bn.RAY_BEST_DT.itemsize], non_blocking=True)
+        st.synchronize()
+        if i >= 100:
+            lat.append(time.perf_counter() - a)
+    lat = np.array(lat) * 1e3
+    s.close()
+    return {"workload": f"{n_frames} frames of 8v8, {n_dirs} directions x {speeds} flat powers "
+                        f"1.0-6.5 m/s, K = 256 samples per ray",
+            "evals_per_call": evals, "ms_per_call": round(ms, 4),
+            "frames_per_s": round(n_frames / (ms * 1e-3), 1),
+            "pass_evals_per_s": round(evals / (ms * 1e-3), 1),
+            "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+            "feasible_fraction": round(float(n_feas.sum()) / (n_frames * n_dirs * speeds), 4),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                           "p99": round(float(np.percentile(lat, 99)), 4),
+                           "frames": int(lat.size),
+                           "path": "one frame per call, host inputs to the best pass on the host"}}
+
+
 def surrogate_bench(frames: int, weights: str, lat_frames: int = 10000):
     """Surrogate + top-64 exact re-score (5 cm) against the exact 5 cm search
     on 6v6 frames with one flat pass at 4 m/s, K = 64 (the network's
@@ -131,6 +198,8 @@ def surrogate_bench(frames: int, weights: str, lat_frames: int = 10000):
     res = evaluate(weights, frames, k=64, batch=min(frames, 1024))
     res["speedup_vs_exact"] = res["surrogate_frames_per_s"] / res["exact_frames_per_s"]
     res["latency_ms"] = latency(weights, frames=lat_frames)
+    from paper_1909_07717_amd.profiling import mlp_timing
+    res["mlp"] = mlp_timing(4096, 20)
     return res
 
 
@@ -166,6 +235,7 @@ def main() -> int:
     ap.add_argument("--latency-frames", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ray-frames", type=int, default=512)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -242,6 +312,8 @@ def main() -> int:
     batch = None
     if args.batch_frames > 0:
         batch = batch_bench(args.batch_frames, args.batch_steps, args.tune_cache, st)
+    rays = (ray_bench(args.ray_frames, 5, min(args.latency_frames, 2000), st)
+            if args.ray_frames > 0 else None)
     sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
            if args.surrogate_frames > 0 else None)
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
@@ -272,6 +344,7 @@ def main() -> int:
                        "frames": int(lat.size), "path": "exact, dpps_search from host inputs"},
         "graph_ms_per_step": round(graph_ms, 5),
         "batch": batch,
+        "rays": rays,
         "surrogate": sur,
         "serving": serving,
     }

@@ -291,6 +291,61 @@ int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
                                  int32_t k, dpps_best *d_best, int fallback, float fallback_below,
                                  int32_t *n_fallback, void *hip_stream);
 
+/* ---- the paper's direction x power form (Sec. 4.2) ----------------------
+ * The search as the paper states it, from the passer's point of view: for
+ * every kick direction theta_d = 2 pi d / n_dirs (d = 0 .. n_dirs-1, from +x,
+ * counterclockwise) and every pass variant of a frame, the ball runs from the
+ * ball position along the direction until it stops or leaves the field.  K
+ * samples uniform in distance over the part of the ray inside the field,
+ * s_k = (k+1) L / K, are shared by all variants; a variant uses the samples
+ * its ball reaches (chips: from the landing point on).  Each robot's
+ * interception is searched as in dpps_search (Sec. 4.2); the pass is
+ * received at the first teammate's interception, the passing point, and is
+ * feasible when the first opponent intercepts at least margin_s later, or
+ * never.  Its score is Eq. (3) over the five features of Sec. 4.3:
+ *   w_angle * open goal angle at the passing point / pi
+ *   + w_dist * (1 - distance from the passing point to the goal centre / dist_norm)
+ *   + w_margin * clamp(t_opp - t_team, 0, margin_cap_s)
+ *   - w_time * t_team (seconds)
+ *   - w_refract * refraction angle / pi,
+ * the refraction angle being the angle between the ball's direction and the
+ * shot from the passing point to the goal centre.  The frames' windows are
+ * not used (n_windows is ignored). */
+typedef struct {
+    int32_t n_dirs;   /* 1 .. 4096 (the paper: 128, 360/128 = 2.8 degrees) */
+    float w_time;     /* weight per second of the first teammate's interception time (>= 0) */
+    float w_refract;  /* weight of the refraction angle / pi (>= 0) */
+    int32_t reserved; /* must be 0 */
+} dpps_ray_params;
+
+/* The best pass of a frame: largest score, ties to the lowest (direction,
+ * variant) index d * n_variants + v.  found = 0 when none is feasible. */
+typedef struct {
+    int32_t found, dir, variant, type;
+    float theta, v0, x, y; /* direction (rad), kick speed, passing point */
+    float score, t_team, t_opp, open_angle, refract;
+    int32_t pad;
+} dpps_ray_best;
+
+/* Device outputs of dpps_ray_search.  Element (f, d, v) sits at
+ * base(f) + d * n_variants(f) + v, base(f) being the sum of n_dirs *
+ * n_variants over the frames before f.  Any map pointer may be NULL. */
+typedef struct {
+    uint8_t *mask;   /* 1 where the pass is feasible */
+    float *score;    /* score where feasible, -inf elsewhere */
+    float *t_team;   /* first teammate interception (ball) time, +inf if none */
+    float *t_opp;    /* first opponent interception time, +inf if none */
+    float *s_recv;   /* distance along the ray to the passing point, +inf if none */
+    dpps_ray_best *best; /* one record per frame (required) */
+} dpps_ray_outputs;
+
+/* Every direction x variant of n_frames frames, asynchronous on the stream
+ * (inputs are host arrays staged through the context, as for
+ * dpps_search_batch). */
+int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                    const dpps_robot *robots, const dpps_variant *variants,
+                    const dpps_ray_params *rp, const dpps_ray_outputs *out, void *hip_stream);
+
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);
 int dpps_version(void);

@@ -36,6 +36,11 @@ BEST_DT = np.dtype([("found", "<i4"), ("window", "<i4"), ("variant", "<i4"), ("i
                     ("score", "<f4"), ("t_team", "<f4"), ("t_opp", "<f4"), ("t_ball", "<f4"),
                     ("pad", "<i4")])
 
+RAY_BEST_DT = np.dtype([("found", "<i4"), ("dir", "<i4"), ("variant", "<i4"), ("type", "<i4"),
+                        ("theta", "<f4"), ("v0", "<f4"), ("x", "<f4"), ("y", "<f4"),
+                        ("score", "<f4"), ("t_team", "<f4"), ("t_opp", "<f4"),
+                        ("open_angle", "<f4"), ("refract", "<f4"), ("pad", "<i4")])
+
 
 class DppsError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -56,6 +61,16 @@ class Params_C(C.Structure):
 class Outputs_C(C.Structure):
     _fields_ = [("mask", C.c_void_p), ("score", C.c_void_p), ("t_team", C.c_void_p),
                 ("t_opp", C.c_void_p), ("best", C.c_void_p)]
+
+
+class RayParams_C(C.Structure):
+    _fields_ = [("n_dirs", C.c_int32), ("w_time", C.c_float), ("w_refract", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class RayOutputs_C(C.Structure):
+    _fields_ = [("mask", C.c_void_p), ("score", C.c_void_p), ("t_team", C.c_void_p),
+                ("t_opp", C.c_void_p), ("s_recv", C.c_void_p), ("best", C.c_void_p)]
 
 
 _lib = None
@@ -113,6 +128,8 @@ def lib():
                                             C.POINTER(i32), vp]
         L.dpps_surrogate_search_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp, i32, vp, C.c_int,
                                                    C.c_float, C.POINTER(i32), vp]
+        L.dpps_ray_search.argtypes = [vp, i32, vp, vp, vp, C.POINTER(RayParams_C),
+                                      C.POINTER(RayOutputs_C), vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
         L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
@@ -184,7 +201,9 @@ def pack(frames, p, out_flags: int = 0) -> Packed:
     variants = np.array(var, VARIANT_DT) if var else np.zeros(0, VARIANT_DT)
     total = C.c_int64()
     pc = params_c(p, out_flags)
-    _check(lib().dpps_layout(C.byref(pc), nf, _ptr(fr), _ptr(windows), C.byref(total)))
+    # frames without windows (direction x variant searches) still pass a valid array
+    wl = windows if windows.size else np.zeros(1, WINDOW_DT)
+    _check(lib().dpps_layout(C.byref(pc), nf, _ptr(fr), _ptr(wl), C.byref(total)))
     ends = np.append(fr["out_off"][1:], total.value) if nf else np.zeros(0, np.int64)
     return Packed(fr, robots, windows, variants, int(total.value),
                   (ends - fr["out_off"]).astype(np.int64) if nf else ends)
@@ -218,6 +237,33 @@ class DeviceOutputs:
 
     def best_host(self) -> np.ndarray:
         return np.frombuffer(self.best.cpu().numpy().tobytes(), BEST_DT)
+
+
+class RayDeviceOutputs:
+    """torch tensors for the outputs of a direction x variant search:
+    [sum over frames of n_dirs * n_variants] maps and one record per frame."""
+
+    def __init__(self, total: int, n_frames: int, device, mask=True, score=True, times=True,
+                 recv=True):
+        import torch
+        f32 = dict(dtype=torch.float32, device=device)
+        self.mask = torch.empty(total, dtype=torch.uint8, device=device) if mask else None
+        self.score = torch.empty(total, **f32) if score else None
+        self.t_team = torch.empty(total, **f32) if times else None
+        self.t_opp = torch.empty(total, **f32) if times else None
+        self.s_recv = torch.empty(total, **f32) if recv else None
+        self.best = torch.empty(max(n_frames, 1) * RAY_BEST_DT.itemsize, dtype=torch.uint8,
+                                device=device)
+
+    def c(self) -> RayOutputs_C:
+        o = RayOutputs_C()
+        o.mask, o.score = _tptr(self.mask), _tptr(self.score)
+        o.t_team, o.t_opp, o.s_recv = _tptr(self.t_team), _tptr(self.t_opp), _tptr(self.s_recv)
+        o.best = _tptr(self.best)
+        return o
+
+    def best_host(self) -> np.ndarray:
+        return np.frombuffer(self.best.cpu().numpy().tobytes(), RAY_BEST_DT)
 
 
 def _stream_ptr(stream):
@@ -273,6 +319,24 @@ class Searcher:
         _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
                                  _ptr(pk.variants), C.byref(oc), best.ctypes.data))
         return out, best[0]
+
+    def ray_search(self, frames, n_dirs: int = 128, w_time: float = 0.05, w_refract: float = 0.1,
+                   mask=True, score=True, times=True, recv=True, stream=None, out=None):
+        """The paper's direction x variant search of framegen frames (or a
+        Packed request), asynchronous on the stream.  Returns RayDeviceOutputs;
+        frame f's maps are [n_dirs][n_variants] starting at the sum of
+        n_dirs * n_variants over the frames before it."""
+        pk = frames if isinstance(frames, Packed) else pack(frames, self.params, self.out_flags)
+        nf = len(pk.frames)
+        total = int(n_dirs * pk.frames["n_variants"].astype(np.int64).sum())
+        if out is None:
+            out = RayDeviceOutputs(total, nf, self.device, mask, score, times, recv)
+        rp = RayParams_C(int(n_dirs), float(w_time), float(w_refract), 0)
+        oc = out.c()
+        _check(lib().dpps_ray_search(self.h, nf, _ptr(pk.frames), _ptr(pk.robots),
+                                     _ptr(pk.variants), C.byref(rp), C.byref(oc),
+                                     _stream_ptr(stream)))
+        return out
 
     def search_batch(self, frames, mask=True, score=True, times=False, stream=None, out=None):
         """Many frames, asynchronous on the stream.  Returns (Packed, DeviceOutputs)."""
@@ -427,12 +491,15 @@ class Mlp:
                                    _stream_ptr(stream)))
 
     def train_step(self, batch: "Batch", target, lr: float, pos_weight: float = 0.0,
-                   ce_weight: float = 0.0, tau: float = 0.02, stream=None) -> float:
+                   ce_weight: float = 0.0, tau: float = 0.02, stream=None, want_loss=True):
+        """One training step; returns the loss (synchronises), or None with
+        want_loss=False (stays asynchronous on the stream)."""
         loss = C.c_float()
         _check(lib().dpps_mlp_train_step(self.h, batch.h, target.data_ptr(), target.stride(0), lr,
-                                         pos_weight, ce_weight, tau, C.byref(loss),
+                                         pos_weight, ce_weight, tau,
+                                         C.byref(loss) if want_loss else None,
                                          _stream_ptr(stream)))
-        return float(loss.value)
+        return float(loss.value) if want_loss else None
 
     def features(self, batch: "Batch", stream=None):
         """bfloat16 network inputs [n_frames][66] as a float32 torch tensor."""

@@ -77,6 +77,8 @@ DevParams derive(const dpps_params *p)
     memset(&P, 0, sizeof P);
     double A = p->amax, V = p->vmax, as = p->slide_decel, ar = p->roll_decel;
     double rho = p->slide_ratio, th = p->chip_angle, g = p->gravity;
+    P.field_len = p->field_len;
+    P.field_wid = p->field_wid;
     P.goal_x = p->goal_x;
     P.half_goal_w = 0.5f * p->goal_width;
     P.goal_eps = p->goal_eps;
@@ -459,6 +461,7 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
     c->device = device;
     c->scratch.ctx = c;
     c->fallback.ctx = c;
+    c->rays.ctx = c;
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return fail(DPPS_E_DEVICE, "hipSetDevice(%d) failed", device);
@@ -503,6 +506,8 @@ void dpps_destroy(dpps_ctx *c)
     ring_free(c);
     batch_free_device(&c->scratch);
     batch_free_device(&c->fallback);
+    batch_free_device(&c->rays);
+    if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staged) (void)hipEventDestroy(c->staged);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -590,6 +595,14 @@ int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *
     if (rc) return rc;
     b->n_frames = n_frames;
     b->tile_points = c->tile_points;
+    return stage_tables(c, b, st);
+}
+
+// Copy the host tables already in b->T to the batch's device memory through
+// the pinned staging buffer (asynchronous on st).
+int stage_tables(dpps_ctx *c, dpps_batch *b, hipStream_t st)
+{
+    int rc;
     graph_drop(b);
     Layout L = table_layout(b->T);
     // the previous call's copy must have left the pinned buffer
@@ -625,6 +638,82 @@ int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     int rc = stage_batch(c, &c->scratch, n_frames, frames, robots, windows, variants, st);
     if (rc) return rc;
     return run_batch(c, &c->scratch, out, st, true);
+}
+
+int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                    const dpps_robot *robots, const dpps_variant *variants,
+                    const dpps_ray_params *rp, const dpps_ray_outputs *out, void *hip_stream)
+{
+    if (!c || !rp || !out || !out->best) return fail(DPPS_E_INVALID, "NULL argument");
+    if (rp->n_dirs < 1 || rp->n_dirs > 4096) return fail(DPPS_E_INVALID, "n_dirs must be in [1, 4096]");
+    if (!(rp->w_time >= 0.0f) || !isfinite(rp->w_time) || !(rp->w_refract >= 0.0f) ||
+        !isfinite(rp->w_refract) || rp->reserved != 0)
+        return fail(DPPS_E_INVALID, "ray weights must be finite and >= 0, reserved 0");
+    if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (n_frames == 0) return DPPS_OK;
+    if (!frames) return fail(DPPS_E_INVALID, "NULL input array");
+    // validate as for dpps_search_batch, the windows aside
+    std::vector<dpps_frame> fr(frames, frames + n_frames);
+    for (dpps_frame &F : fr) {
+        F.n_windows = 0;
+        F.window_off = 0;
+        F.out_off = 0;
+    }
+    const dpps_window no_window = {0.0f, 0, 0, 0, 0};
+    dpps_batch *b = &c->rays;
+    int rc = build_tables(&c->p, n_frames, fr.data(), robots, &no_window, variants, c->tile_points,
+                          b->T);
+    if (rc) return rc;
+    // tiles of ray_tile_dirs directions of one frame; outputs frame by frame
+    const int td = c->ray_tile_dirs;
+    b->T.tiles.clear();
+    int64_t base = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        FrameDev &F = b->T.frames[f];
+        F.tile_begin = (int32_t)b->T.tiles.size();
+        for (int d0 = 0; d0 < rp->n_dirs; d0 += td) b->T.tiles.push_back({f, d0});
+        F.tile_count = (int32_t)b->T.tiles.size() - F.tile_begin;
+        F.ray_base = base;
+        base += (int64_t)rp->n_dirs * F.n_variants;
+    }
+    b->n_frames = n_frames;
+    b->tile_points = c->tile_points;
+    rc = stage_tables(c, b, st);
+    if (rc) return rc;
+    const size_t nt = b->T.tiles.size();
+    void *old = c->ray_aux.ptr;
+    rc = arena_reserve(c, c->ray_aux, 256 + nt * sizeof(RayRec));
+    if (rc) return rc;
+    // a fresh allocation starts with the work counter at zero; afterwards the
+    // finalize kernel rearms it at the end of every launch
+    if (c->ray_aux.ptr != old) HIP_OK(hipMemset(c->ray_aux.ptr, 0, 256));
+    RayArgs a;
+    memset(&a, 0, sizeof a);
+    a.P = c->P;
+    a.frames = b->d_frames;
+    a.robots = b->d_robots;
+    a.variants = b->d_variants;
+    a.tiles = b->d_tiles;
+    a.n_tiles = (int32_t)nt;
+    a.n_frames = n_frames;
+    a.tile_dirs = td;
+    a.n_dirs = rp->n_dirs;
+    a.w_time = rp->w_time;
+    a.w_refract = rp->w_refract;
+    a.counter = (uint32_t *)c->ray_aux.ptr;
+    a.tile_rec = (RayRec *)((char *)c->ray_aux.ptr + 256);
+    a.mask = out->mask;
+    a.score = out->score;
+    a.t_team = out->t_team;
+    a.t_opp = out->t_opp;
+    a.s_recv = out->s_recv;
+    a.best = out->best;
+    const int64_t cap = (int64_t)c->n_cu * ray_occupancy(c->p.n_samples, c->waves);
+    const int grid = (int)((int64_t)nt < cap ? (int64_t)nt : cap);
+    if (launch_ray(a, c->waves, grid, (void *)st)) return fail(DPPS_E_DEVICE, "ray launch failed");
+    return DPPS_OK;
 }
 
 int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,

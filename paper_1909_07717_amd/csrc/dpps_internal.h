@@ -13,6 +13,7 @@ namespace dpps {
 // coefficients that invert the ball model for the critical kick speed.
 struct DevParams {
     // geometry
+    float field_len, field_wid;
     float goal_x, half_goal_w, goal_eps;
     float R, RA;       // robot radius, and scaled by amax
     float V, A, invV;
@@ -65,6 +66,7 @@ struct FrameDev {
     int32_t n_windows, win_off, n_variants, variant_off;
     float ball_x, ball_y;
     int32_t tile_begin, tile_count;
+    int64_t ray_base;       // direction x variant search: first output element
 };
 
 struct LaunchArgs {
@@ -87,11 +89,41 @@ struct LaunchArgs {
     dpps_best *best;
 };
 
+// Best pass of one tile of the direction x variant search.
+struct RayRec {
+    unsigned long long key;  // ordered score bits << 32 | ~(d * n_variants + v)
+    float t_team, t_opp, s_recv, open_angle, refract, pad;
+};
+
+struct RayArgs {
+    DevParams P;
+    const FrameDev *frames;
+    const dpps_robot *robots;
+    const dpps_variant *variants;
+    const TileDev *tiles;   // win = frame, p0 = first direction of the tile
+    int32_t n_tiles;
+    int32_t n_frames;
+    int32_t tile_dirs;
+    int32_t n_dirs;
+    float w_time, w_refract;
+    uint32_t *counter;      // persistent work counter; the finalize kernel resets it
+    RayRec *tile_rec;
+    uint8_t *mask;
+    float *score;
+    float *t_team;
+    float *t_opp;
+    float *s_recv;
+    dpps_ray_best *best;
+};
+
 // host-side launchers (dpps_kernels.hip)
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the search kernel only.
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                   void *ev_stop);
 // Resident workgroups per CU of the search kernel for this K and block size.
 int search_occupancy(int K, int waves_per_wg);
+// Direction x variant search (ray kernel then its finalize) on `stream`.
+int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream);
+int ray_occupancy(int K, int waves_per_wg);
 
 }  // namespace dpps

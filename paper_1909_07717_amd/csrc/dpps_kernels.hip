@@ -111,14 +111,14 @@ __device__ VarConst var_const(const DevParams &P, int type, float v0f)
 // Stage the frame into LDS: interceptors (passer dropped), scaled by amax so
 // that the robot model runs in units where the acceleration limit is 1; the
 // per-variant ball constants in float64.  Called by all threads of a block.
-__device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
+__device__ void stage_frame(const DevParams &P, const FrameDev *frames, const dpps_robot *robots,
+                            const dpps_variant *variants, int f, StageLDS &S)
 {
-    const DevParams &P = a.P;
-    const FrameDev F = a.frames[f];
+    const FrameDev F = frames[f];
     int tid = threadIdx.x;
     int nrob = F.n_team + F.n_opp;
     if (tid < nrob) {
-        dpps_robot r = a.robots[F.robot_off + tid];
+        dpps_robot r = robots[F.robot_off + tid];
         int slot;
         if (tid < F.n_team) {
             slot = tid < F.passer ? tid : tid - 1;
@@ -130,10 +130,10 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
     if (tid < F.n_variants) {
         // staged in order of kick type, then speed (stable): within a type
         // the first crossing never moves earlier as the speed grows
-        const dpps_variant v = a.variants[F.variant_off + tid];
+        const dpps_variant v = variants[F.variant_off + tid];
         int rank = 0;
         for (int j = 0; j < F.n_variants; ++j) {
-            const dpps_variant u = a.variants[F.variant_off + j];
+            const dpps_variant u = variants[F.variant_off + j];
             rank += u.type < v.type ||
                     (u.type == v.type && (u.v0 < v.v0 || (u.v0 == v.v0 && j < tid)));
         }
@@ -148,7 +148,7 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
         S.n_var = F.n_variants;
         int hf = 0, hc = 0;
         for (int v = 0; v < F.n_variants; ++v) {
-            int t = a.variants[F.variant_off + v].type;
+            int t = variants[F.variant_off + v].type;
             hf |= t == DPPS_FLAT;
             hc |= t == DPPS_CHIP;
         }
@@ -156,7 +156,7 @@ __device__ void stage_frame(const LaunchArgs &a, int f, StageLDS &S)
         S.has_chip = hc;
         int ok = 1;
         for (int r = 0; r < nrob; ++r) {
-            const dpps_robot R = a.robots[F.robot_off + r];
+            const dpps_robot R = robots[F.robot_off + r];
             ok &= fmaf(R.vx, R.vx, R.vy * R.vy) <= P.V * P.V;
         }
         S.vel_ok = ok;
@@ -216,26 +216,16 @@ __device__ __forceinline__ void robot_stage(const float4 *pr, const DevParams &P
     }
 }
 
-// Path frame of candidate point c for the staged robots (lanes = robots),
-// in float64 and then rounded once: for robot j with offset a = ball - x_j,
-// path direction e = (c - ball) / |c - ball| and normal n = (-e_y, e_x):
-// t = -a.e and q = a.n (scaled by amax), w = velocity / sqrt(2), and pr[j] =
-// (t, q^2, w.e, q w.n).  A point on the ball gets e = (1, 0); it is never
-// reachable.  1 / |c - ball| is the hardware estimate refined by one Newton
-// step (relative error far below the float32 rounding that follows).
-// Returns |c - ball| A.
-__device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &P, float4 *pr,
-                                            int n_rob, double cx64, double cy64, double bx,
-                                            double by)
+// Path frame of a ball path along the unit direction e = (ux, uy) for the
+// staged robots (lanes = robots), in float64 and then rounded once: for robot
+// j with offset a = ball - x_j and normal n = (-e_y, e_x): t = -a.e and
+// q = a.n (scaled by amax), w = velocity / sqrt(2), and pr[j] =
+// (t, q^2, w.e, q w.n).
+__device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParams &P, float4 *pr,
+                                               int n_rob, double ux, double uy, double bx,
+                                               double by)
 {
     const int l = lane_id();
-    const double ex = cx64 - bx, ey = cy64 - by;
-    const double L2 = ex * ex + ey * ey;
-    double iL = __builtin_amdgcn_rsq(L2);
-    iL = iL * (1.5 - 0.5 * L2 * iL * iL);
-    const bool pos = L2 > 0.0;
-    const double L = pos ? L2 * iL : 0.0;
-    const double ux = pos ? ex * iL : 1.0, uy = pos ? ey * iL : 0.0;
     if (l < n_rob) {
         const float4 r = S.rob[l];
         const double A = (double)P.A;
@@ -250,6 +240,25 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same for the path from the ball to candidate point c: e = (c - ball) /
+// |c - ball| (a point on the ball gets e = (1, 0); it is never reachable).
+// 1 / |c - ball| is the hardware estimate refined by one Newton step
+// (relative error far below the float32 rounding that follows).  Returns
+// |c - ball| A.
+__device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &P, float4 *pr,
+                                            int n_rob, double cx64, double cy64, double bx,
+                                            double by)
+{
+    const double ex = cx64 - bx, ey = cy64 - by;
+    const double L2 = ex * ex + ey * ey;
+    double iL = __builtin_amdgcn_rsq(L2);
+    iL = iL * (1.5 - 0.5 * L2 * iL * iL);
+    const bool pos = L2 > 0.0;
+    const double L = pos ? L2 * iL : 0.0;
+    const double ux = pos ? ex * iL : 1.0, uy = pos ? ey * iL : 0.0;
+    path_frame_dir(S, P, pr, n_rob, ux, uy, bx, by);
     return (float)(L * (double)P.A);
 }
 
@@ -421,17 +430,20 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
 // Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
 // hold lane v's variant (lanes >= n_var: type -1).  On return lane v
 // (< n_var) holds that variant's results.
+// SBIP of every staged variant along one path of length d (metres; LA = d
+// scaled by amax) whose path frame is in pr: robot stage over the lane's
+// samples (lanes = samples), critical speeds, first crossings through xr.  On
+// return lane v (a staged variant) holds its first team / opponent crossing
+// samples (K: none).
 template <int KPL>
-__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
-                           float myv0, int mytype, float cx, float cy, double cx64,
-                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to)
+__device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParams &P,
+                                               const float4 *pr, uint32_t *xr, float myv0,
+                                               int mytype, float d, float LA, int &my_kt,
+                                               int &my_ko)
 {
     const int l = lane_id();
     const int K = KPL * 64;
-    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
-    const float bx = unif(S.bx), by = unif(S.by);
-    const float ex = cx - bx, ey = cy - by;
-    const float d = hsqrt(fmaf(ex, ex, ey * ey));
+    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op);
     const float invK = 1.0f / (float)K;
     const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
     const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
@@ -444,8 +456,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
         Tt[q] = INFINITY;
         To[q] = INFINITY;
     }
-    // 1. robot stage, in the path frame of the point
-    const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
+    // 1. robot stage, in the path frame
     if (uni(S.vel_ok)) {
         robot_stage<KPL, false>(pr, P, 0, n_tm, fs, LA, Tt);
         robot_stage<KPL, false>(pr, P, n_tm, n_op, fs, LA, To);
@@ -478,12 +489,32 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int my_kt = K, my_ko = K;
+    my_kt = K;
+    my_ko = K;
     if ((mytype == DPPS_FLAT) | (mytype == DPPS_CHIP)) {
         const uint32_t x = xr[l];
         my_kt = (int)(x & 0xFFFFu);
         my_ko = (int)(x >> 16);
     }
+}
+
+// Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
+// hold lane v's variant (lanes >= n_var: type -1).  On return lane v
+// (< n_var) holds that variant's results.
+template <int KPL>
+__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
+                           float myv0, int mytype, float cx, float cy, double cx64,
+                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to)
+{
+    const int l = lane_id();
+    const int K = KPL * 64;
+    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
+    const float bx = unif(S.bx), by = unif(S.by);
+    const float ex = cx - bx, ey = cy - by;
+    const float d = hsqrt(fmaf(ex, ex, ey * ey));
+    const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
+    int my_kt, my_ko;
+    sbip_crossings<KPL>(S, P, pr, xr, myv0, mytype, d, LA, my_kt, my_ko);
     // open goal angle (lanes = opponents)
     const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
     // 4. finish: lanes = variants
@@ -552,7 +583,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         const WinDev W = a.wins[tile.win];
         if (W.frame != cur_frame) {
             __syncthreads();
-            stage_frame(a, W.frame, S);
+            stage_frame(a.P, a.frames, a.robots, a.variants, W.frame, S);
             __syncthreads();
             cur_frame = W.frame;
             const int nv = S.n_var;
@@ -714,6 +745,303 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
     if (a.n_frames > 0)
         hipLaunchKernelGGL(finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ----------------------------------------------------------------------------
+// The paper's direction x power form (Sec. 4.2): rays from the ball, the pass
+// received at the first teammate's interception, five-feature score.
+// ----------------------------------------------------------------------------
+
+// Order-preserving map of a float's bits to an unsigned key (negative scores
+// order below positive ones).
+__device__ __forceinline__ uint32_t ordered_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return u ^ ((u & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u);
+}
+
+__device__ __forceinline__ float unordered_bits(uint32_t k)
+{
+    return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
+}
+
+// Distance from the ball along (ux, uy) to the edge of the field (0 when the
+// ray leaves at once).
+__device__ __forceinline__ double ray_length(const DevParams &P, double bx, double by,
+                                             double ux, double uy)
+{
+    const double hl = 0.5 * (double)P.field_len, hw = 0.5 * (double)P.field_wid;
+    double L = INFINITY;
+    if (ux > 0.0) L = fmin(L, (hl - bx) / ux);
+    if (ux < 0.0) L = fmin(L, (-hl - bx) / ux);
+    if (uy > 0.0) L = fmin(L, (hw - by) / uy);
+    if (uy < 0.0) L = fmin(L, (-hw - by) / uy);
+    return L > 0.0 ? L : 0.0;
+}
+
+struct RayOut {
+    unsigned long long key;  // 0: not feasible
+    float score, t_team, t_opp, s_recv, open_angle, refract;
+    int feas;
+};
+
+// Every staged variant (lanes) for direction d of the staged frame.
+template <int KPL>
+__device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
+                                float myv0, int mytype, int myvid, int d, int n_dirs,
+                                float w_time, float w_refract)
+{
+    const int l = lane_id();
+    const int K = KPL * 64;
+    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
+    const double bx = (double)unif(S.bx), by = (double)unif(S.by);
+    const double xd = 2.0 * (double)d / (double)n_dirs;  // theta_d / pi
+    const double ux = cospi(xd), uy = sinpi(xd);
+    const double L = ray_length(P, bx, by, ux, uy);
+    path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, bx, by);
+    int my_kt, my_ko;
+    sbip_crossings<KPL>(S, P, pr, xr, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
+                        my_ko);
+
+    RayOut o;
+    o.key = 0ull;
+    o.score = -INFINITY;
+    o.t_team = INFINITY;
+    o.t_opp = INFINITY;
+    o.s_recv = INFINITY;
+    o.open_angle = 0.0f;
+    o.refract = 0.0f;
+    o.feas = 0;
+    double px = 0.0, py = 0.0, m = -INFINITY;
+    if (l < n_var) {
+        // a crossing counts only where the ball gets to (within its stop)
+        const VarConst c = S.vc[l];
+        const double st = (double)(my_kt + 1) * P.invK_d * L;
+        const double so = (double)(my_ko + 1) * P.invK_d * L;
+        const double tt = (my_kt < K && st <= c.D) ? ball_time64(c, st) : INFINITY;
+        const double to = (my_ko < K && so <= c.D) ? ball_time64(c, so) : INFINITY;
+        const bool tfin = tt < INFINITY;
+        m = !tfin ? -INFINITY : (to < INFINITY ? to - tt : INFINITY);
+        o.feas = tfin && m >= P.margin_d;
+        o.t_team = (float)tt;
+        o.t_opp = (float)to;
+        o.s_recv = tfin ? (float)st : INFINITY;
+        px = bx + st * ux;
+        py = by + st * uy;
+    }
+    // open goal angle at each feasible passing point (lanes = opponents), once
+    // per distinct passing sample
+    const unsigned long long fm = __ballot(o.feas != 0);
+    float ang = 0.0f, my_ang = 0.0f;
+    int last_k = -1;
+    for (unsigned long long mm = fm; mm; mm &= mm - 1) {
+        const int v = __builtin_ctzll(mm);
+        const int kv = readlane_i(my_kt, v);
+        if (kv != last_k) {
+            const float pxv = __int_as_float(readlane_i(__float_as_int((float)px), v));
+            const float pyv = __int_as_float(readlane_i(__float_as_int((float)py), v));
+            ang = open_angle(S, P, pxv, pyv, n_op, n_tm);
+            last_k = kv;
+        }
+        my_ang = l == v ? ang : my_ang;
+    }
+    if (o.feas) {
+        const double gx = (double)P.goal_x - px, gy = -py;
+        const float dg = (float)sqrt(gx * gx + gy * gy);
+        const float refr = dg > 0.0f ? atan2f((float)fabs(ux * gy - uy * gx), (float)(ux * gx + uy * gy))
+                                     : 0.0f;
+        const float mc = fminf(fmaxf((float)m, 0.0f), P.margin_cap);
+        const float sc = fmaf(P.w_ang_pi, my_ang,
+                              fmaf(P.w_dist, fmaf(-dg, P.inv_dist_norm, 1.0f),
+                                   fmaf(P.w_margin, mc,
+                                        fmaf(-w_time, o.t_team, -w_refract * refr * 0.318309886183790672f))));
+        o.score = sc;
+        o.open_angle = my_ang;
+        o.refract = refr;
+        const uint32_t lin = (uint32_t)(d * n_var + myvid);
+        o.key = ((unsigned long long)ordered_bits(sc) << 32) | (unsigned long long)(0xFFFFFFFFu - lin);
+    }
+    return o;
+}
+
+template <int KPL>
+__global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
+{
+    __shared__ StageLDS S;
+    __shared__ float4 PR[MAX_WAVES][MAX_ROB];
+    __shared__ uint32_t XR[MAX_WAVES][64];
+    __shared__ RayRec WB[MAX_WAVES];
+    __shared__ int s_tile;
+    const DevParams &P = a.P;
+    const int nw = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6;
+    const int l = lane_id();
+    int cur_frame = -1;
+    float myv0 = 0.0f;
+    int mytype = -1, myvid = 0;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= a.n_tiles) break;
+        const TileDev tile = a.tiles[t];
+        const int f = tile.win;
+        if (f != cur_frame) {
+            __syncthreads();
+            stage_frame(a.P, a.frames, a.robots, a.variants, f, S);
+            __syncthreads();
+            cur_frame = f;
+            const int nv = S.n_var;
+            myv0 = l < nv ? S.v0[l] : 0.0f;
+            mytype = l < nv ? S.type[l] : -1;
+            myvid = l < nv ? S.vidx[l] : 0;
+        } else {
+            __syncthreads();
+        }
+        const int n_var = S.n_var;
+        const int64_t base = a.frames[f].ray_base;
+        const int nd = min(a.tile_dirs, a.n_dirs - tile.p0);
+        RayRec best;
+        best.key = 0ull;
+        best.t_team = best.t_opp = best.s_recv = INFINITY;
+        best.open_angle = best.refract = best.pad = 0.0f;
+        for (int slot = w; slot < nd; slot += nw) {
+            const int d = tile.p0 + slot;
+            const RayOut o = ray_direction<KPL>(S, P, PR[w], XR[w], myv0, mytype, myvid, d,
+                                                a.n_dirs, a.w_time, a.w_refract);
+            if (l < n_var) {
+                const int64_t e = base + (int64_t)d * n_var + myvid;
+                if (a.mask) a.mask[e] = (uint8_t)o.feas;
+                if (a.score) a.score[e] = o.score;
+                if (a.t_team) a.t_team[e] = o.t_team;
+                if (a.t_opp) a.t_opp[e] = o.t_opp;
+                if (a.s_recv) a.s_recv[e] = o.s_recv;
+            }
+            if (o.key > best.key) {
+                best.key = o.key;
+                best.t_team = o.t_team;
+                best.t_opp = o.t_opp;
+                best.s_recv = o.s_recv;
+                best.open_angle = o.open_angle;
+                best.refract = o.refract;
+            }
+        }
+        // the wave's best, then the tile's
+        const unsigned long long wk = wave_max_u64(best.key);
+        const unsigned long long who = __ballot(best.key == wk);
+        const int src = who ? __builtin_ctzll(who) : 0;
+        if (l == 0) WB[w].key = wk;
+        const float r0 = readlane_f(best.t_team, src), r1 = readlane_f(best.t_opp, src);
+        const float r2 = readlane_f(best.s_recv, src), r3 = readlane_f(best.open_angle, src);
+        const float r4 = readlane_f(best.refract, src);
+        if (l == 0) {
+            WB[w].t_team = r0;
+            WB[w].t_opp = r1;
+            WB[w].s_recv = r2;
+            WB[w].open_angle = r3;
+            WB[w].refract = r4;
+            WB[w].pad = 0.0f;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            RayRec r = WB[0];
+            for (int k = 1; k < nw; ++k)
+                if (WB[k].key > r.key) r = WB[k];
+            a.tile_rec[t] = r;
+        }
+    }
+}
+
+// One workgroup per frame: reduce the frame's tile records into its best
+// pass; block 0 also rearms the persistent work counter.
+__global__ void __launch_bounds__(256) ray_finalize_kernel(RayArgs a)
+{
+    __shared__ RayRec red[256];
+    const int f = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (f == 0 && tid == 0) *a.counter = 0u;
+    const FrameDev F = a.frames[f];
+    RayRec r;
+    r.key = 0ull;
+    r.t_team = r.t_opp = r.s_recv = INFINITY;
+    r.open_angle = r.refract = r.pad = 0.0f;
+    for (int k = tid; k < F.tile_count; k += blockDim.x) {
+        const RayRec x = a.tile_rec[F.tile_begin + k];
+        if (x.key > r.key) r = x;
+    }
+    red[tid] = r;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s && red[tid + s].key > red[tid].key) red[tid] = red[tid + s];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const RayRec b = red[0];
+    dpps_ray_best o;
+    o.found = 0; o.dir = -1; o.variant = -1; o.type = -1;
+    o.theta = 0.0f; o.v0 = 0.0f; o.x = 0.0f; o.y = 0.0f;
+    o.score = -INFINITY; o.t_team = INFINITY; o.t_opp = INFINITY;
+    o.open_angle = 0.0f; o.refract = 0.0f; o.pad = 0;
+    if (b.key != 0ull) {
+        const uint32_t lin = 0xFFFFFFFFu - (uint32_t)b.key;
+        const int d = (int)(lin / (uint32_t)F.n_variants);
+        const int v = (int)(lin - (uint32_t)d * (uint32_t)F.n_variants);
+        const dpps_variant var = a.variants[F.variant_off + v];
+        const double th = 6.283185307179586476925 * (double)d / (double)a.n_dirs;
+        const double xd = 2.0 * (double)d / (double)a.n_dirs;
+        const double ux = cospi(xd), uy = sinpi(xd);
+        o.found = 1;
+        o.dir = d;
+        o.variant = v;
+        o.type = var.type;
+        o.theta = (float)th;
+        o.v0 = var.v0;
+        o.x = (float)((double)F.ball_x + (double)b.s_recv * ux);
+        o.y = (float)((double)F.ball_y + (double)b.s_recv * uy);
+        o.score = unordered_bits((uint32_t)(b.key >> 32));
+        o.t_team = b.t_team;
+        o.t_opp = b.t_opp;
+        o.open_angle = b.open_angle;
+        o.refract = b.refract;
+    }
+    a.best[f] = o;
+}
+
+template <int KPL>
+static int launch_ray_kpl(const RayArgs &a, int waves_per_wg, int grid, hipStream_t st)
+{
+    if (a.n_tiles > 0 && grid > 0)
+        hipLaunchKernelGGL(ray_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg), 0, st, a);
+    if (a.n_frames > 0)
+        hipLaunchKernelGGL(ray_finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (a.P.K / 64) {
+    case 1: return launch_ray_kpl<1>(a, waves_per_wg, grid, st);
+    case 2: return launch_ray_kpl<2>(a, waves_per_wg, grid, st);
+    case 3: return launch_ray_kpl<3>(a, waves_per_wg, grid, st);
+    case 4: return launch_ray_kpl<4>(a, waves_per_wg, grid, st);
+    default: return -2;
+    }
+}
+
+int ray_occupancy(int K, int waves_per_wg)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const int bs = 64 * waves_per_wg;
+    switch (K / 64) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<1>, bs, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<2>, bs, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<3>, bs, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<4>, bs, 0); break;
+    default: break;
+    }
+    return e == hipSuccess && n > 0 ? n : 1;
 }
 
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,

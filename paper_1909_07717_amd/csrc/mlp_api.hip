@@ -49,6 +49,7 @@ struct dpps_mlp {
     uint16_t *dz4;
     uint16_t *dz[3];
     float *partial;
+    float *colpart;          // partial column sums of the bias gradients
     int64_t step = 0;
     // re-score tables
     int32_t *cells;
@@ -165,7 +166,7 @@ static int backward_loss(dpps_mlp *m, int nf, const float *tgt, int64_t ld_t, Lo
         g.ldc = IN_DIM[l];
         g.Cf = m->gw[l];
         if (gemm(g, false, false, EPI_NONE, (void *)st)) return fail(DPPS_E_DEVICE, "gemm failed");
-        if (launch_colsum(dz_top, R, OUT_DIM[l], OUT_DIM[l], m->gb[l], (void *)st))
+        if (launch_colsum(dz_top, R, OUT_DIM[l], OUT_DIM[l], m->gb[l], m->colpart, (void *)st))
             return fail(DPPS_E_DEVICE, "colsum failed");
         if (l == 0) break;
         // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
@@ -245,6 +246,7 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     }
     size_t oy = carve(off, R * OUT_PAD * 4), odz4 = carve(off, R * OUT_PAD * 2);
     size_t opart = carve(off, R * 8);
+    size_t ocol = carve(off, (size_t)colsum_chunks((int)R) * OUT_PAD * 4);
     size_t ocells = carve(off, R * max_k * 4);
     size_t orf = carve(off, R * sizeof(FrameDev));
     size_t orw = carve(off, R * max_k * sizeof(WinDev));
@@ -279,6 +281,7 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     m->y = (float *)(A + oy);
     m->dz4 = (uint16_t *)(A + odz4);
     m->partial = (float *)(A + opart);
+    m->colpart = (float *)(A + ocol);
     m->cells = (int32_t *)(A + ocells);
     m->rf = (FrameDev *)(A + orf);
     m->rw = (WinDev *)(A + orw);

@@ -24,7 +24,9 @@ struct GemmArgs {
 };
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream);
-int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st);
+// Column sums (bias gradients); part holds colsum_chunks(M) x N floats.
+int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, float *part, void *st);
+int colsum_chunks(int M);
 int launch_loss(const float *y, int ldy, const float *tgt, int ldt, int rows, int outs, int rows_pad,
                 int outs_pad, float pos_weight, float ce_weight, float tau, uint16_t *dz,
                 float *partial, void *st);

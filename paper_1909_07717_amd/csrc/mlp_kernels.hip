@@ -184,13 +184,35 @@ int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
 // ---------------------------------------------------------------------------
 
 // db[n] = sum over the first M rows of dZ[m][n] (bf16), fixed order.
-__global__ void colsum_kernel(const uint16_t *__restrict__ dz, int M, int N, int ld,
-                              float *__restrict__ db)
+// Column sums of dz [M][ld] (bias gradients), in two deterministic passes:
+// block (x, y) sums rows [y * COLSUM_ROWS, (y + 1) * COLSUM_ROWS) of columns
+// [64 x, 64 x + 64) (lanes = columns, four row phases, combined in a fixed
+// order) into part[y][n]; then each column adds its chunks in order.
+#define COLSUM_ROWS 128
+__global__ void __launch_bounds__(256) colsum_part_kernel(const uint16_t *__restrict__ dz, int M,
+                                                          int N, int ld, float *__restrict__ part)
 {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    const int m0 = blockIdx.y * COLSUM_ROWS;
+    const int m1 = min(m0 + COLSUM_ROWS, M);
+    float s = 0.0f;
+    if (n < N)
+        for (int m = m0 + r; m < m1; m += 4) s += bf2f(dz[(size_t)m * ld + n]);
+    red[r][c] = s;
+    __syncthreads();
+    if (r == 0 && n < N)
+        part[(size_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void colsum_final_kernel(const float *__restrict__ part, int chunks, int N,
+                                    float *__restrict__ db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) s += bf2f(dz[(size_t)m * ld + n]);
+    for (int k = 0; k < chunks; ++k) s += part[(size_t)k * N + n];
     db[n] = s;
 }
 
@@ -494,10 +516,17 @@ __global__ void rescore_tables_kernel(const FrameDev *__restrict__ src, int n_fr
 
 // host launchers -------------------------------------------------------------
 
-int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, void *st)
+int colsum_chunks(int M) { return (M + COLSUM_ROWS - 1) / COLSUM_ROWS; }
+
+int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, float *part, void *st)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, (hipStream_t)st, dz, M,
-                       N, ld, db);
+    const int chunks = colsum_chunks(M);
+    if (M > 0 && N > 0) {
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(256), 0,
+                           (hipStream_t)st, dz, M, N, ld, part);
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0,
+                           (hipStream_t)st, part, chunks, N, db);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -83,6 +83,9 @@ struct dpps_ctx {
     int persistent = 1;
     dpps_batch scratch;      // used by dpps_search / dpps_search_batch / host-frame surrogate
     dpps_batch fallback;     // exact searches of surrogate frames without a feasible proposal
+    dpps_batch rays;         // tables of dpps_ray_search
+    DeviceArena ray_aux;     // its work counter and per-tile records
+    int ray_tile_dirs = 4;   // directions per tile of dpps_ray_search
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;   // pinned staging consumed
@@ -110,3 +113,4 @@ int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t s
 int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *frames,
                 const dpps_robot *robots, const dpps_window *windows,
                 const dpps_variant *variants, hipStream_t st);
+int stage_tables(dpps_ctx *c, dpps_batch *b, hipStream_t st);

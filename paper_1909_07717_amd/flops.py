@@ -64,6 +64,30 @@ def batch_work(frames, K: int) -> tuple[int, int]:
     return ev, fl
 
 
+# The direction x power search (the paper's own form): per direction the same
+# robot stage, critical speeds and crossings as a candidate point (the ray
+# plays the part of the path), a direction set-up (ray length and path frame:
+# C_RAY_DIR), a per-variant finish that also forms the passing point and the
+# refraction angle (C_RAY_FINISH), and one open goal angle per feasible
+# passing point.
+C_RAY_DIR = 60
+C_RAY_FINISH = 70
+
+
+def ray_frame_work(frame, K: int, n_dirs: int, n_feasible: int) -> tuple[int, int]:
+    """(pass evaluations, flops) of one frame of the direction x variant
+    search, given how many of its passes came out feasible."""
+    n_int = frame.n_team - 1 + frame.n_opp
+    n_flat = sum(1 for v in frame.variants if v[0] == 0)
+    n_chip = len(frame.variants) - n_flat
+    V = n_flat + n_chip
+    types = (n_flat > 0) + (n_chip > 0)
+    per_sample = C_SAMPLE + 2 * C_VCRIT * types + (C_CHIP_SAMPLE if n_chip else 0)
+    per_dir = (n_int * K * C_ROBOT + K * per_sample + V * K * C_CROSS + V * C_RAY_FINISH
+               + C_RAY_DIR)
+    return n_dirs * V, n_dirs * per_dir + n_feasible * (C_ANGLE + C_ANGLE_OPP * frame.n_opp)
+
+
 # MI355X peaks used for the roofline (256 CUs, 2.4 GHz)
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # published; assumes packed FP32 FMA every cycle
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz

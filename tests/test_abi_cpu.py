@@ -48,6 +48,9 @@ int main(void) {
   O(dpps_frame, out_off); O(dpps_frame, ball_x); O(dpps_frame, ball_y);
   O(dpps_params, n_samples); O(dpps_params, out_flags); O(dpps_params, hbm_budget_bytes);
   O(dpps_best, score); O(dpps_best, t_ball); O(dpps_outputs, best);
+  S(dpps_ray_params); S(dpps_ray_best); S(dpps_ray_outputs);
+  O(dpps_ray_params, w_refract); O(dpps_ray_best, theta); O(dpps_ray_best, score);
+  O(dpps_ray_best, refract); O(dpps_ray_outputs, s_recv); O(dpps_ray_outputs, best);
   return 0;
 }
 """
@@ -75,6 +78,14 @@ def test_struct_layouts_match_header(tmp_path):
     assert got["dpps_best.score"] == B.BEST_DT.fields["score"][1]
     assert got["dpps_best.t_ball"] == B.BEST_DT.fields["t_ball"][1]
     assert got["dpps_outputs.best"] == B.Outputs_C.best.offset
+    assert got["dpps_ray_params"] == C.sizeof(B.RayParams_C)
+    assert got["dpps_ray_best"] == B.RAY_BEST_DT.itemsize
+    assert got["dpps_ray_outputs"] == C.sizeof(B.RayOutputs_C)
+    assert got["dpps_ray_params.w_refract"] == B.RayParams_C.w_refract.offset
+    for f in ("theta", "score", "refract"):
+        assert got[f"dpps_ray_best.{f}"] == B.RAY_BEST_DT.fields[f][1]
+    assert got["dpps_ray_outputs.s_recv"] == B.RayOutputs_C.s_recv.offset
+    assert got["dpps_ray_outputs.best"] == B.RayOutputs_C.best.offset
 
 
 def test_layout_is_host_only_and_dense():
