@@ -5,7 +5,11 @@
         K = 256), inputs resident, `steps` launches;
     python3 -m paper_1909_07717_amd.profiling copy --mib 512 --reps 4
         a plain device-to-device copy of known size, to calibrate the HBM
-        byte counters (FETCH_SIZE / WRITE_SIZE) against bytes actually moved.
+        byte counters (FETCH_SIZE / WRITE_SIZE) against bytes actually moved;
+    python3 -m paper_1909_07717_amd.profiling mlp --batch 4096 --steps 20
+        the surrogate network: `steps` forward passes, then `steps` training
+        steps (forward, loss, backward, Adam) on one batch of 6 v 6 frames
+        with synthetic labels.
 """
 from __future__ import annotations
 
@@ -38,6 +42,54 @@ def run_search(steps: int, seed: int = 100, reduced: bool = False):
     s.close()
 
 
+MLP_FWD_FLOP = 2 * (66 * 512 + 2 * 512 * 512 + 512 * 2806)  # per frame
+# backward: weight gradients of every layer, input gradients of all but the first
+MLP_STEP_FLOP = 3 * MLP_FWD_FLOP - 2 * 66 * 512
+
+
+def mlp_timing(batch: int, steps: int, stream=None):
+    """Average forward and training-step times (ms) of the surrogate network
+    at `batch` frames, from CUDA events on the stream the kernels run on."""
+    import torch
+
+    from paper_1909_07717_amd import binding as Bn
+    from paper_1909_07717_amd.framegen import Params, full_window, uniform_batch_arrays, variants_for
+
+    p = Params(n_samples=64).as_f32()
+    s = Bn.Searcher(p)
+    net = Bn.Mlp(s, batch, seed=1)
+    team, opp, passer = uniform_batch_arrays(4242, batch)
+    bt = s.batch(Bn.pack_uniform(team, opp, passer, [full_window(0.2)],
+                                 variants_for([4.0], flat=True, chip=False), p))
+    g = torch.Generator(device="cpu").manual_seed(0)
+    lab = torch.rand((batch, 2806), generator=g).to(s.device)
+    st = stream or torch.cuda.current_stream()
+    out = torch.empty((batch, 2806), dtype=torch.float32, device=s.device)
+    res = {}
+    with torch.cuda.stream(st):
+        for name, fn in (("forward", lambda: net.forward(bt, out=out, stream=st)),
+                         ("train_step", lambda: net.train_step(bt, lab, 1e-4, 8.0, 0.2, 0.02,
+                                                               stream=st, want_loss=False))):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                fn()
+            e1.record(st)
+            e1.synchronize()
+            res[name + "_ms"] = e0.elapsed_time(e1) / steps
+    bt.close()
+    net.close()
+    s.close()
+    fl_f, fl_s = MLP_FWD_FLOP * batch, MLP_STEP_FLOP * batch
+    res.update({"batch": batch,
+                "forward_tflops": fl_f / (res["forward_ms"] * 1e-3) / 1e12,
+                "train_step_tflops": fl_s / (res["train_step_ms"] * 1e-3) / 1e12,
+                "bf16_mfma_peak_tflops": 2500.0})
+    return res
+
+
 def run_copy(mib: int, reps: int):
     import torch
 
@@ -60,11 +112,17 @@ def main():
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=512)
     c.add_argument("--reps", type=int, default=4)
+    m = sub.add_parser("mlp")
+    m.add_argument("--batch", type=int, default=4096)
+    m.add_argument("--steps", type=int, default=20)
     args = ap.parse_args()
     if args.cmd == "search":
         run_search(args.steps, args.seed, args.reduced)
-    else:
+    elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
+    else:
+        import json
+        print(json.dumps(mlp_timing(args.batch, args.steps)), flush=True)
 
 
 if __name__ == "__main__":

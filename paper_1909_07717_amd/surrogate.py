@@ -174,16 +174,18 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
     st = torch.cuda.Stream()
     cache = torch.empty((n_virt, batch, 2806), dtype=torch.float32, device=s.device)
     have = np.zeros(n_virt, bool)
+    tables = {}  # device tables of each batch, kept for later epochs
     fine_out = None
     log = []
     t0 = time.time()
     for step in range(start, steps):
         bi = int(order[step])
-        team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi % n_batches, batch)
-        if bi >= n_batches:
-            team, opp = mirror_arrays(team, opp)
-        pk = B.pack_uniform(team, opp, passer, windows, variants, p)
-        bt = s.batch(pk)
+        if bi not in tables:
+            team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi % n_batches, batch)
+            if bi >= n_batches:
+                team, opp = mirror_arrays(team, opp)
+            tables[bi] = s.batch(B.pack_uniform(team, opp, passer, windows, variants, p))
+        bt = tables[bi]
         with torch.cuda.stream(st):
             if not have[bi]:
                 if labels == "pooled":
@@ -201,9 +203,10 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
                     cache[bi].copy_(lab.score.view(batch, 2806))
                 have[bi] = True
             rate = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
-            loss = net.train_step(bt, cache[bi], rate, pos_weight, ce_weight, tau, stream=st)
-        bt.close()
-        if step % log_every == 0 or step == steps - 1:
+            logged = step % log_every == 0 or step == steps - 1
+            loss = net.train_step(bt, cache[bi], rate, pos_weight, ce_weight, tau, stream=st,
+                                  want_loss=logged)
+        if logged:
             rec = {"step": step, "presented": (step + 1) * batch, "loss": loss, "lr": rate,
                    "elapsed_s": round(time.time() - t0, 2)}
             log.append(rec)
@@ -211,6 +214,8 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
     meta = {"frames": n_batches * batch, "epochs": epochs, "batch": batch, "lr": lr,
             "pos_weight": pos_weight, "ce_weight": ce_weight, "tau": tau, "labels": labels,
             "steps": steps, "train_seed": TRAIN_SEED, "mirror": mirror, "log": log}
+    for t in tables.values():
+        t.close()
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     save_checkpoint(out, net, steps, meta, params_only)
     net.close()
