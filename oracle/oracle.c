@@ -698,4 +698,83 @@ int64_t orc_ray_search(const orc_params *P, const orc_ray_params *R, const orc_w
     return (int64_t)R->n_dirs * n_var;
 }
 
-int orc_abi_version(void) { return 2; }
+/* ------------------------------------------------------------------------ */
+/* Passing power (Sec. 4.1, Eq. 1-2): the kick speed for a pass to point c.  */
+/* Readings: the receiver B is the teammate (passer excluded) that reaches c */
+/* first (arrival-time predictor above); the ball should arrive when B does  */
+/* plus a buffer (0.3 s in the paper); Eq. 1, as the paper simplifies it,    */
+/* ignores the sliding phase, so over distance d and time t at the rolling    */
+/* deceleration a the speed after the slide is v1 = (d + a t^2 / 2) / t      */
+/* while the ball still rolls at t (d >= a t^2 / 2); when t is longer than a  */
+/* rolling ball can take, the slowest ball that still reaches c,             */
+/* v1 = sqrt(2 a d); Eq. 2 gives the kick speed v0 = v1 / slide_ratio (the   */
+/* ball slides down to 5/7 of v0); the result is clamped to the robots'      */
+/* kick range [v_min, v_max].  Returns 0 when no teammate can receive.       */
+/* ------------------------------------------------------------------------ */
+double orc_power_speed(const orc_params *P, const orc_world *W, double cx, double cy,
+                       double buffer_s, double v_min, double v_max, double *t_recv)
+{
+    double tb = INFINITY;
+    for (int j = 0; j < W->n_team; ++j) {
+        if (j == W->passer) continue;
+        double t = robot_time_to(P, W->team + 4 * j, cx, cy);
+        if (t < tb) tb = t;
+    }
+    if (t_recv) *t_recv = tb;
+    if (!isfinite(tb)) return 0.0;
+    double dx = cx - W->ball_x, dy = cy - W->ball_y;
+    double d = sqrt(dx * dx + dy * dy);
+    double t = tb + buffer_s;
+    double a = P->roll_decel;
+    double v1 = d >= 0.5 * a * t * t ? (d + 0.5 * a * t * t) / t : sqrt(2.0 * a * d);
+    double v0 = v1 / P->slide_ratio;
+    if (v0 < v_min) v0 = v_min;
+    if (v0 > v_max) v0 = v_max;
+    return v0;
+}
+
+/* Every point of the windows with one flat pass at the point's own power;
+ * outputs as orc_search with one variant, plus the power per point. */
+int64_t orc_power_search(const orc_params *P, const orc_world *W, int n_win, const double *win_h,
+                         const int32_t *win_int, double buffer_s, double v_min, double v_max,
+                         int bands, uint8_t *mask, double *score, double *t_team, double *t_opp,
+                         double *v0_out, uint8_t *ambig)
+{
+    int64_t base = 0;
+    for (int w = 0; w < n_win; ++w) {
+        double h = win_h[w];
+        int i0 = win_int[4 * w], j0 = win_int[4 * w + 1];
+        int nx = win_int[4 * w + 2], ny = win_int[4 * w + 3];
+        int64_t npts = (int64_t)nx * ny;
+#ifdef _OPENMP
+        int nt = P->n_threads > 0 ? P->n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
+#endif
+        for (int64_t p = 0; p < npts; ++p) {
+            int i = (int)(p % nx), j = (int)(p / nx);
+            double cx, cy;
+            orc_point(P, h, i0 + i, j0 + j, &cx, &cy);
+            double v0 = orc_power_speed(P, W, cx, cy, buffer_s, v_min, v_max, NULL);
+            orc_result r;
+            if (v0 > 0.0) {
+                orc_eval(P, W, ORC_FLAT, v0, cx, cy, bands, &r);
+            } else {
+                memset(&r, 0, sizeof r);
+                r.t_team = INFINITY;
+                r.t_opp = INFINITY;
+                r.score = -INFINITY;
+            }
+            int64_t o = base + p;
+            if (mask) mask[o] = (uint8_t)r.feasible;
+            if (score) score[o] = r.score;
+            if (t_team) t_team[o] = r.t_team;
+            if (t_opp) t_opp[o] = r.t_opp;
+            if (v0_out) v0_out[o] = v0;
+            if (ambig) ambig[o] = (uint8_t)r.ambig;
+        }
+        base += npts;
+    }
+    return base;
+}
+
+int orc_abi_version(void) { return 3; }

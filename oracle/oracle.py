@@ -110,6 +110,11 @@ def lib():
         L.orc_ray_search.argtypes = [P, RP, Wp, C.c_int, pi32, pd, C.c_int, pu8, pd, pd, pd, pd,
                                      pu8]
         L.orc_ray_search.restype = i64
+        L.orc_power_speed.argtypes = [P, Wp, d, d, d, d, d, pd]
+        L.orc_power_speed.restype = d
+        L.orc_power_search.argtypes = [P, Wp, C.c_int, pd, pi32, d, d, d, C.c_int, pu8, pd, pd,
+                                       pd, pd, pu8]
+        L.orc_power_search.restype = i64
         _lib = L
     return _lib
 
@@ -314,3 +319,41 @@ def ray_eval(frame, params, n_dirs: int, w_time: float, w_refract: float, direct
     L.orc_ray_eval(C.byref(P), C.byref(R), C.byref(wh.w), direction, vtype, v0, int(bands),
                    C.byref(r))
     return {k: getattr(r, k) for k, _ in OrcRayResult._fields_}
+
+
+# ---------------------------------------------------------------------------
+# passing power per point (Sec. 4.1, Eq. 1-2)
+# ---------------------------------------------------------------------------
+
+def power_speed(frame, params, cx, cy, buffer_s=0.3, v_min=1.0, v_max=6.5):
+    """(kick speed, receiver arrival time) for a pass to (cx, cy)."""
+    L = lib()
+    P = make_params(params)
+    wh = _WorldHolder(frame)
+    t = C.c_double()
+    v = L.orc_power_speed(C.byref(P), C.byref(wh.w), cx, cy, buffer_s, v_min, v_max,
+                          C.byref(t))
+    return float(v), float(t.value)
+
+
+def power_search(frame, params, buffer_s=0.3, v_min=1.0, v_max=6.5, bands=False,
+                 n_threads: int = 0, **band_eps):
+    """Every point of the frame's windows with one flat pass at the point's
+    own power; flat arrays in window-major, row-major order."""
+    L = lib()
+    P = make_params(params, n_threads, **band_eps)
+    wh = _WorldHolder(frame)
+    win_h = np.array([w[0] for w in frame.windows], dtype=np.float64)
+    win_i = np.array([[w[1], w[2], w[3], w[4]] for w in frame.windows], dtype=np.int32).reshape(-1)
+    n = int(sum(w[3] * w[4] for w in frame.windows))
+    out = dict(mask=np.zeros(n, np.uint8), score=np.zeros(n), t_team=np.zeros(n),
+               t_opp=np.zeros(n), v0=np.zeros(n), ambig=np.zeros(n, np.uint8))
+    L.orc_power_search(C.byref(P), C.byref(wh.w), len(win_h), _ptr(win_h, C.c_double),
+                       _ptr(win_i, C.c_int32), buffer_s, v_min, v_max, int(bands),
+                       _ptr(out["mask"], C.c_uint8), _ptr(out["score"], C.c_double),
+                       _ptr(out["t_team"], C.c_double), _ptr(out["t_opp"], C.c_double),
+                       _ptr(out["v0"], C.c_double), _ptr(out["ambig"], C.c_uint8))
+    best = int(L.orc_argmax(n, _ptr(out["score"], C.c_double)))
+    out["best"] = best
+    out["best_score"] = float(out["score"][best]) if best >= 0 else float("-inf")
+    return out
