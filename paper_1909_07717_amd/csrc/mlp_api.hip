@@ -23,6 +23,8 @@ constexpr int IN_DIM[NL] = {IN_PAD, HID, HID, HID};
 constexpr int IN_REAL[NL] = {IN, HID, HID, HID};
 constexpr int OUT_DIM[NL] = {HID, HID, HID, OUT_PAD};
 constexpr int OUT_REAL[NL] = {HID, HID, HID, OUT};
+// workspace of the split weight-gradient products (partial sums, floats)
+constexpr int64_t GWORK_ELEMS = 3 * 1024 * 1024;
 constexpr double COARSE_H = 0.2, FINE_H = 0.05;
 
 int64_t real_count()
@@ -50,6 +52,7 @@ struct dpps_mlp {
     uint16_t *dz[3];
     float *partial;
     float *colpart;          // partial column sums of the bias gradients
+    float *gwork;            // partial weight-gradient products
     int64_t step = 0;
     // re-score tables
     int32_t *cells;
@@ -165,6 +168,8 @@ static int backward_loss(dpps_mlp *m, int nf, const float *tgt, int64_t ld_t, Lo
         g.K = R;
         g.ldc = IN_DIM[l];
         g.Cf = m->gw[l];
+        g.work = m->gwork;  // the reduction over the batch may be split
+        g.work_elems = GWORK_ELEMS;
         if (gemm(g, false, false, EPI_NONE, (void *)st)) return fail(DPPS_E_DEVICE, "gemm failed");
         if (launch_colsum(dz_top, R, OUT_DIM[l], OUT_DIM[l], m->gb[l], m->colpart, (void *)st))
             return fail(DPPS_E_DEVICE, "colsum failed");
@@ -247,6 +252,7 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     size_t oy = carve(off, R * OUT_PAD * 4), odz4 = carve(off, R * OUT_PAD * 2);
     size_t opart = carve(off, R * 8);
     size_t ocol = carve(off, (size_t)colsum_chunks((int)R) * OUT_PAD * 4);
+    size_t ogwork = carve(off, (size_t)GWORK_ELEMS * 4);
     size_t ocells = carve(off, R * max_k * 4);
     size_t orf = carve(off, R * sizeof(FrameDev));
     size_t orw = carve(off, R * max_k * sizeof(WinDev));
@@ -282,6 +288,7 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     m->dz4 = (uint16_t *)(A + odz4);
     m->partial = (float *)(A + opart);
     m->colpart = (float *)(A + ocol);
+    m->gwork = (float *)(A + ogwork);
     m->cells = (int32_t *)(A + ocells);
     m->rf = (FrameDev *)(A + orf);
     m->rw = (WinDev *)(A + orw);

@@ -7,7 +7,7 @@
 
 namespace dpps {
 
-enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3, EPI_PARTIAL = 4 };
 
 #define TOPK_SORT 4096   // cells sorted per frame (>= coarse lattice size)
 #define TOPK_MAX 128     // largest k
@@ -21,6 +21,9 @@ struct GemmArgs {
     const float *Zin;    // EPI_GELU_GRAD: pre-activation, [M][ldc]
     float *Cf;           // f32 output
     uint16_t *Cb;        // bf16 output
+    float *work;         // optional workspace for a K split (EPI_NONE only), work_elems floats
+    int64_t work_elems;
+    int k_slice;         // set by the dispatcher
 };
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream);

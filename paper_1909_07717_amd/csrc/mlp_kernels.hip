@@ -44,86 +44,114 @@ __device__ __forceinline__ float gelu_grad(float x)
 // A(m, k) = A[m*lda + k] when A_K (k contiguous), else A[k*lda + m].
 // B(k, n) = B[n*ldb + k] when B_K (k contiguous), else B[k*ldb + n].
 // M, N, K are multiples of 8 (vectors of 8 never straddle an edge).
-// Block tile 64 x 64, K step 32, 4 waves each owning a 32 x 32 quarter as
-// 2 x 2 MFMA tiles of 16 x 16.
+// Block tile BM x BN (128 x 128 or 64 x 64), K step 32, 256 threads: four
+// waves in a 2 x 2 arrangement, each owning a (BM/2) x (BN/2) quarter as
+// (BM/32) x (BN/32) MFMA tiles of 16 x 16 (v_mfma_f32_16x16x32_bf16).  The
+// next K step is fetched into registers while the current one multiplies
+// out of LDS, into the other of two LDS buffers, one barrier per step.
+// blockIdx.z splits K into slices of g.k_slice; with EPI_PARTIAL slice z
+// writes its partial product to Cf + z * M * ldc (summed by gemm_reduce).
 // ---------------------------------------------------------------------------
-#define GT 64
 #define GK 32
 #define LDSK (GK + 8)   // padded row (bf16 elements) to spread LDS banks
 
-template <bool A_K, bool B_K>
-__device__ __forceinline__ void load_tiles(const uint16_t *__restrict__ A, int lda,
-                                           const uint16_t *__restrict__ B, int ldb, int M, int N,
-                                           int K, int m0, int n0, int k0, uint16_t *As,
-                                           uint16_t *Bs)
+template <int BM, bool A_K>
+__device__ __forceinline__ void fetch_tile(const uint16_t *__restrict__ A, int lda, int M, int K,
+                                           int m0, int k0, uint4 (&r)[BM / 64])
 {
-    const int t = threadIdx.x;  // 256 threads, one vector of 8 for A and one for B
-    // A tile: 64 (m) x 32 (k)
-    if (A_K) {
-        const int m = t >> 2, kk = (t & 3) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (m0 + m < M && k0 + kk < K) v = *(const uint4 *)(A + (size_t)(m0 + m) * lda + k0 + kk);
-        *(uint4 *)(As + m * LDSK + kk) = v;
-    } else {
-        const int kk = t >> 3, m = (t & 7) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (m0 + m < M && k0 + kk < K) v = *(const uint4 *)(A + (size_t)(k0 + kk) * lda + m0 + m);
-        const uint16_t *e = (const uint16_t *)&v;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) As[(m + j) * LDSK + kk] = e[j];
-    }
-    // B tile: 32 (k) x 64 (n), stored as Bs[n][k]
-    if (B_K) {
-        const int n = t >> 2, kk = (t & 3) * 8;
+    for (int i = 0; i < BM / 64; ++i) {
+        const int idx = threadIdx.x + i * 256;
+        int m, kk;
+        if (A_K) {
+            m = idx >> 2;
+            kk = (idx & 3) * 8;
+        } else {
+            kk = idx / (BM / 8);
+            m = (idx % (BM / 8)) * 8;
+        }
         uint4 v = make_uint4(0, 0, 0, 0);
-        if (n0 + n < N && k0 + kk < K) v = *(const uint4 *)(B + (size_t)(n0 + n) * ldb + k0 + kk);
-        *(uint4 *)(Bs + n * LDSK + kk) = v;
-    } else {
-        const int kk = t >> 3, n = (t & 7) * 8;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (n0 + n < N && k0 + kk < K) v = *(const uint4 *)(B + (size_t)(k0 + kk) * ldb + n0 + n);
-        const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) Bs[(n + j) * LDSK + kk] = e[j];
+        if (m0 + m < M && k0 + kk < K)
+            v = A_K ? *(const uint4 *)(A + (size_t)(m0 + m) * lda + k0 + kk)
+                    : *(const uint4 *)(A + (size_t)(k0 + kk) * lda + m0 + m);
+        r[i] = v;
     }
 }
 
-template <bool A_K, bool B_K, int EPI>
+// Tiles are kept in LDS as [row][k] (rows = m for A, n for B).
+template <int BM, bool A_K>
+__device__ __forceinline__ void store_tile(const uint4 (&r)[BM / 64], uint16_t *As)
+{
+#pragma unroll
+    for (int i = 0; i < BM / 64; ++i) {
+        const int idx = threadIdx.x + i * 256;
+        if (A_K) {
+            *(uint4 *)(As + (idx >> 2) * LDSK + (idx & 3) * 8) = r[i];
+        } else {
+            const int kk = idx / (BM / 8), m = (idx % (BM / 8)) * 8;
+            const uint16_t *e = (const uint16_t *)&r[i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) As[(m + j) * LDSK + kk] = e[j];
+        }
+    }
+}
+
+template <int BM, int BN, bool A_K, bool B_K, int EPI>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GT * LDSK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT * LDSK];
-    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    constexpr int TM = BM / 32, TN = BN / 32;
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDSK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDSK];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kb = blockIdx.z * g.k_slice;
+    const int ke = min(kb + g.k_slice, g.K);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-    f32x4_t acc[2][2];
+    const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BN / 2);
+    f32x4_t acc[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < TN; ++b) acc[a][b] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
     const int fr = l & 15, fk = (l >> 4) * 8;  // fragment row/col and k offset
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
-        __syncthreads();
-        load_tiles<A_K, B_K>(g.A, g.lda, g.B, g.ldb, g.M, g.N, g.K, m0, n0, k0, As, Bs);
-        __syncthreads();
-        bf16x8_t af[2], bfr[2];
+    uint4 ra[BM / 64], rb[BN / 64];
+    fetch_tile<BM, A_K>(g.A, g.lda, g.M, g.K, m0, kb, ra);
+    fetch_tile<BN, B_K>(g.B, g.ldb, g.N, g.K, n0, kb, rb);
+    store_tile<BM, A_K>(ra, As[0]);
+    store_tile<BN, B_K>(rb, Bs[0]);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+        const bool more = k0 + GK < ke;
+        if (more) {
+            fetch_tile<BM, A_K>(g.A, g.lda, g.M, g.K, m0, k0 + GK, ra);
+            fetch_tile<BN, B_K>(g.B, g.ldb, g.N, g.K, n0, k0 + GK, rb);
+        }
+        bf16x8_t af[TM], bfr[TN];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-            af[a] = *(const bf16x8_t *)(As + (wm + a * 16 + fr) * LDSK + fk);
+        for (int a = 0; a < TM; ++a)
+            af[a] = *(const bf16x8_t *)(As[cur] + (wm + a * 16 + fr) * LDSK + fk);
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-            bfr[b] = *(const bf16x8_t *)(Bs + (wn + b * 16 + fr) * LDSK + fk);
+        for (int b = 0; b < TN; ++b)
+            bfr[b] = *(const bf16x8_t *)(Bs[cur] + (wn + b * 16 + fr) * LDSK + fk);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < TM; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < TN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        if (more) {
+            // the other buffer was last read before the previous barrier
+            store_tile<BM, A_K>(ra, As[cur ^ 1]);
+            store_tile<BN, B_K>(rb, Bs[cur ^ 1]);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
     // epilogue: lane holds D[(l/16)*4 + i][l%16] of each 16 x 16 tile
+    float *part = g.Cf + (size_t)blockIdx.z * g.M * g.ldc;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < TM; ++a) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < TN; ++b) {
             const int n = n0 + wn + b * 16 + (l & 15);
             if (n >= g.N) continue;
 #pragma unroll
@@ -141,6 +169,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                 } else if (EPI == EPI_GELU_GRAD) {
                     // v = dA; dZ = dA * gelu'(Z)
                     g.Cb[o] = f2bf(v * gelu_grad(g.Zin[o]));
+                } else if (EPI == EPI_PARTIAL) {
+                    part[o] = v;
                 } else {
                     g.Cf[o] = v;
                 }
@@ -149,11 +179,54 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     }
 }
 
-template <bool A_K, bool B_K, int EPI>
-static void launch_gemm(const GemmArgs &g, hipStream_t st)
+// out[m][n] = sum over z of part[z][m][n], in order of z.
+__global__ void gemm_reduce_kernel(const float *__restrict__ part, int splits, int64_t n_el,
+                                   float *__restrict__ out)
 {
-    dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT);
-    hipLaunchKernelGGL((gemm_kernel<A_K, B_K, EPI>), grid, dim3(256), 0, st, g);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_el) return;
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * n_el + e];
+    out[e] = s;
+}
+
+template <int BM, int BN, bool A_K, bool B_K, int EPI>
+static void launch_gemm(const GemmArgs &g, int splits, hipStream_t st)
+{
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, A_K, B_K, EPI>), grid, dim3(256), 0, st, g);
+}
+
+template <bool A_K, bool B_K, int EPI>
+static void launch_shape(GemmArgs g, hipStream_t st)
+{
+    const int64_t t128 = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64);
+    if (EPI == EPI_NONE && g.work && t64 < 512 && g.K >= 1024) {
+        // few output tiles and a long reduction (weight gradients over the
+        // batch): split K into slices of a multiple of the K step, partial
+        // products into the workspace, then a fixed-order sum
+        int splits = (int)((512 + t64 - 1) / t64);
+        splits = min(splits, g.K / 256);
+        const int64_t mn = (int64_t)g.M * g.ldc;
+        while (splits > 1 && (int64_t)splits * mn > g.work_elems) --splits;
+        if (splits > 1) {
+            const int slice = ((g.K + splits - 1) / splits + GK - 1) / GK * GK;
+            splits = (g.K + slice - 1) / slice;
+            GemmArgs h = g;
+            h.k_slice = slice;
+            h.Cf = g.work;
+            launch_gemm<64, 64, A_K, B_K, EPI_PARTIAL>(h, splits, st);
+            hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0,
+                               st, (const float *)g.work, splits, mn, g.Cf);
+            return;
+        }
+    }
+    g.k_slice = g.K;
+    if (t128 >= 256)
+        launch_gemm<128, 128, A_K, B_K, EPI>(g, 1, st);
+    else
+        launch_gemm<64, 64, A_K, B_K, EPI>(g, 1, st);
 }
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
@@ -163,10 +236,10 @@ int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
 #define GEMM_CASE(AK, BK)                                                          \
     if (a_k == AK && b_k == BK) {                                                  \
         switch (epi) {                                                             \
-        case EPI_NONE: launch_gemm<AK, BK, EPI_NONE>(g, st); break;                \
-        case EPI_BIAS: launch_gemm<AK, BK, EPI_BIAS>(g, st); break;                \
-        case EPI_BIAS_GELU: launch_gemm<AK, BK, EPI_BIAS_GELU>(g, st); break;      \
-        case EPI_GELU_GRAD: launch_gemm<AK, BK, EPI_GELU_GRAD>(g, st); break;      \
+        case EPI_NONE: launch_shape<AK, BK, EPI_NONE>(g, st); break;               \
+        case EPI_BIAS: launch_shape<AK, BK, EPI_BIAS>(g, st); break;               \
+        case EPI_BIAS_GELU: launch_shape<AK, BK, EPI_BIAS_GELU>(g, st); break;     \
+        case EPI_GELU_GRAD: launch_shape<AK, BK, EPI_GELU_GRAD>(g, st); break;     \
         default: return -1;                                                        \
         }                                                                          \
         return hipGetLastError() == hipSuccess ? 0 : -1;                           \
@@ -183,7 +256,6 @@ int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
 // elementwise and reduction kernels
 // ---------------------------------------------------------------------------
 
-// db[n] = sum over the first M rows of dZ[m][n] (bf16), fixed order.
 // Column sums of dz [M][ld] (bias gradients), in two deterministic passes:
 // block (x, y) sums rows [y * COLSUM_ROWS, (y + 1) * COLSUM_ROWS) of columns
 // [64 x, 64 x + 64) (lanes = columns, four row phases, combined in a fixed

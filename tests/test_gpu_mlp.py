@@ -90,6 +90,41 @@ def test_forward_loss_and_gradients(B):
     bt.close(); net.close(); s.close()
 
 
+def test_forward_and_gradients_large_batch(B):
+    # 2048 frames: the output layer runs on the 128 x 128 tiles and the
+    # weight gradients reduce over the batch in split slices
+    from paper_1909_07717_amd.framegen import (frames_from_arrays, uniform_batch_arrays,
+                                               variants_for)
+    s = B.Searcher(P)
+    team, opp, passer = uniform_batch_arrays(777, 2048)
+    frames = frames_from_arrays(team, opp, passer, [full_window(0.2)],
+                                variants_for([4.0], flat=True, chip=False))
+    net = B.Mlp(s, 2048, seed=9)
+    bt = s.batch(frames)
+    T = _labels(B, s, frames)
+    y = net.forward(bt).cpu().numpy()
+    w = net.get_params().astype(np.float64)
+    X = np.stack([M.features(f) for f in frames])
+    Yref, _ = M.forward(w, X)
+    assert _rel_l2(y, Yref) <= 2e-2
+    kw = dict(pos_weight=8.0, ce_weight=0.2, tau=0.02)
+    loss = net.loss_grad(bt, T, **kw)
+    g = net.get_grads().astype(np.float64)
+    lref, gref = M.loss_and_grad(w, X, T.cpu().numpy(), **kw)
+    assert abs(loss - lref) <= 2e-2 * lref
+    o = 0
+    for l, (r, c) in enumerate(M.DIMS):
+        for name, n in (("W", r * c), ("b", r)):
+            e = _rel_l2(g[o:o + n], gref[o:o + n])
+            print(f"[mlp 2048] grad {name}{l} rel L2 {e:.2e}", flush=True)
+            assert e <= 3e-2, (name, l, e)
+            o += n
+    # the split reduction is deterministic
+    net.loss_grad(bt, T, **kw)
+    assert np.array_equal(net.get_grads(), g.astype(np.float32))
+    bt.close(); net.close(); s.close()
+
+
 def test_pooled_labels(B):
     s = B.Searcher(P)
     frames = _frames(3, 400)
