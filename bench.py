@@ -121,6 +121,40 @@ def batch_bench(n_frames: int, steps: int, tune_cache: str, st):
     return rec
 
 
+def power_bench(steps: int, st):
+    """Per-point passing power (Sec. 4.1, Eq. 1-2): the full frame's 8v8 robots
+    and 5 cm lattice (43 621 points), one flat pass per point at the point's
+    own power (receiver + 0.3 s, kick range 1-6.5 m/s), K = 256; inputs staged
+    from the host on every call."""
+    import torch
+
+    from paper_1909_07717_amd import binding as Bn
+    from paper_1909_07717_amd.framegen import Params, config_full
+
+    p = Params(n_samples=256).as_f32()
+    f = config_full(100)
+    s = Bn.Searcher(p, device=0)
+    with torch.cuda.stream(st):
+        out, v0 = s.search_power([f], stream=st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            s.search_power([f], stream=st)
+        e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    feas = int(out.mask.sum().item())
+    vv = v0.cpu()
+    s.close()
+    return {"workload": "full frame 8v8, 5 cm lattice 241x181, one flat pass per point at its "
+                        "own power (Eq. 1-2), K = 256", "points": 43621,
+            "ms_per_frame": round(ms, 4), "points_per_s": round(43621 / (ms * 1e-3), 1),
+            "feasible_points": feas, "v0_min": round(float(vv.min()), 4),
+            "v0_max": round(float(vv.max()), 4)}
+
+
 def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
     """The paper's own DPPS form: 8v8 frames, 128 kick directions x 64 flat
     powers in [1, 6.5] m/s, K = 256 samples per ray.  Batched: n_frames frames
@@ -257,6 +291,9 @@ def main() -> int:
     st = torch.cuda.Stream()
     bt = s.batch([frame])
     out = s.outputs_for(bt.pk)
+    # launch shape (tile size, waves, persistent grid) from the autotuner, cached
+    tuned = bt.autotune(out, args.tune_cache, reps=3, stream=st)
+    shape = s.get_launch()
     with torch.cuda.stream(st):
         for _ in range(args.warmup):
             bt.run(out, stream=st)
@@ -314,6 +351,7 @@ def main() -> int:
         batch = batch_bench(args.batch_frames, args.batch_steps, args.tune_cache, st)
     rays = (ray_bench(args.ray_frames, 5, min(args.latency_frames, 2000), st)
             if args.ray_frames > 0 else None)
+    power = power_bench(20, st) if args.ray_frames > 0 else None
     sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
            if args.surrogate_frames > 0 else None)
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
@@ -336,7 +374,9 @@ def main() -> int:
         "config": {"workload": "full frame: 8v8 robots, 5 cm lattice 241x181 = 43621 points, "
                                "16 kick speeds 1.0-6.5 m/s x {flat, chip} = 32 variants, "
                                "K = 256 samples", "frame_seed": FRAME_SEED,
-                   "evals_per_frame": evals, "frames_per_step": 1},
+                   "evals_per_frame": evals, "frames_per_step": 1,
+                   "launch": {"tile_points": shape[0], "waves_per_wg": shape[1],
+                              "wg_per_cu": shape[2], "from_cache": tuned < 0}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
@@ -345,6 +385,7 @@ def main() -> int:
         "graph_ms_per_step": round(graph_ms, 5),
         "batch": batch,
         "rays": rays,
+        "power": power,
         "surrogate": sur,
         "serving": serving,
     }

@@ -291,6 +291,31 @@ int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
                                  int32_t k, dpps_best *d_best, int fallback, float fallback_below,
                                  int32_t *n_fallback, void *hip_stream);
 
+/* ---- passing power per point (Sec. 4.1, Eq. 1-2) ------------------------
+ * Instead of a list of kick speeds, every candidate point gets its own flat
+ * pass whose speed follows the receiver: the receiver is the teammate
+ * (passer excluded) that reaches the point first, the ball should arrive at
+ * its arrival time plus buffer_s; ignoring the sliding phase as Eq. 1 does,
+ * the speed after the slide over distance d and time t at the rolling
+ * deceleration a is v1 = (d + a t^2 / 2) / t while the ball still rolls at t
+ * (else the slowest ball that reaches the point, sqrt(2 a d)); Eq. 2 gives
+ * the kick speed v1 / slide_ratio, clamped to the robots' kick range
+ * [v_min, v_max].  The pass is then searched as in dpps_search with the full
+ * ball model.  Outputs: one element per point (layout of dpps_search with
+ * one variant per frame; the frames' variants are not used), d_v0 (may be
+ * NULL) the kick speed per point (0 where no teammate can receive), best.v0
+ * the chosen pass's speed. */
+typedef struct {
+    float buffer_s;   /* time added to the receiver's arrival (0.3 s in the paper) */
+    float v_min, v_max; /* kick range (1, 6.5 m/s) */
+    int32_t reserved; /* must be 0 */
+} dpps_power_params;
+
+int dpps_search_power(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_power_params *pp, const dpps_outputs *out, float *d_v0,
+                      void *hip_stream);
+
 /* ---- the paper's direction x power form (Sec. 4.2) ----------------------
  * The search as the paper states it, from the passer's point of view: for
  * every kick direction theta_d = 2 pi d / n_dirs (d = 0 .. n_dirs-1, from +x,

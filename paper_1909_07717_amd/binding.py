@@ -68,6 +68,11 @@ class RayParams_C(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class PowerParams_C(C.Structure):
+    _fields_ = [("buffer_s", C.c_float), ("v_min", C.c_float), ("v_max", C.c_float),
+                ("reserved", C.c_int32)]
+
+
 class RayOutputs_C(C.Structure):
     _fields_ = [("mask", C.c_void_p), ("score", C.c_void_p), ("t_team", C.c_void_p),
                 ("t_opp", C.c_void_p), ("s_recv", C.c_void_p), ("best", C.c_void_p)]
@@ -130,6 +135,8 @@ def lib():
                                                    C.c_float, C.POINTER(i32), vp]
         L.dpps_ray_search.argtypes = [vp, i32, vp, vp, vp, C.POINTER(RayParams_C),
                                       C.POINTER(RayOutputs_C), vp]
+        L.dpps_search_power.argtypes = [vp, i32, vp, vp, vp, C.POINTER(PowerParams_C),
+                                        C.POINTER(Outputs_C), vp, vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
         L.dpps_timing_end.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(i32)]
         L.dpps_strerror.argtypes = [C.c_int]
@@ -319,6 +326,29 @@ class Searcher:
         _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
                                  _ptr(pk.variants), C.byref(oc), best.ctypes.data))
         return out, best[0]
+
+    def search_power(self, frames, buffer_s: float = 0.3, v_min: float = 1.0,
+                     v_max: float = 6.5, mask=True, score=True, times=True, stream=None):
+        """Every point of the frames' windows with one flat pass at the point's
+        own passing power (Eq. 1-2), asynchronous on the stream.  Returns
+        (DeviceOutputs, v0) with one element per point (the frames' variants
+        are not used)."""
+        import torch
+        one = [(DPPS_FLAT, float(v_min))]
+        fr = []
+        for f in frames:
+            g = f.copy()
+            g.variants = list(one)
+            fr.append(g)
+        pk = pack(fr, self.params, self.out_flags)
+        out = self.outputs_for(pk, mask, score, times)
+        v0 = torch.empty(max(pk.total, 1), dtype=torch.float32, device=self.device)
+        pp = PowerParams_C(float(buffer_s), float(v_min), float(v_max), 0)
+        oc = out.c()
+        _check(lib().dpps_search_power(self.h, len(fr), _ptr(pk.frames), _ptr(pk.robots),
+                                       _ptr(pk.windows), C.byref(pp), C.byref(oc),
+                                       v0.data_ptr(), _stream_ptr(stream)))
+        return out, v0[:pk.total]
 
     def ray_search(self, frames, n_dirs: int = 128, w_time: float = 0.05, w_refract: float = 0.1,
                    mask=True, score=True, times=True, recv=True, stream=None, out=None):

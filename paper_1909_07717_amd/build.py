@@ -1,6 +1,7 @@
 """Build libdpps.so (HIP, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -33,6 +34,16 @@ SOURCES = {
 }
 
 
+def kernel_rev() -> str:
+    """Short hash of the search kernels' sources, compiled into the library so
+    that cached launch shapes tuned on other kernels are not reused."""
+    h = hashlib.sha256()
+    for f in ("dpps_kernels.hip", "dpps_internal.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def hipcc() -> str:
     for p in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if p and os.path.exists(p):
@@ -53,12 +64,13 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     """Compile every source and link libdpps.so (always recompiles)."""
+    rev = [f'-DDPPS_KERNEL_REV="{kernel_rev()}"']
     with tempfile.TemporaryDirectory() as td:
         objs = []
         for src, flags in SOURCES.items():
             obj = os.path.join(td, src + ".o")
-            _run([hipcc()] + COMMON + flags + (extra or []) + ["-c", os.path.join(CSRC, src),
-                                                              "-o", obj], verbose)
+            _run([hipcc()] + COMMON + flags + rev + (extra or []) +
+                 ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
             objs.append(obj)
         tmp = LIB + ".tmp"
         _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs, verbose)

@@ -381,7 +381,7 @@ int batch_upload(dpps_ctx *c, dpps_batch *b)
 }
 
 int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st,
-                     bool timed)
+                     bool timed, const dpps_power_params *power, float *v0_out)
 {
     if (!out) return fail(DPPS_E_INVALID, "outputs is NULL");
     if (b->tile_points != c->tile_points)
@@ -407,6 +407,13 @@ int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t s
     a.t_team = reduced ? nullptr : out->t_team;
     a.t_opp = reduced ? nullptr : out->t_opp;
     a.best = out->best ? out->best : b->d_best;
+    if (power) {
+        a.power = 1;
+        a.p_buffer = power->buffer_s;
+        a.p_vmin = power->v_min;
+        a.p_vmax = power->v_max;
+        a.v0_out = v0_out;
+    }
     int per_cu = c->wg_per_cu > 0 ? c->wg_per_cu : search_occupancy(c->p.n_samples, c->waves);
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
@@ -640,6 +647,35 @@ int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     return run_batch(c, &c->scratch, out, st, true);
 }
 
+int dpps_search_power(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                      const dpps_robot *robots, const dpps_window *windows,
+                      const dpps_power_params *pp, const dpps_outputs *out, float *d_v0,
+                      void *hip_stream)
+{
+    if (!c || !pp || !out) return fail(DPPS_E_INVALID, "NULL argument");
+    if (!(pp->buffer_s >= 0.0f) || !isfinite(pp->buffer_s) || !(pp->v_min > 0.0f) ||
+        !(pp->v_max >= pp->v_min) || !isfinite(pp->v_max) || pp->v_max > 100.0f ||
+        pp->reserved != 0)
+        return fail(DPPS_E_INVALID, "power: buffer >= 0, 0 < v_min <= v_max <= 100, reserved 0");
+    if (c->p.out_flags & DPPS_OUT_REDUCED)
+        return fail(DPPS_E_UNSUPPORTED, "the power search has one variant per point: no REDUCED");
+    if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (n_frames == 0) return DPPS_OK;
+    if (!frames) return fail(DPPS_E_INVALID, "NULL input array");
+    // one flat variant per frame (its speed is computed per point)
+    std::vector<dpps_frame> fr(frames, frames + n_frames);
+    std::vector<dpps_variant> one(1, dpps_variant{DPPS_FLAT, pp->v_min});
+    for (dpps_frame &F : fr) {
+        F.n_variants = 1;
+        F.variant_off = 0;
+    }
+    int rc = stage_batch(c, &c->scratch, n_frames, fr.data(), robots, windows, one.data(), st);
+    if (rc) return rc;
+    return run_batch(c, &c->scratch, out, st, true, pp, d_v0);
+}
+
 int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
                     const dpps_robot *robots, const dpps_variant *variants,
                     const dpps_ray_params *rp, const dpps_ray_outputs *out, void *hip_stream)
@@ -761,6 +797,13 @@ int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
 // autotuner: launch shapes timed on the caller's batch, cached per class
 // ----------------------------------------------------------------------------
 
+#ifndef DPPS_KERNEL_REV
+#define DPPS_KERNEL_REV "unknown"
+#endif
+
+// Cache key of a launch shape: architecture, kernel sources, K, largest
+// variant and interceptor counts, log2 points per frame and frames, output
+// mode.
 static std::string tune_key(const dpps_ctx *c, const dpps_batch *b)
 {
     hipDeviceProp_t prop;
@@ -779,8 +822,9 @@ static std::string tune_key(const dpps_ctx *c, const dpps_batch *b)
     for (int64_t x = pts / nf; x > 1; x >>= 1) ++lp;
     for (int x = nf; x > 1; x >>= 1) ++lf;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|K%d|V%d|R%d|P2^%d|F2^%d|%s", arch.c_str(), c->p.n_samples, vmax,
-             rmax, lp, lf, (c->p.out_flags & DPPS_OUT_REDUCED) ? "reduced" : "full");
+    snprintf(buf, sizeof buf, "%s|rev%s|K%d|V%d|R%d|P2^%d|F2^%d|%s", arch.c_str(), DPPS_KERNEL_REV,
+             c->p.n_samples, vmax, rmax, lp, lf,
+             (c->p.out_flags & DPPS_OUT_REDUCED) ? "reduced" : "full");
     return buf;
 }
 

@@ -58,6 +58,7 @@ struct TileDev {
 struct TileRec {
     unsigned long long key;
     float t_team, t_opp;
+    float v0, pad;          // kick speed of that pass (the per-point power search)
 };
 
 // Device-side copy of a frame (the public struct plus derived indices).
@@ -82,6 +83,10 @@ struct LaunchArgs {
     int32_t persistent;
     uint32_t *counter;      // persistent work counter; the finalize kernel resets it
     TileRec *tile_rec;      // one per tile
+    // per-point passing power (Eq. 1-2) instead of the frames' variants
+    int32_t power;
+    float p_buffer, p_vmin, p_vmax;
+    float *v0_out;          // power per point (may be NULL)
     uint8_t *mask;
     float *score;
     float *t_team;

@@ -430,23 +430,41 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
 // Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
 // hold lane v's variant (lanes >= n_var: type -1).  On return lane v
 // (< n_var) holds that variant's results.
+// Passing power (Sec. 4.1, Eq. 1-2) for a pass over d64 metres whose
+// receiver arrives after t_recv seconds: the ball should arrive t_recv +
+// buffer; ignoring the sliding phase, the speed after it is (d + a t^2/2) / t
+// while the ball still rolls at t, else the slowest ball that reaches the
+// point, sqrt(2 a d); the kick speed is that over the slide ratio, clamped to
+// [vmin, vmax]; 0 when no teammate can receive.
+__device__ __forceinline__ double pass_power(const DevParams &P, double d64, float t_recv,
+                                             double buffer, double vmin, double vmax)
+{
+    if (!(t_recv < INFINITY)) return 0.0;
+    const double t = (double)t_recv + buffer;
+    const double a = P.a_r_d;
+    const double v1 = d64 >= 0.5 * a * t * t ? (d64 + 0.5 * a * t * t) / t : sqrt(2.0 * a * d64);
+    return fmin(fmax(v1 / P.ratio_d, vmin), vmax);
+}
+
 // SBIP of every staged variant along one path of length d (metres; LA = d
 // scaled by amax) whose path frame is in pr: robot stage over the lane's
 // samples (lanes = samples), critical speeds, first crossings through xr.  On
 // return lane v (a staged variant) holds its first team / opponent crossing
-// samples (K: none).
-template <int KPL>
+// samples (K: none).  With POWER the frame's variants are replaced by one
+// flat pass at the power of Eq. 1-2 (lane 0), whose receiver is the first
+// teammate at the last sample, the point itself; its speed is returned in v0.
+template <int KPL, bool POWER>
 __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParams &P,
                                                const float4 *pr, uint32_t *xr, float myv0,
                                                int mytype, float d, float LA, int &my_kt,
-                                               int &my_ko)
+                                               int &my_ko, double d64 = 0.0, double buffer = 0.0,
+                                               double vmin = 0.0, double vmax = 0.0,
+                                               double *v0 = nullptr)
 {
     const int l = lane_id();
     const int K = KPL * 64;
     const int n_tm = uni(S.n_tm), n_op = uni(S.n_op);
     const float invK = 1.0f / (float)K;
-    const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
-    const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
 
     float fs[KPL], sk[KPL], Tt[KPL], To[KPL];
 #pragma unroll
@@ -472,6 +490,15 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
         Tt[q] *= P.invA2;  // seconds
         To[q] *= P.invA2;
     }
+    if (POWER) {
+        const float t_recv = readlane_f(Tt[KPL - 1], 63);
+        const double v = pass_power(P, d64, t_recv, buffer, vmin, vmax);
+        *v0 = v;
+        myv0 = (float)v;
+        mytype = (l == 0 && v > 0.0) ? DPPS_FLAT : -1;
+    }
+    const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
+    const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
     if (flat_m) {
         float vt[KPL], vo[KPL];
         side_vcrit<KPL, false>(P, n_tm, Tt, sk, sk, vt);
@@ -500,11 +527,14 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
 
 // Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
 // hold lane v's variant (lanes >= n_var: type -1).  On return lane v
-// (< n_var) holds that variant's results.
-template <int KPL>
+// (< n_var) holds that variant's results.  With POWER the point has one flat
+// variant at its own passing power (returned in o_v0), computed from the
+// launch's buffer and kick range.
+template <int KPL, bool POWER>
 __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
                            float myv0, int mytype, float cx, float cy, double cx64,
-                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to)
+                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to,
+                           float &o_v0, const LaunchArgs &a)
 {
     const int l = lane_id();
     const int K = KPL * 64;
@@ -513,8 +543,13 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
     const float ex = cx - bx, ey = cy - by;
     const float d = hsqrt(fmaf(ex, ex, ey * ey));
     const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
+    const double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
+    const double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
     int my_kt, my_ko;
-    sbip_crossings<KPL>(S, P, pr, xr, myv0, mytype, d, LA, my_kt, my_ko);
+    double v0 = 0.0;
+    sbip_crossings<KPL, POWER>(S, P, pr, xr, myv0, mytype, d, LA, my_kt, my_ko, d64,
+                               (double)a.p_buffer, (double)a.p_vmin, (double)a.p_vmax, &v0);
+    o_v0 = (float)v0;
     // open goal angle (lanes = opponents)
     const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
     // 4. finish: lanes = variants
@@ -522,10 +557,8 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
     o_feas = 0;
     o_tt = INFINITY;
     o_to = INFINITY;
-    if (l < n_var) {
-        const VarConst c = S.vc[l];
-        double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
-        double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
+    if (l < n_var && (!POWER || v0 > 0.0)) {
+        const VarConst c = POWER ? var_const(P, DPPS_FLAT, (float)v0) : S.vc[l];
         bool reach = d64 >= 1e-9 && d64 <= c.D && d64 >= c.sf_reach;
         double tt = INFINITY, to = INFINITY;
         if (reach) {
@@ -548,8 +581,9 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
     }
 }
 
-// At most 128 VGPRs, so four waves fit on each SIMD.
-template <int KPL>
+// At most 128 VGPRs, so four waves fit on each SIMD.  POWER: one flat pass
+// per point at the point's own passing power (Eq. 1-2).
+template <int KPL, bool POWER>
 __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
@@ -596,7 +630,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         const int n_var = S.n_var;
         const int npts = min(TP, W.npts - tile.p0);
         unsigned long long bkey = 0ull;
-        float btt = INFINITY, bto = INFINITY;
+        float btt = INFINITY, bto = INFINITY, bv0 = 0.0f;
         for (int slot = w; slot < npts; slot += nw) {
             const int p = tile.p0 + slot;
             const int j = p / W.nx, i = p - j * W.nx;
@@ -604,10 +638,11 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const float mj = (float)(W.j0 + j) - W.halfNy;
             const float cx = W.h * mi, cy = W.h * mj;
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
-            float sc, tt, to;
+            float sc, tt, to, pv0;
             int fe;
-            eval_point<KPL>(S, P, PR[w], XR[w], myv0, mytype, cx, cy, cx64, cy64, sc, fe, tt,
-                            to);
+            eval_point<KPL, POWER>(S, P, PR[w], XR[w], myv0, mytype, cx, cy, cx64, cy64, sc, fe,
+                                   tt, to, pv0, a);
+            if (POWER && l == 0 && a.v0_out) a.v0_out[W.out_base + p] = pv0;
             unsigned long long key = 0ull;
             if (fe) {
                 uint32_t lin = (uint32_t)(W.elem_base + myvid * W.npts + p);
@@ -618,6 +653,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                 bkey = key;
                 btt = tt;
                 bto = to;
+                bv0 = POWER ? pv0 : myv0;
             }
             if (reduced) {
                 unsigned long long pk = wave_max_u64(key);
@@ -643,10 +679,13 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         const unsigned long long who = __ballot(bkey == wk);
         const int src = who ? __builtin_ctzll(who) : 0;
         const float wtt = readlane_f(btt, src), wto = readlane_f(bto, src);
+        const float wv0 = readlane_f(bv0, src);
         if (l == 0) {
             O.wbest[w].key = wk;
             O.wbest[w].t_team = wtt;
             O.wbest[w].t_opp = wto;
+            O.wbest[w].v0 = wv0;
+            O.wbest[w].pad = 0.0f;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -682,6 +721,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
     const FrameDev F = a.frames[f];
     TileRec r;
     r.key = 0ull;
+    r.v0 = 0.0f;
+    r.pad = 0.0f;
     r.t_team = INFINITY;
     r.t_opp = INFINITY;
     for (int k = tid; k < F.tile_count; k += blockDim.x) {
@@ -714,7 +755,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
         const float mi = (float)(W.i0 + i) - W.halfNx;
         const float mj = (float)(W.j0 + j) - W.halfNy;
         const dpps_variant var = a.variants[F.variant_off + v];
-        const VarConst c = var_const(a.P, var.type, var.v0);
+        // the per-point power search passes one flat kick at the point's power
+        const int ptype = a.power ? DPPS_FLAT : var.type;
+        const float pv0 = a.power ? bestr.v0 : var.v0;
+        const VarConst c = var_const(a.P, ptype, pv0);
         double ex64 = (double)W.h * (double)mi - (double)F.ball_x;
         double ey64 = (double)W.h * (double)mj - (double)F.ball_y;
         b.found = 1;
@@ -722,10 +766,10 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
         b.variant = v;
         b.i = i;
         b.j = j;
-        b.type = var.type;
+        b.type = ptype;
         b.x = W.h * mi;
         b.y = W.h * mj;
-        b.v0 = var.v0;
+        b.v0 = pv0;
         b.score = __uint_as_float((uint32_t)(bestr.key >> 32));
         b.t_team = bestr.t_team;
         b.t_opp = bestr.t_opp;
@@ -739,8 +783,14 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
                       hipEvent_t e0, hipEvent_t e1)
 {
     if (e0) (void)hipEventRecord(e0, st);
-    if (a.n_tiles > 0 && grid > 0)
-        hipLaunchKernelGGL(search_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg), 0, st, a);
+    if (a.n_tiles > 0 && grid > 0) {
+        if (a.power)
+            hipLaunchKernelGGL((search_kernel<KPL, true>), dim3(grid), dim3(64 * waves_per_wg), 0,
+                               st, a);
+        else
+            hipLaunchKernelGGL((search_kernel<KPL, false>), dim3(grid), dim3(64 * waves_per_wg), 0,
+                               st, a);
+    }
     if (e1) (void)hipEventRecord(e1, st);
     if (a.n_frames > 0)
         hipLaunchKernelGGL(finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
@@ -800,7 +850,7 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
     const double L = ray_length(P, bx, by, ux, uy);
     path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, bx, by);
     int my_kt, my_ko;
-    sbip_crossings<KPL>(S, P, pr, xr, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
+    sbip_crossings<KPL, false>(S, P, pr, xr, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
                         my_ko);
 
     RayOut o;
@@ -1064,10 +1114,10 @@ int search_occupancy(int K, int waves_per_wg)
     hipError_t e = hipErrorInvalidValue;
     const int bs = 64 * waves_per_wg;
     switch (K / 64) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1>, bs, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2>, bs, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3>, bs, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4>, bs, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1, false>, bs, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2, false>, bs, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3, false>, bs, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4, false>, bs, 0); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;

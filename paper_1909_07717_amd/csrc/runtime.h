@@ -109,7 +109,8 @@ Layout table_layout(const dpps::HostTables &T);
 void pack_tables(const dpps::HostTables &T, const Layout &L, char *dst);
 int batch_reserve(dpps_ctx *c, dpps_batch *b, const Layout &L);
 int batch_upload(dpps_ctx *c, dpps_batch *b);
-int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st, bool timed);
+int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t st, bool timed,
+              const dpps_power_params *power = nullptr, float *v0_out = nullptr);
 int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *frames,
                 const dpps_robot *robots, const dpps_window *windows,
                 const dpps_variant *variants, hipStream_t st);

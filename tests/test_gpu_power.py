@@ -1,0 +1,111 @@
+"""GPU parity of the per-point passing-power search (Sec. 4.1, Eq. 1-2)
+against the FP64 oracle: dpps_search_power through the C ABI.
+
+Per point, outside the oracle's ambiguity bands: identical feasibility
+flags, interception times within 1e-4 s, scores within 1e-5 relative, and
+the kick speed within 1e-5 relative (it follows the receiver's arrival time,
+which the kernel takes in FP32 from its robot stage).  The chosen pass is
+feasible (or ambiguous) in the oracle and scores within 1e-5 of its best.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1909_07717_amd.framegen import Params, config_small, full_window, random_frame
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BUF, VMIN, VMAX = 0.3, 1.0, 6.5
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_07717_amd import binding
+    return binding
+
+
+def _check(p, f, out, v0, i, off, n):
+    o = O.power_search(f, p, BUF, VMIN, VMAX, bands=True)
+    sl = slice(off, off + n)
+    mask = out.mask[sl].cpu().numpy()
+    score = out.score[sl].cpu().numpy().astype(np.float64)
+    tt = out.t_team[sl].cpu().numpy().astype(np.float64)
+    to = out.t_opp[sl].cpu().numpy().astype(np.float64)
+    v = v0[sl].cpu().numpy().astype(np.float64)
+    amb = o["ambig"] > 0
+    # where the speed is clamped the margin field can be flat near the 0.1 s
+    # threshold, so its band covers more points (1.5 % on one 5 cm window)
+    assert amb.mean() < 3e-2, amb.mean()
+    ok = ~amb
+    np.testing.assert_allclose(v, o["v0"], rtol=1e-5, atol=0)
+    assert (mask[ok] == o["mask"][ok]).all()
+    for a, b in ((tt, o["t_team"]), (to, o["t_opp"])):
+        ia, ib = np.isinf(a[ok]), np.isinf(b[ok])
+        assert (ia == ib).all()
+        assert (np.abs(a[ok][~ia] - b[ok][~ib]) <= 1e-4).all()
+    both = ok & (mask == 1) & (o["mask"] == 1)
+    assert (np.abs(score[both] - o["score"][both]) <= 1e-5 * np.abs(o["score"][both])).all()
+    best = out.best_host()[i]
+    if o["best"] < 0:
+        assert best["found"] == 0
+        return
+    assert best["found"] == 1
+    # the chosen element, relative to this frame's outputs
+    e = int(best["j"]) * f.windows[0][3] + int(best["i"]) if len(f.windows) == 1 else None
+    if e is not None:
+        assert o["mask"][e] == 1 or amb[e]
+        assert o["score"][e] >= o["best_score"] * (1 - 1e-5) or amb[e]
+        assert float(best["v0"]) == pytest.approx(v[e], rel=1e-6)
+    assert abs(float(best["score"]) - o["best_score"]) <= 1e-5 * o["best_score"] or amb[o["best"]]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_power_small_frames(B, seed):
+    p = Params(n_samples=64).as_f32()
+    s = B.Searcher(p)
+    f = config_small(seed)
+    out, v0 = s.search_power([f], BUF, VMIN, VMAX)
+    torch.cuda.synchronize()
+    _check(p, f, out, v0, 0, 0, 2806)
+    s.close()
+
+
+def test_power_batch_of_5cm_windows(B):
+    # 8v8 frames, a few 5 cm windows each, K = 128: several tiles per window
+    p = Params(n_samples=128).as_f32()
+    s = B.Searcher(p)
+    frames = []
+    for i in range(3):
+        f = random_frame(np.random.default_rng(600 + i), 8, 8, Params())
+        f.windows = [(np.float32(0.05), 60 + 30 * i, 40, 47, 33)]
+        frames.append(f)
+    out, v0 = s.search_power(frames, BUF, VMIN, VMAX)
+    torch.cuda.synchronize()
+    off = 0
+    for i, f in enumerate(frames):
+        n = 47 * 33
+        _check(p, f, out, v0, i, off, n)
+        off += n
+    s.close()
+
+
+def test_power_lone_passer_and_invalid_arguments(B):
+    p = Params(n_samples=64).as_f32()
+    s = B.Searcher(p)
+    f = config_small(9)
+    lone = f.copy()
+    lone.team = f.team[f.passer:f.passer + 1].copy()
+    lone.passer = 0
+    lone.ball = lone.team[0, :2].copy()
+    out, v0 = s.search_power([lone], BUF, VMIN, VMAX)
+    torch.cuda.synchronize()
+    assert (v0.cpu().numpy() == 0).all()
+    assert out.mask.cpu().numpy().sum() == 0 and out.best_host()[0]["found"] == 0
+    for args in ((-0.1, VMIN, VMAX), (BUF, 0.0, VMAX), (BUF, 3.0, 2.0),
+                 (BUF, VMIN, float("nan"))):
+        with pytest.raises(B.DppsError):
+            s.search_power([f], *args)
+    s.close()
