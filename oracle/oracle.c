@@ -1,6 +1,6 @@
 /*
  * oracle.c -- plain, slow FP64 reference of the SBIP-DPPS passing-point search
- * (arXiv 1909.07717, Sec. 4.1-4.3).
+ * (arXiv 1909.07717, Sec. 4.1-4.4).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
  * or calls this file; only the test suite, the smoke check and the CPU
@@ -777,4 +777,190 @@ int64_t orc_power_search(const orc_params *P, const orc_world *W, int n_win, con
     return base;
 }
 
-int orc_abi_version(void) { return 3; }
+/* ------------------------------------------------------------------------ */
+/* Shooting decision (Sec. 4.4): the shot-angle test fused with the         */
+/* interception prediction along the shot.  Readings (the paper gives no    */
+/* numbers or construction details):                                        */
+/*  - the goal mouth as seen from the shooter c spans the directions         */
+/*    [lo, hi] to the posts (depth to the goal line floored at goal_eps, as  */
+/*    for the open angle); opponent discs of the robot radius in front of    */
+/*    the goal line shadow directions, exactly as for the open goal angle;   */
+/*    a shooter inside an opponent disc has no open direction;              */
+/*  - the "valid angle" of a shot is the width of the widest open gap of    */
+/*    the mouth, and the shot aims at that gap's centre (ties go to the gap  */
+/*    with the lower angle); with no open direction the shot aims at the     */
+/*    goal centre;                                                          */
+/*  - the shot is a flat kick at v_shot along the aim to the goal line,     */
+/*    sampled like a pass (K samples uniform in distance, the kick point     */
+/*    excluded, the goal line included); an opponent intercepts at a sample  */
+/*    it reaches no later than the ball (teammates never block a shot);      */
+/*  - slack = the smallest (opponent arrival - ball time) over the samples  */
+/*    the ball gets to, +inf with no opponents; the shot is intercepted      */
+/*    exactly when slack <= 0;                                               */
+/*  - shoot = (widest gap >= min_angle) and (the ball reaches the goal line) */
+/*    and (slack > margin_s).                                                */
+/* ------------------------------------------------------------------------ */
+#define ORC_AMB_ANGLE 16  /* gap-width decision or aim within the angle band */
+
+typedef struct {
+    double v_shot, min_angle, margin_s, eps_angle, eps_aim;
+} orc_shot_params;
+
+typedef struct {
+    int32_t shoot, reachable, ambig, n_gaps;
+    double aim, gap, open_angle, length, t_goal, slack, slack_sens, second_gap;
+} orc_shot_result;
+
+/* Open gaps of the goal mouth seen from c: fills starts/widths in
+ * increasing angle (at most n_opp + 1 gaps) and returns their number; -1
+ * when c lies inside an opponent disc.  Writes the mouth's ends. */
+static int shot_gaps(const orc_params *P, const orc_world *W, double cx, double cy, double *lo,
+                     double *hi, double *gs, double *gw)
+{
+    double dx = P->goal_x - cx;
+    if (dx < P->goal_eps) dx = P->goal_eps;
+    *lo = atan2(-0.5 * P->goal_width - cy, dx);
+    *hi = atan2(0.5 * P->goal_width - cy, dx);
+    double a[32], b[32];
+    int n = 0;
+    for (int o = 0; o < W->n_opp && o < 32; ++o) {
+        const double *r = W->opp + 4 * o;
+        if (r[0] >= P->goal_x) continue;
+        double ox = r[0] - cx, oy = r[1] - cy;
+        double rho = sqrt(ox * ox + oy * oy);
+        if (rho <= P->robot_radius) return -1;
+        double phi = atan2(oy, ox);
+        double al = asin(P->robot_radius / rho);
+        double s = fmax(phi - al, *lo), e = fmin(phi + al, *hi);
+        if (e > s) { a[n] = s; b[n] = e; ++n; }
+    }
+    /* insertion sort by start */
+    for (int i = 1; i < n; ++i) {
+        double sa = a[i], sb = b[i];
+        int j = i - 1;
+        while (j >= 0 && a[j] > sa) { a[j + 1] = a[j]; b[j + 1] = b[j]; --j; }
+        a[j + 1] = sa; b[j + 1] = sb;
+    }
+    /* walk the mouth from lo: a gap runs from the covered edge to the next
+     * blocked start */
+    int ng = 0;
+    double edge = *lo;
+    for (int i = 0; i < n; ++i) {
+        if (a[i] > edge) { gs[ng] = edge; gw[ng] = a[i] - edge; ++ng; }
+        if (b[i] > edge) edge = b[i];
+    }
+    if (*hi > edge) { gs[ng] = edge; gw[ng] = *hi - edge; ++ng; }
+    return ng;
+}
+
+/* Along the shot from c in direction aim to the goal line: path length, ball
+ * time at the goal line (inf when the ball stops short) and the slack. */
+static void shot_path(const orc_params *P, const orc_world *W, double cx, double cy, double aim,
+                      double v_shot, double *L_out, double *t_goal, double *slack)
+{
+    double dx = P->goal_x - cx;
+    if (dx < P->goal_eps) dx = P->goal_eps;
+    double ux = cos(aim), uy = sin(aim);
+    double L = dx / ux;
+    double D, sf;
+    orc_ball_range(P, ORC_FLAT, v_shot, &D, &sf);
+    *L_out = L;
+    *t_goal = L <= D ? orc_ball_time(P, ORC_FLAT, v_shot, L) : INFINITY;
+    double m = INFINITY;
+    int K = P->n_samples;
+    for (int k = 0; k < K; ++k) {
+        double s = (double)(k + 1) / (double)K * L;
+        if (s > D) break;
+        double tb = orc_ball_time(P, ORC_FLAT, v_shot, s);
+        double px = cx + s * ux, py = cy + s * uy;
+        for (int o = 0; o < W->n_opp; ++o) {
+            double tr = robot_time_to(P, W->opp + 4 * o, px, py);
+            if (tr - tb < m) m = tr - tb;
+        }
+    }
+    *slack = m;
+}
+
+void orc_shot(const orc_params *P, const orc_shot_params *S, const orc_world *W, double cx,
+              double cy, int bands, orc_shot_result *out)
+{
+    double lo, hi, gs[40], gw[40];
+    int ng = shot_gaps(P, W, cx, cy, &lo, &hi, gs, gw);
+    double best = 0.0, start = 0.0, second = 0.0, total = 0.0;
+    int have = 0;
+    for (int g = 0; g < ng; ++g) {
+        total += gw[g];
+        if (!have || gw[g] > best) {
+            if (have) second = fmax(second, best);
+            best = gw[g]; start = gs[g]; have = 1;
+        } else {
+            second = fmax(second, gw[g]);
+        }
+    }
+    double dx = P->goal_x - cx;
+    if (dx < P->goal_eps) dx = P->goal_eps;
+    double aim = best > 0.0 ? start + 0.5 * best : atan2(-cy, dx);
+    memset(out, 0, sizeof *out);
+    out->n_gaps = ng < 0 ? 0 : ng;
+    out->gap = best;
+    out->second_gap = second;
+    out->open_angle = total;
+    out->aim = aim;
+    shot_path(P, W, cx, cy, aim, S->v_shot, &out->length, &out->t_goal, &out->slack);
+    double D, sf;
+    orc_ball_range(P, ORC_FLAT, S->v_shot, &D, &sf);
+    out->reachable = out->length <= D;
+    out->shoot = best >= S->min_angle && out->reachable && out->slack > S->margin_s;
+    if (!bands) return;
+    int amb = 0;
+    if (fabs(out->length - D) < P->eps_reach) amb |= ORC_AMB_REACH;
+    if (fabs(best - S->min_angle) < S->eps_angle) amb |= ORC_AMB_ANGLE;  /* decision */
+    if (have && best - second < S->eps_angle) amb |= ORC_AMB_ANGLE;      /* which gap */
+    if (best > 0.0 && best < S->eps_angle) amb |= ORC_AMB_ANGLE;         /* aim rule */
+    for (int o = 0; o < W->n_opp; ++o) {                                  /* inside rule */
+        const double *r = W->opp + 4 * o;
+        double rho = hypot(r[0] - cx, r[1] - cy);
+        if (r[0] < P->goal_x && fabs(rho - P->robot_radius) < P->eps_reach) amb |= ORC_AMB_ANGLE;
+    }
+    /* how much the slack moves when the aim moves by eps_aim (the float32
+     * rounding of the aim on the device is well inside it) */
+    double sens = 0.0;
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+        double L2, tg2, s2;
+        shot_path(P, W, cx, cy, aim + sgn * S->eps_aim, S->v_shot, &L2, &tg2, &s2);
+        double dsl = isinf(s2) && isinf(out->slack) ? 0.0 : fabs(s2 - out->slack);
+        if (!(dsl <= sens)) sens = dsl;
+    }
+    out->slack_sens = sens;
+    if (fabs(out->slack - S->margin_s) < P->eps_cross_t + sens) amb |= ORC_AMB_MARGIN;
+    out->ambig = amb;
+}
+
+/* The shot decision from every point of the windows (the ball placed there,
+ * everything else unchanged). */
+int64_t orc_shot_search(const orc_params *P, const orc_shot_params *S, const orc_world *W,
+                        int n_win, const double *win_h, const int32_t *win_int, int bands,
+                        orc_shot_result *res)
+{
+    int64_t base = 0;
+    for (int w = 0; w < n_win; ++w) {
+        double h = win_h[w];
+        int i0 = win_int[4 * w], j0 = win_int[4 * w + 1];
+        int nx = win_int[4 * w + 2], ny = win_int[4 * w + 3];
+        int64_t npts = (int64_t)nx * ny;
+#ifdef _OPENMP
+        int nt = P->n_threads > 0 ? P->n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nt)
+#endif
+        for (int64_t p = 0; p < npts; ++p) {
+            int i = (int)(p % nx), j = (int)(p / nx);
+            double cx, cy;
+            orc_point(P, h, i0 + i, j0 + j, &cx, &cy);
+            orc_shot(P, S, W, cx, cy, bands, res + base + p);
+        }
+        base += npts;
+    }
+    return base;
+}
+
+int orc_abi_version(void) { return 4; }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN = 1, 2, 4, 8
+AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN, AMB_ANGLE = 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:
@@ -62,6 +62,18 @@ class OrcRayResult(C.Structure):
                 ("ambig", C.c_int32)] + [(n, C.c_double) for n in (
                     "t_team", "t_opp", "margin", "score", "s_recv", "x", "y", "open_angle",
                     "refract", "length")]
+
+
+class OrcShotParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("v_shot", "min_angle", "margin_s", "eps_angle",
+                                           "eps_aim")]
+
+
+class OrcShotResult(C.Structure):
+    _fields_ = [("shoot", C.c_int32), ("reachable", C.c_int32), ("ambig", C.c_int32),
+                ("n_gaps", C.c_int32)] + [(n, C.c_double) for n in (
+                    "aim", "gap", "open_angle", "length", "t_goal", "slack", "slack_sens",
+                    "second_gap")]
 
 
 # Parity bands (widths of the ambiguity regions computed by the oracle).
@@ -115,6 +127,10 @@ def lib():
         L.orc_power_search.argtypes = [P, Wp, C.c_int, pd, pi32, d, d, d, C.c_int, pu8, pd, pd,
                                        pd, pd, pu8]
         L.orc_power_search.restype = i64
+        SP, SR = C.POINTER(OrcShotParams), C.POINTER(OrcShotResult)
+        L.orc_shot.argtypes = [P, SP, Wp, d, d, C.c_int, SR]
+        L.orc_shot_search.argtypes = [P, SP, Wp, C.c_int, pd, pi32, C.c_int, SR]
+        L.orc_shot_search.restype = i64
         _lib = L
     return _lib
 
@@ -357,3 +373,50 @@ def power_search(frame, params, buffer_s=0.3, v_min=1.0, v_max=6.5, bands=False,
     out["best"] = best
     out["best_score"] = float(out["score"][best]) if best >= 0 else float("-inf")
     return out
+
+
+# ---------------------------------------------------------------------------
+# shooting decision (Sec. 4.4)
+# ---------------------------------------------------------------------------
+
+SHOT_FIELDS = [k for k, _ in OrcShotResult._fields_]
+
+
+def _shot_params(v_shot, min_angle, margin_s, eps_angle=1e-5, eps_aim=2e-6):
+    s = OrcShotParams()
+    s.v_shot, s.min_angle, s.margin_s = float(v_shot), float(min_angle), float(margin_s)
+    s.eps_angle, s.eps_aim = float(eps_angle), float(eps_aim)
+    return s
+
+
+def shot(frame, params, cx=None, cy=None, v_shot=6.5, min_angle=0.05, margin_s=0.0,
+         bands=False, **band_eps):
+    """Shooting decision from (cx, cy), by default from the frame's ball:
+    a dict of the oracle's result fields."""
+    L = lib()
+    P = make_params(params, **band_eps)
+    wh = _WorldHolder(frame)
+    cx = float(frame.ball[0]) if cx is None else float(cx)
+    cy = float(frame.ball[1]) if cy is None else float(cy)
+    r = OrcShotResult()
+    L.orc_shot(C.byref(P), C.byref(_shot_params(v_shot, min_angle, margin_s)), C.byref(wh.w),
+               cx, cy, int(bands), C.byref(r))
+    return {k: getattr(r, k) for k in SHOT_FIELDS}
+
+
+def shot_search(frame, params, v_shot=6.5, min_angle=0.05, margin_s=0.0, bands=False,
+                n_threads: int = 0, **band_eps):
+    """The shooting decision from every point of the frame's windows (the ball
+    placed there); a dict of flat arrays in window-major, row-major order."""
+    L = lib()
+    P = make_params(params, n_threads, **band_eps)
+    wh = _WorldHolder(frame)
+    win_h = np.array([w[0] for w in frame.windows], dtype=np.float64)
+    win_i = np.array([[w[1], w[2], w[3], w[4]] for w in frame.windows], dtype=np.int32).reshape(-1)
+    n = int(sum(w[3] * w[4] for w in frame.windows))
+    res = (OrcShotResult * max(n, 1))()
+    L.orc_shot_search(C.byref(P), C.byref(_shot_params(v_shot, min_angle, margin_s)),
+                      C.byref(wh.w), len(win_h), _ptr(win_h, C.c_double),
+                      _ptr(win_i, C.c_int32), int(bands), res)
+    a = np.ctypeslib.as_array(res)[:n]
+    return {k: np.array(a[k]) for k in SHOT_FIELDS}
