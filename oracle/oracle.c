@@ -808,7 +808,7 @@ typedef struct {
 
 typedef struct {
     int32_t shoot, reachable, ambig, n_gaps;
-    double aim, gap, open_angle, length, t_goal, slack, slack_sens, second_gap;
+    double aim, gap, open_angle, length, t_goal, slack, slack_sens, second_gap, length_sens;
 } orc_shot_result;
 
 /* Open gaps of the goal mouth seen from c: fills starts/widths in
@@ -913,7 +913,6 @@ void orc_shot(const orc_params *P, const orc_shot_params *S, const orc_world *W,
     out->shoot = best >= S->min_angle && out->reachable && out->slack > S->margin_s;
     if (!bands) return;
     int amb = 0;
-    if (fabs(out->length - D) < P->eps_reach) amb |= ORC_AMB_REACH;
     if (fabs(best - S->min_angle) < S->eps_angle) amb |= ORC_AMB_ANGLE;  /* decision */
     if (have && best - second < S->eps_angle) amb |= ORC_AMB_ANGLE;      /* which gap */
     if (best > 0.0 && best < S->eps_angle) amb |= ORC_AMB_ANGLE;         /* aim rule */
@@ -922,16 +921,21 @@ void orc_shot(const orc_params *P, const orc_shot_params *S, const orc_world *W,
         double rho = hypot(r[0] - cx, r[1] - cy);
         if (r[0] < P->goal_x && fabs(rho - P->robot_radius) < P->eps_reach) amb |= ORC_AMB_ANGLE;
     }
-    /* how much the slack moves when the aim moves by eps_aim (the float32
-     * rounding of the aim on the device is well inside it) */
-    double sens = 0.0;
+    /* how much the slack and the path length move when the aim moves by
+     * eps_aim (the float32 rounding of the aim on the device is well inside
+     * it); a shooter on the goal line aims almost along it, where the length
+     * is ill-conditioned */
+    double sens = 0.0, lsens = 0.0;
     for (int sgn = -1; sgn <= 1; sgn += 2) {
         double L2, tg2, s2;
         shot_path(P, W, cx, cy, aim + sgn * S->eps_aim, S->v_shot, &L2, &tg2, &s2);
         double dsl = isinf(s2) && isinf(out->slack) ? 0.0 : fabs(s2 - out->slack);
         if (!(dsl <= sens)) sens = dsl;
+        if (!(fabs(L2 - out->length) <= lsens)) lsens = fabs(L2 - out->length);
     }
     out->slack_sens = sens;
+    out->length_sens = lsens;
+    if (fabs(out->length - D) < P->eps_reach + lsens) amb |= ORC_AMB_REACH;
     if (fabs(out->slack - S->margin_s) < P->eps_cross_t + sens) amb |= ORC_AMB_MARGIN;
     out->ambig = amb;
 }

@@ -73,7 +73,7 @@ class OrcShotResult(C.Structure):
     _fields_ = [("shoot", C.c_int32), ("reachable", C.c_int32), ("ambig", C.c_int32),
                 ("n_gaps", C.c_int32)] + [(n, C.c_double) for n in (
                     "aim", "gap", "open_angle", "length", "t_goal", "slack", "slack_sens",
-                    "second_gap")]
+                    "second_gap", "length_sens")]
 
 
 # Parity bands (widths of the ambiguity regions computed by the oracle).
