@@ -155,6 +155,83 @@ def power_bench(steps: int, st):
             "v0_max": round(float(vv.max()), 4)}
 
 
+def shot_bench(n_frames: int, steps: int, lat_frames: int, st):
+    """Shooting decision (Sec. 4.4), flat shot at 6.5 m/s, gap threshold
+    0.05 rad: (a) from the ball of n_frames 8v8 frames per call, K = 128;
+    (b) the shot map of a full 5 cm lattice (43 621 shooter positions, 8
+    opponents), K = 256; (c) latency of one frame's decision, host inputs to
+    the record on the host.  (a) and (b) pack the frames once; the library
+    still stages them from the host on every call."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07717_amd import binding as Bn
+    from paper_1909_07717_amd import flops as FL
+    from paper_1909_07717_amd.framegen import Params, config_full, random_frame
+
+    res = {}
+    p = Params(n_samples=128).as_f32()
+    s = Bn.Searcher(p, device=0)
+    frames = [random_frame(np.random.default_rng(700 + i), 8, 8, Params())
+              for i in range(n_frames)]
+    pk = s.pack_shots(frames, map=False)
+    with torch.cuda.stream(st):
+        ball, _ = s.shot(pk, map=False, stream=st)
+    torch.cuda.synchronize()
+    n_shoot = int(Bn.shots_host(ball)[:n_frames]["shoot"].sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            s.shot(pk, map=False, stream=st, out=(ball, None))
+        e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["ball"] = {"workload": f"{n_frames} frames of 8v8, decision from the ball, K = 128",
+                   "ms_per_call": round(ms, 4),
+                   "decisions_per_s": round(n_frames / (ms * 1e-3), 1),
+                   "shoot_fraction": round(n_shoot / n_frames, 4)}
+    lat = []
+    b1 = torch.empty(Bn.SHOT_DT.itemsize, dtype=torch.uint8, device=ball.device)
+    host = torch.empty(Bn.SHOT_DT.itemsize, dtype=torch.uint8, pin_memory=True)
+    for i in range(100 + lat_frames):
+        a = time.perf_counter()
+        with torch.cuda.stream(st):
+            s.shot([frames[i % n_frames]], map=False, stream=st, out=(b1, None))
+            host.copy_(b1, non_blocking=True)
+        st.synchronize()
+        if i >= 100:
+            lat.append(time.perf_counter() - a)
+    lat = np.array(lat) * 1e3
+    res["latency_ms"] = {"p50": round(float(np.percentile(lat, 50)), 4),
+                         "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(lat.size),
+                         "path": "one frame per call, host inputs to the decision on the host"}
+    s.close()
+    p = Params(n_samples=256).as_f32()
+    s = Bn.Searcher(p, device=0)
+    f = config_full(100)
+    pk = s.pack_shots([f])
+    with torch.cuda.stream(st):
+        bm, mp = s.shot(pk, stream=st)
+    torch.cuda.synchronize()
+    n = 43621
+    n_shoot = int(Bn.shots_host(mp)[:n]["shoot"].sum())
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            s.shot(pk, stream=st, out=(bm, mp))
+        e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fl = n * FL.shot_flops(int(np.asarray(f.opp).shape[0]), 256)
+    res["map"] = {"workload": "shot map of the full 5 cm lattice 241x181, 8 opponents, K = 256",
+                  "ms_per_frame": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1),
+                  "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                  "shoot_fraction": round(n_shoot / n, 4)}
+    s.close()
+    return res
+
+
 def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
     """The paper's own DPPS form: 8v8 frames, 128 kick directions x 64 flat
     powers in [1, 6.5] m/s, K = 256 samples per ray.  Batched: n_frames frames
@@ -352,6 +429,8 @@ def main() -> int:
     rays = (ray_bench(args.ray_frames, 5, min(args.latency_frames, 2000), st)
             if args.ray_frames > 0 else None)
     power = power_bench(20, st) if args.ray_frames > 0 else None
+    shots = (shot_bench(4096, 20, min(args.latency_frames, 2000), st)
+             if args.ray_frames > 0 else None)
     sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
            if args.surrogate_frames > 0 else None)
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
@@ -386,6 +465,7 @@ def main() -> int:
         "batch": batch,
         "rays": rays,
         "power": power,
+        "shots": shots,
         "surrogate": sur,
         "serving": serving,
     }

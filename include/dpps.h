@@ -371,6 +371,58 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
                     const dpps_robot *robots, const dpps_variant *variants,
                     const dpps_ray_params *rp, const dpps_ray_outputs *out, void *hip_stream);
 
+/* ---- shooting decision (Sec. 4.4) ----------------------------------------
+ * The shot-angle test fused with the interception prediction along the shot.
+ * From a shooter position c (the frame's ball, and optionally every point of
+ * the frame's windows with the ball placed there):
+ *   - the goal mouth spans the directions from c to the two posts (the depth
+ *     to the goal line is floored at goal_eps); the frame's opponents
+ *     in front of the goal line shadow the directions that pass within
+ *     robot_radius of them, as for the open goal angle of dpps_search; a
+ *     shooter inside an opponent's radius has no open direction;
+ *   - gap = the widest open run of directions, the valid angle of the shot;
+ *     the shot aims at its centre (ties to the lower angle), or at the goal
+ *     centre when nothing is open;
+ *   - the shot is a flat kick at v_shot along the aim to the goal line,
+ *     sampled like a pass: K samples uniform in distance, the kick point
+ *     excluded, the goal-line point included; slack = the smallest
+ *     (earliest opponent arrival - ball time) over the samples the ball gets
+ *     to (+inf without opponents); an opponent intercepts exactly when
+ *     slack <= 0; teammates never block;
+ *   - shoot = gap >= min_angle and the ball reaches the goal line and
+ *     slack > margin_s.
+ * The frames' variants are not used. */
+typedef struct {
+    float v_shot;     /* flat kick speed of the shot, m/s (> 0; 6.5 = top of the kick range) */
+    float min_angle;  /* threshold on the widest open gap, rad (>= 0) */
+    float margin_s;   /* required slack, s (>= 0; 0 = not intercepted) */
+    int32_t reserved; /* must be 0 */
+} dpps_shot_params;
+
+typedef struct {
+    int32_t shoot;     /* the decision */
+    int32_t reachable; /* the ball reaches the goal line */
+    float aim;         /* direction of the shot, rad from +x */
+    float gap;         /* widest open gap, rad */
+    float open_angle;  /* sum of the open gaps, rad */
+    float length;      /* distance to the goal line along the aim, m */
+    float t_goal;      /* ball time to the goal line, s (+inf when it stops short) */
+    float slack;       /* s, see above */
+} dpps_shot;
+
+/* Decisions from each frame's ball into d_ball (n_frames records, device
+ * memory, required) and, when d_map is not NULL, from every point of the
+ * frames' windows into d_map: one record per point at the element index
+ * dpps_search_batch uses with one variant per frame (out_off + window base +
+ * j*nx + i; dpps_layout with n_variants = 1 packs them densely).
+ * Asynchronous on the stream; inputs are host arrays staged through the
+ * context and may be reused when the call returns.  Errors: DPPS_E_INVALID
+ * for bad parameters or frames (as dpps_search_batch), DPPS_E_DEVICE. */
+int dpps_shot_decision(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                       const dpps_robot *robots, const dpps_window *windows,
+                       const dpps_shot_params *sp, dpps_shot *d_ball, dpps_shot *d_map,
+                       void *hip_stream);
+
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);
 int dpps_version(void);

@@ -41,6 +41,10 @@ RAY_BEST_DT = np.dtype([("found", "<i4"), ("dir", "<i4"), ("variant", "<i4"), ("
                         ("score", "<f4"), ("t_team", "<f4"), ("t_opp", "<f4"),
                         ("open_angle", "<f4"), ("refract", "<f4"), ("pad", "<i4")])
 
+SHOT_DT = np.dtype([("shoot", "<i4"), ("reachable", "<i4"), ("aim", "<f4"), ("gap", "<f4"),
+                    ("open_angle", "<f4"), ("length", "<f4"), ("t_goal", "<f4"),
+                    ("slack", "<f4")])
+
 
 class DppsError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -65,6 +69,11 @@ class Outputs_C(C.Structure):
 
 class RayParams_C(C.Structure):
     _fields_ = [("n_dirs", C.c_int32), ("w_time", C.c_float), ("w_refract", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class ShotParams_C(C.Structure):
+    _fields_ = [("v_shot", C.c_float), ("min_angle", C.c_float), ("margin_s", C.c_float),
                 ("reserved", C.c_int32)]
 
 
@@ -135,6 +144,8 @@ def lib():
                                                    C.c_float, C.POINTER(i32), vp]
         L.dpps_ray_search.argtypes = [vp, i32, vp, vp, vp, C.POINTER(RayParams_C),
                                       C.POINTER(RayOutputs_C), vp]
+        L.dpps_shot_decision.argtypes = [vp, i32, vp, vp, vp, C.POINTER(ShotParams_C), vp, vp,
+                                         vp]
         L.dpps_search_power.argtypes = [vp, i32, vp, vp, vp, C.POINTER(PowerParams_C),
                                         C.POINTER(Outputs_C), vp, vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
@@ -273,6 +284,11 @@ class RayDeviceOutputs:
         return np.frombuffer(self.best.cpu().numpy().tobytes(), RAY_BEST_DT)
 
 
+def shots_host(t) -> np.ndarray:
+    """SHOT_DT records of a byte tensor written by Searcher.shot."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), SHOT_DT)
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -326,6 +342,46 @@ class Searcher:
         _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
                                  _ptr(pk.variants), C.byref(oc), best.ctypes.data))
         return out, best[0]
+
+    def pack_shots(self, frames, v_shot: float = 6.5, map: bool = True) -> "Packed":
+        """Pack frames for shot(): one flat variant at v_shot per frame, and
+        no windows without map."""
+        fr = []
+        for f in frames:
+            g = f.copy()
+            g.variants = [(DPPS_FLAT, float(v_shot))]
+            if not map:
+                g.windows = []
+            fr.append(g)
+        return pack(fr, self.params, self.out_flags)
+
+    def shot(self, frames, v_shot: float = 6.5, min_angle: float = 0.05, margin_s: float = 0.0,
+             map: bool = True, stream=None, out=None):
+        """Shooting decisions (Sec. 4.4) from each frame's ball and, with map,
+        from every point of the frames' windows; asynchronous on the stream.
+        `frames` are framegen frames or a Packed from pack_shots.  Returns
+        (ball, map) as byte tensors of SHOT_DT records (map None without map;
+        `out` may pass tensors to reuse); shots_host() converts them."""
+        import torch
+        pk = frames if isinstance(frames, Packed) else self.pack_shots(frames, v_shot, map)
+        n = len(pk.frames)
+        if out is not None:
+            ball, mp = out
+        else:
+            ball = torch.empty(max(n, 1) * SHOT_DT.itemsize, dtype=torch.uint8,
+                               device=self.device)
+            mp = None
+            if map:
+                mp = torch.empty(max(pk.total, 1) * SHOT_DT.itemsize, dtype=torch.uint8,
+                                 device=self.device)
+        if not map:
+            mp = None
+        sp = ShotParams_C(float(v_shot), float(min_angle), float(margin_s), 0)
+        _check(lib().dpps_shot_decision(self.h, n, _ptr(pk.frames), _ptr(pk.robots),
+                                        _ptr(pk.windows), C.byref(sp), ball.data_ptr(),
+                                        mp.data_ptr() if mp is not None else None,
+                                        _stream_ptr(stream)))
+        return ball, mp
 
     def search_power(self, frames, buffer_s: float = 0.3, v_min: float = 1.0,
                      v_max: float = 6.5, mask=True, score=True, times=True, stream=None):

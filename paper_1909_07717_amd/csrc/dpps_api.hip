@@ -469,6 +469,7 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
     c->scratch.ctx = c;
     c->fallback.ctx = c;
     c->rays.ctx = c;
+    c->shots.ctx = c;
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return fail(DPPS_E_DEVICE, "hipSetDevice(%d) failed", device);
@@ -514,6 +515,7 @@ void dpps_destroy(dpps_ctx *c)
     batch_free_device(&c->scratch);
     batch_free_device(&c->fallback);
     batch_free_device(&c->rays);
+    batch_free_device(&c->shots);
     if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staged) (void)hipEventDestroy(c->staged);
@@ -749,6 +751,62 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     const int64_t cap = (int64_t)c->n_cu * ray_occupancy(c->p.n_samples, c->waves);
     const int grid = (int)((int64_t)nt < cap ? (int64_t)nt : cap);
     if (launch_ray(a, c->waves, grid, (void *)st)) return fail(DPPS_E_DEVICE, "ray launch failed");
+    return DPPS_OK;
+}
+
+int dpps_shot_decision(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                       const dpps_robot *robots, const dpps_window *windows,
+                       const dpps_shot_params *sp, dpps_shot *d_ball, dpps_shot *d_map,
+                       void *hip_stream)
+{
+    if (!c || !sp || !d_ball) return fail(DPPS_E_INVALID, "NULL argument");
+    if (!(sp->v_shot > 0.0f) || !(sp->v_shot <= 100.0f) || !(sp->min_angle >= 0.0f) ||
+        !isfinite(sp->min_angle) || !(sp->margin_s >= 0.0f) || !isfinite(sp->margin_s) ||
+        sp->reserved != 0)
+        return fail(DPPS_E_INVALID,
+                    "shot: 0 < v_shot <= 100, finite min_angle >= 0 and margin_s >= 0, reserved 0");
+    if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (n_frames == 0) return DPPS_OK;
+    if (!frames) return fail(DPPS_E_INVALID, "NULL input array");
+    // one (unused) flat variant per frame; without a map the windows are skipped
+    std::vector<dpps_frame> fr(frames, frames + n_frames);
+    const dpps_variant one = {DPPS_FLAT, sp->v_shot};
+    for (dpps_frame &F : fr) {
+        F.n_variants = 1;
+        F.variant_off = 0;
+        if (!d_map) {
+            F.n_windows = 0;
+            F.window_off = 0;
+        }
+    }
+    const dpps_window no_window = {0.0f, 0, 0, 0, 0};
+    dpps_batch *b = &c->shots;
+    int rc = build_tables(&c->p, n_frames, fr.data(), robots, d_map ? windows : &no_window, &one,
+                          c->shot_tile, b->T);
+    if (rc) return rc;
+    b->n_frames = n_frames;
+    b->tile_points = c->shot_tile;
+    rc = stage_tables(c, b, st);
+    if (rc) return rc;
+    ShotArgs a;
+    memset(&a, 0, sizeof a);
+    a.P = c->P;
+    a.frames = b->d_frames;
+    a.robots = b->d_robots;
+    a.variants = b->d_variants;
+    a.wins = b->d_wins;
+    a.tiles = b->d_tiles;
+    a.n_tiles = (int32_t)b->T.tiles.size();
+    a.n_frames = n_frames;
+    a.tile_points = c->shot_tile;
+    a.v_shot = sp->v_shot;
+    a.min_angle = sp->min_angle;
+    a.margin = sp->margin_s;
+    a.ball = d_ball;
+    a.map = d_map;
+    if (launch_shot(a, c->shot_waves, (void *)st)) return fail(DPPS_E_DEVICE, "shot launch failed");
     return DPPS_OK;
 }
 

@@ -121,6 +121,22 @@ struct RayArgs {
     dpps_ray_best *best;
 };
 
+// Shooting decision (from each frame's ball, and from window points).
+struct ShotArgs {
+    DevParams P;
+    const FrameDev *frames;
+    const dpps_robot *robots;
+    const dpps_variant *variants;
+    const WinDev *wins;
+    const TileDev *tiles;
+    int32_t n_tiles;
+    int32_t n_frames;
+    int32_t tile_points;
+    float v_shot, min_angle, margin;
+    dpps_shot *ball;        // one record per frame
+    dpps_shot *map;         // one record per window point (may be NULL)
+};
+
 // host-side launchers (dpps_kernels.hip)
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the search kernel only.
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
@@ -130,5 +146,7 @@ int search_occupancy(int K, int waves_per_wg);
 // Direction x variant search (ray kernel then its finalize) on `stream`.
 int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream);
 int ray_occupancy(int K, int waves_per_wg);
+// Shooting decisions: the ball kernel, then (with a.map) the window kernel.
+int launch_shot(const ShotArgs &a, int waves_per_wg, void *stream);
 
 }  // namespace dpps

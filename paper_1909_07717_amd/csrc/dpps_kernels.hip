@@ -1094,6 +1094,189 @@ int ray_occupancy(int K, int waves_per_wg)
     return e == hipSuccess && n > 0 ? n : 1;
 }
 
+// ----------------------------------------------------------------------------
+// Shooting decision (Sec. 4.4): the widest open gap of the goal mouth, then
+// the opponents' interception along a flat shot through its centre.
+// ----------------------------------------------------------------------------
+
+// Ball time (float32) to distance s of a staged variant.
+__device__ __forceinline__ float ball_time32(const VarConst &c, float s)
+{
+    const bool ph1 = s <= (float)c.split;
+    const float va = ph1 ? (float)c.va1 : (float)c.va2;
+    const float ac = ph1 ? (float)c.a1 : (float)c.a2;
+    const float x = s - (ph1 ? 0.0f : (float)c.soff2);
+    const float to = ph1 ? 0.0f : (float)c.toff2;
+    const float q = fmaxf(fmaf(-2.0f * ac, x, va * va), 0.0f);
+    return fmaf(2.0f * x, hrcp(va + hsqrt(q)), to);
+}
+
+__device__ __forceinline__ float wave_min_f(float x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Open gaps of the goal mouth seen from (cx, cy); lanes are opponents, lane 62
+// the lower post.  A gap starts at the lower post or at the end of a shadow
+// that no other shadow covers, and runs to the next shadow start (or the
+// upper post).  Returns the widest gap and its start (ties to the lower
+// start) and the sum of the gaps; the same values on every lane.
+__device__ __forceinline__ void shot_gaps(const StageLDS &S, const DevParams &P, float cx,
+                                          float cy, int n_op, int n_tm, float &gap, float &g0,
+                                          float &open)
+{
+    const int l = lane_id();
+    const float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
+    const float4 o = S.rob[n_tm + (l < n_op ? l : 0)];
+    const float ox = o.x - cx, oy = o.y - cy;
+    const float Y = l < n_op ? oy : (l == 62 ? -P.half_goal_w - cy : P.half_goal_w - cy);
+    const float X = l < n_op ? ox : dxg;
+    const float ang = atan2f(Y, X);
+    const float lo = readlane_f(ang, 62);
+    const float hi = readlane_f(ang, 63);
+    const bool valid = l < n_op && o.x < P.goal_x;
+    const float rho2 = fmaf(ox, ox, oy * oy);
+    gap = 0.0f;
+    g0 = lo;
+    open = 0.0f;
+    if (__ballot(valid && rho2 <= P.R * P.R)) return;
+    const float al = asinf(fminf(P.R * rsq(fmaxf(rho2, 1e-30f)), 1.0f));
+    const float s = fmaxf(ang - al, lo);
+    const float e = fminf(ang + al, hi);
+    const bool has = valid && e > s;
+    const unsigned long long hm = __ballot(has);
+    const bool cand = has || l == 62;
+    const float st = l == 62 ? lo : e;
+    bool cov = false;
+    float nxt = hi;
+    for (unsigned long long m = hm; m; m &= m - 1) {
+        const int k = __builtin_ctzll(m);
+        const float sk = readlane_f(s, k);
+        const float ek = readlane_f(e, k);
+        cov = cov || (sk <= st && ek > st);
+        nxt = sk > st ? fminf(nxt, sk) : nxt;
+    }
+    const float w = cand && !cov ? fmaxf(nxt - st, 0.0f) : 0.0f;
+    const unsigned long long cm = __ballot(cand);
+    for (unsigned long long m = cm; m; m &= m - 1) {
+        const int k = __builtin_ctzll(m);
+        const float wk = readlane_f(w, k);
+        const float sk = readlane_f(st, k);
+        open += wk;
+        if (wk > gap || (wk == gap && wk > 0.0f && sk < g0)) {
+            gap = wk;
+            g0 = sk;
+        }
+    }
+}
+
+// The decision from shooter position (cx, cy) of the staged frame; lane 0's
+// record is the result.
+template <int KPL>
+__device__ dpps_shot shot_origin(const StageLDS &S, const DevParams &P, float4 *pr, double cx,
+                                 double cy, const VarConst &vc, float min_angle, float margin)
+{
+    const int l = lane_id();
+    const int K = KPL * 64;
+    const int n_tm = uni(S.n_tm), n_op = uni(S.n_op);
+    const float fx = (float)cx, fy = (float)cy;
+    float gap, g0, open;
+    shot_gaps(S, P, fx, fy, n_op, n_tm, gap, g0, open);
+    const double dxg = fmax((double)P.goal_x - cx, (double)P.goal_eps);
+    const float aim = gap > 0.0f ? fmaf(0.5f, gap, g0) : atan2f(-fy, (float)dxg);
+    const double ux = (double)cosf(aim), uy = (double)sinf(aim);
+    const double L = dxg / ux;
+    path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, cx, cy);
+    const float Lf = (float)L, LA = (float)(L * (double)P.A);
+    float fs[KPL], T[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        fs[q] = (float)(q * 64 + l + 1) * (1.0f / (float)K);
+        T[q] = INFINITY;
+    }
+    robot_stage<KPL, true>(pr, P, n_tm, n_op, fs, LA, T);
+    const float D = (float)vc.D;
+    float m = INFINITY;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+        const float sk = fs[q] * Lf;
+        const float d = T[q] * P.invA2 - ball_time32(vc, sk);
+        m = sk <= D ? fminf(m, d) : m;
+    }
+    m = wave_min_f(m);
+    dpps_shot r;
+    r.reachable = L <= vc.D;
+    r.aim = aim;
+    r.gap = gap;
+    r.open_angle = open;
+    r.length = Lf;
+    r.t_goal = r.reachable ? (float)ball_time64(vc, L) : INFINITY;
+    r.slack = m;
+    r.shoot = gap >= min_angle && r.reachable && m > margin;
+    return r;
+}
+
+// BALL: one single-wave workgroup per frame, from the frame's ball.  MAP:
+// one workgroup per tile of window points, each wave one point at a time.
+template <int KPL, bool MAP>
+__global__ void __launch_bounds__(512) shot_kernel(ShotArgs a)
+{
+    __shared__ StageLDS S;
+    __shared__ float4 PR[MAX_WAVES][MAX_ROB];
+    const DevParams &P = a.P;
+    const int w = threadIdx.x >> 6;
+    const int l = lane_id();
+    const int t = blockIdx.x;
+    const TileDev tile = MAP ? a.tiles[t] : TileDev{0, 0};
+    const WinDev W = MAP ? a.wins[tile.win] : WinDev{};
+    const int f = MAP ? W.frame : t;
+    stage_frame(P, a.frames, a.robots, a.variants, f, S);
+    __syncthreads();
+    const VarConst vc = var_const(P, DPPS_FLAT, a.v_shot);
+    if (!MAP) {
+        const dpps_shot r = shot_origin<KPL>(S, P, PR[0], (double)S.bx, (double)S.by, vc,
+                                             a.min_angle, a.margin);
+        if (l == 0) a.ball[f] = r;
+        return;
+    }
+    const int np = min(a.tile_points, W.npts - tile.p0);
+    const int nw = blockDim.x >> 6;
+    for (int slot = w; slot < np; slot += nw) {
+        const int p = tile.p0 + slot;
+        const int j = p / W.nx, i = p - j * W.nx;
+        const double cx = (double)W.h * ((double)(W.i0 + i) - (double)W.halfNx);
+        const double cy = (double)W.h * ((double)(W.j0 + j) - (double)W.halfNy);
+        const dpps_shot r = shot_origin<KPL>(S, P, PR[w], cx, cy, vc, a.min_angle, a.margin);
+        if (l == 0) a.map[W.out_base + p] = r;
+    }
+}
+
+template <int KPL>
+static int launch_shot_kpl(const ShotArgs &a, int waves_per_wg, hipStream_t st)
+{
+    if (a.n_frames > 0)
+        hipLaunchKernelGGL((shot_kernel<KPL, false>), dim3(a.n_frames), dim3(64), 0, st, a);
+    if (a.map && a.n_tiles > 0)
+        hipLaunchKernelGGL((shot_kernel<KPL, true>), dim3(a.n_tiles), dim3(64 * waves_per_wg), 0,
+                           st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_shot(const ShotArgs &a, int waves_per_wg, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (waves_per_wg < 1 || waves_per_wg > MAX_WAVES) return -2;
+    switch (a.P.K / 64) {
+    case 1: return launch_shot_kpl<1>(a, waves_per_wg, st);
+    case 2: return launch_shot_kpl<2>(a, waves_per_wg, st);
+    case 3: return launch_shot_kpl<3>(a, waves_per_wg, st);
+    case 4: return launch_shot_kpl<4>(a, waves_per_wg, st);
+    default: return -2;
+    }
+}
+
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                   void *ev_stop)
 {

@@ -86,6 +86,9 @@ struct dpps_ctx {
     dpps_batch rays;         // tables of dpps_ray_search
     DeviceArena ray_aux;     // its work counter and per-tile records
     int ray_tile_dirs = 4;   // directions per tile of dpps_ray_search
+    dpps_batch shots;        // tables of dpps_shot_decision
+    int shot_tile = 16;      // window points per workgroup of the shot map
+    int shot_waves = 4;      // waves per workgroup of the shot map
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;   // pinned staging consumed

@@ -92,3 +92,20 @@ def ray_frame_work(frame, K: int, n_dirs: int, n_feasible: int) -> tuple[int, in
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # published; assumes packed FP32 FMA every cycle
 PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+
+
+# The shooting decision (Sec. 4.4), per shooter position: the widest-gap
+# geometry (the open goal angle's terms plus C_SHOT_GAP per opponent for the
+# gap scan), the aim, the shot's path frame and the ball time to the goal line
+# (C_SHOT_SET), per sample its position, the float32 ball time and the slack
+# (C_SHOT_SAMPLE), and the opponents' robot stage (C_ROBOT per opponent and
+# sample).
+C_SHOT_SET = 120
+C_SHOT_GAP = 8
+C_SHOT_SAMPLE = 26
+
+
+def shot_flops(n_opp: int, K: int) -> int:
+    """Flops of one shooting decision against n_opp opponents, K samples."""
+    return (n_opp * K * C_ROBOT + K * C_SHOT_SAMPLE + C_SHOT_SET + C_ANGLE
+            + (C_ANGLE_OPP + C_SHOT_GAP) * n_opp)

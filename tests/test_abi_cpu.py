@@ -51,6 +51,9 @@ int main(void) {
   S(dpps_ray_params); S(dpps_ray_best); S(dpps_ray_outputs);
   O(dpps_ray_params, w_refract); O(dpps_ray_best, theta); O(dpps_ray_best, score);
   O(dpps_ray_best, refract); O(dpps_ray_outputs, s_recv); O(dpps_ray_outputs, best);
+  S(dpps_power_params); O(dpps_power_params, v_max);
+  S(dpps_shot_params); S(dpps_shot); O(dpps_shot_params, margin_s); O(dpps_shot, aim);
+  O(dpps_shot, t_goal); O(dpps_shot, slack);
   return 0;
 }
 """
@@ -86,6 +89,13 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[f"dpps_ray_best.{f}"] == B.RAY_BEST_DT.fields[f][1]
     assert got["dpps_ray_outputs.s_recv"] == B.RayOutputs_C.s_recv.offset
     assert got["dpps_ray_outputs.best"] == B.RayOutputs_C.best.offset
+    assert got["dpps_power_params"] == C.sizeof(B.PowerParams_C)
+    assert got["dpps_power_params.v_max"] == B.PowerParams_C.v_max.offset
+    assert got["dpps_shot_params"] == C.sizeof(B.ShotParams_C)
+    assert got["dpps_shot_params.margin_s"] == B.ShotParams_C.margin_s.offset
+    assert got["dpps_shot"] == B.SHOT_DT.itemsize
+    for f in ("aim", "t_goal", "slack"):
+        assert got[f"dpps_shot.{f}"] == B.SHOT_DT.fields[f][1]
 
 
 def test_layout_is_host_only_and_dense():

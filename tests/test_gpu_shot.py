@@ -1,0 +1,180 @@
+"""GPU parity of the shooting decision (Sec. 4.4) against the FP64 oracle:
+dpps_shot_decision through the C ABI, from each frame's ball and from every
+point of the frames' windows.
+
+Outside the oracle's ambiguity bands (the gap-width decision, a near tie
+between the two widest gaps, the reach edge, and a slack within the crossing
+band plus its sensitivity to the aim): identical decisions and reach flags;
+the widest gap and the total open angle within 2e-5 rad, the aim within
+2e-5 rad; where they are well conditioned in the aim (moving the aim by
+2e-6 rad moves the length by less than 1e-4 m, the slack by less than
+5e-5 s), the path length within 2e-4 m, the ball time to the goal line within
+1e-4 s and the slack within 1e-4 s.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1909_07717_amd.framegen import Params, config_small, full_window, random_frame
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+V_SHOT, MIN_ANGLE, MARGIN = 6.5, 0.05, 0.0
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_07717_amd import binding
+    return binding
+
+
+def _close(a, b, tol):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    ia, ib = np.isinf(a), np.isinf(b)
+    if not (ia == ib).all():
+        return False
+    return bool((np.abs(a[~ia] - b[~ib]) <= tol).all())
+
+
+def _compare(g, o, max_amb=3e-2):
+    """g: SHOT_DT records; o: oracle dict of arrays (same order)."""
+    amb = o["ambig"]
+    assert (amb != 0).mean() <= max_amb, (amb != 0).mean()
+    ang_ok = (amb & O.AMB_ANGLE) == 0
+    reach_ok = (amb & O.AMB_REACH) == 0
+    ok = amb == 0
+    assert (g["shoot"][ok] == o["shoot"][ok]).all()
+    assert (g["reachable"][reach_ok & ang_ok] == o["reachable"][reach_ok & ang_ok]).all()
+    assert _close(g["gap"][ang_ok], o["gap"][ang_ok], 2e-5)
+    assert _close(g["open_angle"][ang_ok], o["open_angle"][ang_ok], 2e-5)
+    assert _close(g["aim"][ang_ok], o["aim"][ang_ok], 2e-5)
+    # where the length is ill-conditioned in the aim (a shooter on the goal
+    # line aims almost along it) only the decision is compared
+    cond = ang_ok & (o["length_sens"] < 1e-4)
+    assert _close(g["length"][cond], o["length"][cond], 2e-4)
+    both = cond & reach_ok
+    assert _close(g["t_goal"][both], o["t_goal"][both], 1e-4)
+    well = ang_ok & (o["slack_sens"] < 5e-5)
+    assert _close(g["slack"][well], o["slack"][well], 1e-4)
+
+
+def _stack(rs):
+    return {k: np.array([r[k] for r in rs]) for k in O.SHOT_FIELDS}
+
+
+def test_shot_from_the_ball_many_frames(B):
+    p = Params(n_samples=128).as_f32()
+    s = B.Searcher(p)
+    rng = np.random.default_rng(77)
+    frames = [random_frame(rng, int(rng.integers(1, 9)), int(rng.integers(0, 9)), Params())
+              for _ in range(400)]
+    # shooters in the attacking half, where shots are decided
+    for f in frames:
+        f.team[f.passer, 0] = abs(f.team[f.passer, 0])
+        f.ball = f.team[f.passer, :2].copy()
+    ball, mp = s.shot(frames, V_SHOT, MIN_ANGLE, MARGIN, map=False)
+    torch.cuda.synchronize()
+    assert mp is None
+    g = B.shots_host(ball)[:len(frames)]
+    o = _stack([O.shot(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)
+                for f in frames])
+    _compare(g, o)
+    assert 0 < g["shoot"].sum() < len(frames)
+    s.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_shot_map_full_field(B, seed):
+    p = Params(n_samples=64).as_f32()
+    s = B.Searcher(p)
+    f = config_small(seed)
+    f.windows = [full_window(0.2)]
+    ball, mp = s.shot([f], V_SHOT, MIN_ANGLE, MARGIN)
+    torch.cuda.synchronize()
+    g = B.shots_host(mp)[:2806]
+    o = O.shot_search(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)
+    _compare(g, o)
+    gb = B.shots_host(ball)[:1]
+    ob = _stack([O.shot(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)])
+    _compare(gb, ob, max_amb=1.0)
+    assert 0 < g["shoot"].sum() < 2806
+    s.close()
+
+
+def test_shot_map_batch_of_5cm_windows_equals_single_frames(B):
+    # 8v8, several 5 cm windows, K = 256: ragged tiles, frames of one batch
+    p = Params(n_samples=256).as_f32()
+    s = B.Searcher(p)
+    frames = []
+    for i in range(3):
+        f = random_frame(np.random.default_rng(900 + i), 8, 8, Params())
+        f.windows = [(np.float32(0.05), 150 + 15 * i, 50 + 10 * i, 53, 37),
+                     (np.float32(0.05), 200, 80, 17, 9)]
+        frames.append(f)
+    ball, mp = s.shot(frames, V_SHOT, 0.02, 0.05)
+    torch.cuda.synchronize()
+    allm = B.shots_host(mp)
+    off = 0
+    for f in frames:
+        n = 53 * 37 + 17 * 9
+        g = allm[off:off + n]
+        o = O.shot_search(f, p, v_shot=V_SHOT, min_angle=0.02, margin_s=0.05, bands=True)
+        _compare(g, o)
+        b1, m1 = s.shot([f], V_SHOT, 0.02, 0.05)
+        torch.cuda.synchronize()
+        assert B.shots_host(m1)[:n].tobytes() == g.tobytes()
+        off += n
+    s.close()
+
+
+def test_shot_edge_cases_and_invalid_arguments(B):
+    p = Params(n_samples=64).as_f32()
+    s = B.Searcher(p)
+    base = config_small(5)
+    # no opponents: the whole mouth is open, nothing intercepts
+    alone = base.copy()
+    alone.opp = np.zeros((0, 4), np.float32)
+    # the shooter inside an opponent's radius: no open direction
+    inside = base.copy()
+    inside.opp[0, :2] = inside.ball + np.float32(0.05)
+    # an opponent behind the goal line casts no shadow
+    keeper = base.copy()
+    keeper.opp[0] = (6.05, 0.0, 0.0, 0.0)
+    # a lone passer, and a shooter on the goal line
+    lone = base.copy()
+    lone.team = base.team[base.passer:base.passer + 1].copy()
+    lone.passer = 0
+    line = base.copy()
+    line.team[line.passer, :2] = (6.0, 0.3)
+    line.ball = line.team[line.passer, :2].copy()
+    frames = [alone, inside, keeper, lone, line]
+    ball, _ = s.shot(frames, V_SHOT, MIN_ANGLE, MARGIN, map=False)
+    torch.cuda.synchronize()
+    g = B.shots_host(ball)[:len(frames)]
+    o = _stack([O.shot(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)
+                for f in frames])
+    _compare(g, o, max_amb=1.0)
+    assert np.isinf(g["slack"][0]) and g["gap"][1] == 0 and g["shoot"][1] == 0
+    for args in ((0.0, MIN_ANGLE, MARGIN), (V_SHOT, -0.1, MARGIN), (V_SHOT, float("nan"), MARGIN),
+                 (V_SHOT, MIN_ANGLE, -1.0), (float("inf"), MIN_ANGLE, MARGIN)):
+        with pytest.raises(B.DppsError):
+            s.shot([base], *args)
+    # no frames: nothing to do
+    s.shot([], V_SHOT, MIN_ANGLE, MARGIN)
+    s.close()
+
+
+def test_shot_is_deterministic(B):
+    p = Params(n_samples=128).as_f32()
+    s = B.Searcher(p)
+    f = config_small(11)
+    f.windows = [full_window(0.2)]
+    a = s.shot([f])
+    b = s.shot([f])
+    torch.cuda.synchronize()
+    assert a[0].cpu().numpy().tobytes() == b[0].cpu().numpy().tobytes()
+    assert a[1].cpu().numpy().tobytes() == b[1].cpu().numpy().tobytes()
+    s.close()
