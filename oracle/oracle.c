@@ -1,6 +1,6 @@
 /*
  * oracle.c -- plain, slow FP64 reference of the SBIP-DPPS passing-point search
- * (arXiv 1909.07717, Sec. 4.1-4.4).
+ * (arXiv 1909.07717, Sec. 4.1-4.4) and the running-point criteria of Sec. 5.2.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
  * or calls this file; only the test suite, the smoke check and the CPU
@@ -967,4 +967,142 @@ int64_t orc_shot_search(const orc_params *P, const orc_shot_params *S, const orc
     return base;
 }
 
-int orc_abi_version(void) { return 4; }
+/* ------------------------------------------------------------------------ */
+/* Running points (Sec. 5.2): every vertex of a zone raster is scored by the */
+/* weighted sum of Eq. (4) over five criteria, each mapped to [0, 1] with    */
+/* higher better.  Readings (the paper names the criteria but gives no       */
+/* formulas, constants or weights; every constant is a parameter):           */
+/*  x1 distance to the goal: 1 - |c - goal centre| / dist_norm;              */
+/*  x2 distance to the ball: min(|c - ball| / ball_norm, 1) (too close to    */
+/*     the ball is bad);                                                     */
+/*  x3 angle to the goal: phi = |bearing of the goal centre from c| (0 when  */
+/*     it lies straight along +x); 1 inside [ang_lo, ang_hi], falling        */
+/*     linearly to 0 over ang_fall outside it;                               */
+/*  x4 guard time: the segments from c to the two goal posts first meet the  */
+/*     defense area (the rectangle of def_depth x def_width in front of the  */
+/*     goal) at P and Q; each is reached first by some opponent after t_P,   */
+/*     t_Q (the robot arrival model of the pass search); x4 = min((t_P +     */
+/*     t_Q) / guard_norm, 1);                                                */
+/*  x5 avoiding the defense: an opponent o nearer to the ball than c is      */
+/*     (|o - ball| < |c - ball|, decided in FP64) marks c with weight        */
+/*     max(0, 1 - |o - c| / mark_radius); x5 = 1 - the largest such weight;  */
+/*  points strictly inside the defense area cannot be used (score -inf);     */
+/*  the best point of a zone has the largest score, ties to the lowest       */
+/*  row-major index.                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double w_goal, w_ball, w_angle, w_guard, w_defense;
+    double ball_norm, ang_lo, ang_hi, ang_fall, guard_norm, def_depth, def_width, mark_radius;
+} orc_run_params;
+
+typedef struct {
+    int32_t valid, ambig;
+    double score, goal, ball, angle, guard, defense, px, py, qx, qy, t_p, t_q;
+} orc_run_result;
+
+#define ORC_AMB_RUN 32 /* an opponent within 1e-9 m of the ball-distance tie */
+
+/* First point of the segment from (cx, cy) to (ex, ey) inside the closed
+ * rectangle [x0, x1] x [y0, y1], by intersecting the segment with each edge
+ * line and keeping the nearest crossing that lies on the edge (the end point
+ * is inside by construction). */
+static void seg_enter_rect(double cx, double cy, double ex, double ey, double x0, double x1,
+                           double y0, double y1, double *px, double *py)
+{
+    double best = 1.0;
+    double dx = ex - cx, dy = ey - cy;
+    const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+    for (int i = 0; i < 2; ++i) {
+        if (dx != 0.0) {
+            double t = (xs[i] - cx) / dx;
+            double y = cy + t * dy;
+            if (t >= 0.0 && t <= best && y >= y0 && y <= y1) best = t;
+        }
+        if (dy != 0.0) {
+            double t = (ys[i] - cy) / dy;
+            double x = cx + t * dx;
+            if (t >= 0.0 && t <= best && x >= x0 && x <= x1) best = t;
+        }
+    }
+    *px = cx + best * dx;
+    *py = cy + best * dy;
+}
+
+void orc_run(const orc_params *P, const orc_run_params *R, const orc_world *W, double cx,
+             double cy, orc_run_result *out)
+{
+    memset(out, 0, sizeof *out);
+    double x0 = P->goal_x - R->def_depth, x1 = P->goal_x;
+    double y0 = -0.5 * R->def_width, y1 = 0.5 * R->def_width;
+    if (cx > x0 && cx < x1 && cy > y0 && cy < y1) {
+        out->score = -INFINITY;
+        return;
+    }
+    out->valid = 1;
+    double gx = P->goal_x - cx, gy = -cy;
+    out->goal = 1.0 - sqrt(gx * gx + gy * gy) / P->dist_norm;
+    double bx = cx - W->ball_x, by = cy - W->ball_y;
+    double db2 = bx * bx + by * by;
+    out->ball = fmin(sqrt(db2) / R->ball_norm, 1.0);
+    double phi = fabs(atan2(gy, gx));
+    double off = phi < R->ang_lo ? R->ang_lo - phi : (phi > R->ang_hi ? phi - R->ang_hi : 0.0);
+    out->angle = fmax(0.0, 1.0 - off / R->ang_fall);
+    double hw = 0.5 * P->goal_width;
+    seg_enter_rect(cx, cy, P->goal_x, hw, x0, x1, y0, y1, &out->px, &out->py);
+    seg_enter_rect(cx, cy, P->goal_x, -hw, x0, x1, y0, y1, &out->qx, &out->qy);
+    double tp = INFINITY, tq = INFINITY;
+    double mark = 0.0;
+    int amb = 0;
+    for (int o = 0; o < W->n_opp; ++o) {
+        const double *r = W->opp + 4 * o;
+        double a = robot_time_to(P, r, out->px, out->py);
+        double b = robot_time_to(P, r, out->qx, out->qy);
+        if (a < tp) tp = a;
+        if (b < tq) tq = b;
+        double ox = r[0] - W->ball_x, oy = r[1] - W->ball_y;
+        double do2 = ox * ox + oy * oy;
+        double dc = hypot(r[0] - cx, r[1] - cy);
+        double wgt = fmax(0.0, 1.0 - dc / R->mark_radius);
+        if (do2 < db2 && wgt > mark) mark = wgt;
+        if (fabs(do2 - db2) < 1e-9 && wgt > 0.0) amb |= ORC_AMB_RUN;
+    }
+    out->t_p = tp;
+    out->t_q = tq;
+    out->guard = isfinite(tp + tq) ? fmin((tp + tq) / R->guard_norm, 1.0) : 1.0;
+    out->defense = 1.0 - mark;
+    out->ambig = amb;
+    out->score = R->w_goal * out->goal + R->w_ball * out->ball + R->w_angle * out->angle
+               + R->w_guard * out->guard + R->w_defense * out->defense;
+}
+
+/* Every point of the windows (the zones); res in window-major, row-major
+ * order; best[w] = index within window w of its best point, or -1. */
+int64_t orc_run_search(const orc_params *P, const orc_run_params *R, const orc_world *W,
+                       int n_win, const double *win_h, const int32_t *win_int,
+                       orc_run_result *res, int64_t *best)
+{
+    int64_t base = 0;
+    for (int w = 0; w < n_win; ++w) {
+        double h = win_h[w];
+        int i0 = win_int[4 * w], j0 = win_int[4 * w + 1];
+        int nx = win_int[4 * w + 2], ny = win_int[4 * w + 3];
+        int64_t npts = (int64_t)nx * ny;
+        int64_t bi = -1;
+        double bs = -INFINITY;
+        for (int64_t p = 0; p < npts; ++p) {
+            int i = (int)(p % nx), j = (int)(p / nx);
+            double cx, cy;
+            orc_point(P, h, i0 + i, j0 + j, &cx, &cy);
+            orc_run(P, R, W, cx, cy, res + base + p);
+            if (res[base + p].valid && res[base + p].score > bs) {
+                bs = res[base + p].score;
+                bi = p;
+            }
+        }
+        best[w] = bi;
+        base += npts;
+    }
+    return base;
+}
+
+int orc_abi_version(void) { return 5; }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN, AMB_ANGLE = 1, 2, 4, 8, 16
+AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN, AMB_ANGLE, AMB_RUN = 1, 2, 4, 8, 16, 32
 
 
 def build(force: bool = True) -> str:
@@ -76,6 +76,18 @@ class OrcShotResult(C.Structure):
                     "second_gap", "length_sens")]
 
 
+class OrcRunParams(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "w_goal", "w_ball", "w_angle", "w_guard", "w_defense", "ball_norm", "ang_lo", "ang_hi",
+        "ang_fall", "guard_norm", "def_depth", "def_width", "mark_radius")]
+
+
+class OrcRunResult(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("ambig", C.c_int32)] + [(n, C.c_double) for n in (
+        "score", "goal", "ball", "angle", "guard", "defense", "px", "py", "qx", "qy", "t_p",
+        "t_q")]
+
+
 # Parity bands (widths of the ambiguity regions computed by the oracle).
 DEFAULT_BANDS = dict(eps_reach=1e-4, eps_land=1e-5, eps_cross_t=1e-5, eps_cross_s=1e-5,
                      eps_margin=1e-3)
@@ -131,6 +143,10 @@ def lib():
         L.orc_shot.argtypes = [P, SP, Wp, d, d, C.c_int, SR]
         L.orc_shot_search.argtypes = [P, SP, Wp, C.c_int, pd, pi32, C.c_int, SR]
         L.orc_shot_search.restype = i64
+        RPp, RR = C.POINTER(OrcRunParams), C.POINTER(OrcRunResult)
+        L.orc_run.argtypes = [P, RPp, Wp, d, d, RR]
+        L.orc_run_search.argtypes = [P, RPp, Wp, C.c_int, pd, pi32, RR, C.POINTER(i64)]
+        L.orc_run_search.restype = i64
         _lib = L
     return _lib
 
@@ -420,3 +436,53 @@ def shot_search(frame, params, v_shot=6.5, min_angle=0.05, margin_s=0.0, bands=F
                       _ptr(win_i, C.c_int32), int(bands), res)
     a = np.ctypeslib.as_array(res)[:n]
     return {k: np.array(a[k]) for k in SHOT_FIELDS}
+
+
+# ---------------------------------------------------------------------------
+# running points (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+RUN_FIELDS = [k for k, _ in OrcRunResult._fields_]
+RUN_DEFAULTS = dict(w_goal=0.3, w_ball=0.1, w_angle=0.15, w_guard=0.25, w_defense=0.2,
+                    ball_norm=2.0, ang_lo=0.2617993877991494, ang_hi=0.7853981633974483,
+                    ang_fall=0.5235987755982988, guard_norm=2.0, def_depth=1.2, def_width=2.4,
+                    mark_radius=1.0)
+
+
+def _run_params(**kw):
+    r = OrcRunParams()
+    v = dict(RUN_DEFAULTS)
+    v.update(kw)
+    for k, x in v.items():
+        setattr(r, k, float(x))
+    return r
+
+
+def run_point(frame, params, cx, cy, **run):
+    """The five criteria and the score at (cx, cy)."""
+    r = OrcRunResult()
+    wh = _WorldHolder(frame)
+    lib().orc_run(C.byref(make_params(params)), C.byref(_run_params(**run)), C.byref(wh.w),
+                  float(cx), float(cy), C.byref(r))
+    return {k: getattr(r, k) for k in RUN_FIELDS}
+
+
+def run_search(frame, params, n_threads: int = 0, **run):
+    """Every point of the frame's windows (the zones): a dict of flat arrays
+    in window-major, row-major order, plus ``best`` (per window, the index
+    within the window, or -1)."""
+    L = lib()
+    P = make_params(params, n_threads)
+    wh = _WorldHolder(frame)
+    win_h = np.array([w[0] for w in frame.windows], dtype=np.float64)
+    win_i = np.array([[w[1], w[2], w[3], w[4]] for w in frame.windows], dtype=np.int32).reshape(-1)
+    n = int(sum(w[3] * w[4] for w in frame.windows))
+    res = (OrcRunResult * max(n, 1))()
+    best = np.zeros(max(len(win_h), 1), np.int64)
+    L.orc_run_search(C.byref(P), C.byref(_run_params(**run)), C.byref(wh.w), len(win_h),
+                     _ptr(win_h, C.c_double), _ptr(win_i, C.c_int32), res,
+                     best.ctypes.data_as(C.POINTER(C.c_int64)))
+    a = np.ctypeslib.as_array(res)[:n]
+    out = {k: np.array(a[k]) for k in RUN_FIELDS}
+    out["best"] = best[:len(win_h)]
+    return out
