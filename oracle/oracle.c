@@ -1009,6 +1009,11 @@ typedef struct {
 static void seg_enter_rect(double cx, double cy, double ex, double ey, double x0, double x1,
                            double y0, double y1, double *px, double *py)
 {
+    if (cx >= x0 && cx <= x1 && cy >= y0 && cy <= y1) {  /* already on or in it */
+        *px = cx;
+        *py = cy;
+        return;
+    }
     double best = 1.0;
     double dx = ex - cx, dy = ey - cy;
     const double xs[2] = {x0, x1}, ys[2] = {y0, y1};

@@ -39,7 +39,10 @@ def _rest_to_rest(p, dist):
 @pytest.mark.parametrize("c,P,Q", [((2.0, 0.0), (4.8, 0.42), (4.8, -0.42)),
                                    ((4.5, 3.0), (5.625, 1.2), (5.25, 1.2)),
                                    ((5.5, -2.0), (5.5 + 0.5 * 0.8 / 2.6, -1.2),
-                                    (5.5 + 0.5 * 0.8 / 1.4, -1.2))])
+                                    (5.5 + 0.5 * 0.8 / 1.4, -1.2)),
+                                   # on the area's boundary: the point itself
+                                   ((6.0, 0.25), (6.0, 0.25), (6.0, 0.25)),
+                                   ((4.8, -0.5), (4.8, -0.5), (4.8, -0.5))])
 def test_p_and_q_closed_forms(c, P, Q):
     p = Params()
     r = O.run_point(_frame((0.0, 0.0), np.zeros((0, 4))), p, *c)
