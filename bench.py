@@ -232,6 +232,67 @@ def shot_bench(n_frames: int, steps: int, lat_frames: int, st):
     return res
 
 
+def run_bench(n_frames: int, steps: int, lat_frames: int, st):
+    """Running points (Sec. 5.2): n_frames 8v8 frames, each with the four
+    front-field zones at 0.1 m that follow its ball, per call (frames packed
+    once, staged from the host on every call); latency of one frame's four
+    zone bests, host inputs to the records on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1909_07717_amd import binding as Bn
+    from paper_1909_07717_amd import flops as FL
+    from paper_1909_07717_amd.framegen import Params, random_frame
+
+    p = Params(n_samples=64).as_f32()
+    s = Bn.Searcher(p, device=0)
+    frames = []
+    for i in range(n_frames):
+        f = random_frame(np.random.default_rng(800 + i), 8, 8, Params())
+        f.windows = Bn.front_zones(f.ball, p)
+        f.variants = [(Bn.DPPS_FLAT, 1.0)]
+        frames.append(f)
+    pk = Bn.pack(frames, p)
+    pts = int(pk.total)
+    with torch.cuda.stream(st):
+        best, sc = s.running_points(pk, stream=st)
+    torch.cuda.synchronize()
+    found = float(Bn.run_best_host(best)["found"][:4 * n_frames].mean())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        e0.record(st)
+        for _ in range(steps):
+            s.running_points(pk, stream=st, out=(best, sc))
+        e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lat = []
+    b1 = torch.empty(4 * Bn.RUN_BEST_DT.itemsize, dtype=torch.uint8, device=best.device)
+    s1 = torch.empty(8192, dtype=torch.float32, device=best.device)
+    host = torch.empty(4 * Bn.RUN_BEST_DT.itemsize, dtype=torch.uint8, pin_memory=True)
+    for i in range(100 + lat_frames):
+        a = time.perf_counter()
+        with torch.cuda.stream(st):
+            s.running_points([frames[i % n_frames]], score=False, stream=st, out=(b1, s1))
+            host.copy_(b1, non_blocking=True)
+        st.synchronize()
+        if i >= 100:
+            lat.append(time.perf_counter() - a)
+    lat = np.array(lat) * 1e3
+    s.close()
+    fl = pts * FL.run_flops(8)
+    return {"workload": f"{n_frames} frames of 8v8, four front-field zones at 0.1 m each "
+                        f"({pts // n_frames} points per frame)",
+            "ms_per_call": round(ms, 4), "points_per_s": round(pts / (ms * 1e-3), 1),
+            "zones_per_s": round(4 * n_frames / (ms * 1e-3), 1),
+            "tflops": round(fl / (ms * 1e-3) / 1e12, 3), "found_fraction": round(found, 4),
+            "score_map_bytes": 4 * pts,
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                           "p99": round(float(np.percentile(lat, 99)), 4),
+                           "frames": int(lat.size),
+                           "path": "one frame per call, host inputs to the zone bests on the host"}}
+
+
 def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
     """The paper's own DPPS form: 8v8 frames, 128 kick directions x 64 flat
     powers in [1, 6.5] m/s, K = 256 samples per ray.  Batched: n_frames frames
@@ -431,6 +492,8 @@ def main() -> int:
     power = power_bench(20, st) if args.ray_frames > 0 else None
     shots = (shot_bench(4096, 20, min(args.latency_frames, 2000), st)
              if args.ray_frames > 0 else None)
+    running = (run_bench(4096, 20, min(args.latency_frames, 2000), st)
+               if args.ray_frames > 0 else None)
     sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
            if args.surrogate_frames > 0 else None)
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
@@ -466,6 +529,7 @@ def main() -> int:
         "rays": rays,
         "power": power,
         "shots": shots,
+        "running": running,
         "surrogate": sur,
         "serving": serving,
     }

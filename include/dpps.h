@@ -423,6 +423,55 @@ int dpps_shot_decision(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
                        const dpps_shot_params *sp, dpps_shot *d_ball, dpps_shot *d_map,
                        void *hip_stream);
 
+/* ---- running points (Sec. 5.2) --------------------------------------------
+ * Every vertex of each zone raster (the frames' windows, e.g. four front-field
+ * zones at 0.1 m that move with the ball, Sec. 5.1) gets the weighted sum of
+ * Eq. (4) over five criteria, each in [0, 1], higher better:
+ *   x1 distance to the goal: 1 - |c - goal centre| / dist_norm;
+ *   x2 distance to the ball: min(|c - ball| / ball_norm, 1);
+ *   x3 angle to the goal: with phi = |bearing of the goal centre from c| (0
+ *      straight along +x), 1 inside [ang_lo, ang_hi], falling linearly to 0
+ *      over ang_fall outside it;
+ *   x4 the opponents' guard time: the segments from c to the two goal posts
+ *      first meet the defense area (def_depth deep, def_width wide, in front
+ *      of the goal) at P and Q; with t_P, t_Q the earliest opponent arrivals
+ *      there (the robot model of dpps_search), min((t_P + t_Q) / guard_norm, 1),
+ *      1 without opponents;
+ *   x5 avoiding the defense: every opponent nearer to the ball than c marks
+ *      c with weight max(0, 1 - |o - c| / mark_radius); 1 - the largest mark.
+ * A point strictly inside the defense area cannot be used (score -inf).  The
+ * paper names the criteria without formulas or weights: all of the above
+ * constants are caller parameters. */
+typedef struct {
+    float w_goal, w_ball, w_angle, w_guard, w_defense; /* Eq. (4) weights (finite) */
+    float ball_norm;                 /* m, > 0 */
+    float ang_lo, ang_hi, ang_fall;  /* rad: 0 <= ang_lo <= ang_hi, ang_fall > 0 */
+    float guard_norm;                /* s, > 0 */
+    float def_depth, def_width;      /* m, >= 0 (SSL 2019 division A: 1.2 x 2.4) */
+    float mark_radius;               /* m, > 0 */
+    int32_t reserved;                /* must be 0 */
+} dpps_run_params;
+
+/* Best running point of one zone: largest score, ties to the lowest
+ * row-major index; found = 0 when every point lies in the defense area. */
+typedef struct {
+    int32_t found, i, j, reserved;
+    float x, y, score;
+    float goal, ball, angle, guard, defense; /* the five criteria there */
+} dpps_run_best;
+
+/* Scores of every zone point into d_score (may be NULL; element order of
+ * dpps_search_batch with one variant per frame) and one dpps_run_best per
+ * zone into d_best (required; zones in the order of the frames, then of each
+ * frame's windows).  Only the ball and the opponents of a frame are used.
+ * Asynchronous on the stream; host inputs staged through the context.
+ * Errors: DPPS_E_INVALID (parameters, frames, zones outside the lattice),
+ * DPPS_E_DEVICE. */
+int dpps_running_points(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                        const dpps_robot *robots, const dpps_window *zones,
+                        const dpps_run_params *rp, float *d_score, dpps_run_best *d_best,
+                        void *hip_stream);
+
 const char *dpps_strerror(int code);
 const char *dpps_last_error(void);
 int dpps_version(void);

@@ -45,6 +45,20 @@ SHOT_DT = np.dtype([("shoot", "<i4"), ("reachable", "<i4"), ("aim", "<f4"), ("ga
                     ("open_angle", "<f4"), ("length", "<f4"), ("t_goal", "<f4"),
                     ("slack", "<f4")])
 
+RUN_BEST_DT = np.dtype([("found", "<i4"), ("i", "<i4"), ("j", "<i4"), ("reserved", "<i4"),
+                        ("x", "<f4"), ("y", "<f4"), ("score", "<f4"), ("goal", "<f4"),
+                        ("ball", "<f4"), ("angle", "<f4"), ("guard", "<f4"),
+                        ("defense", "<f4")])
+
+# Running-point parameters (Sec. 5.2; the paper gives no values): Eq. (4)
+# weights, the ball-distance and guard-time scales, the preferred bearing
+# window 15-45 degrees with a 30-degree fall-off, the SSL 2019 division A
+# defense area (1.2 m deep, 2.4 m wide) and a 1 m marking radius.
+RUN_DEFAULTS = dict(w_goal=0.3, w_ball=0.1, w_angle=0.15, w_guard=0.25, w_defense=0.2,
+                    ball_norm=2.0, ang_lo=0.2617993877991494, ang_hi=0.7853981633974483,
+                    ang_fall=0.5235987755982988, guard_norm=2.0, def_depth=1.2, def_width=2.4,
+                    mark_radius=1.0)
+
 
 class DppsError(RuntimeError):
     def __init__(self, code: int, msg: str):
@@ -70,6 +84,13 @@ class Outputs_C(C.Structure):
 class RayParams_C(C.Structure):
     _fields_ = [("n_dirs", C.c_int32), ("w_time", C.c_float), ("w_refract", C.c_float),
                 ("reserved", C.c_int32)]
+
+
+class RunParams_C(C.Structure):
+    _fields_ = [(n, C.c_float) for n in (
+        "w_goal", "w_ball", "w_angle", "w_guard", "w_defense", "ball_norm", "ang_lo", "ang_hi",
+        "ang_fall", "guard_norm", "def_depth", "def_width", "mark_radius")] + [
+        ("reserved", C.c_int32)]
 
 
 class ShotParams_C(C.Structure):
@@ -146,6 +167,8 @@ def lib():
                                       C.POINTER(RayOutputs_C), vp]
         L.dpps_shot_decision.argtypes = [vp, i32, vp, vp, vp, C.POINTER(ShotParams_C), vp, vp,
                                          vp]
+        L.dpps_running_points.argtypes = [vp, i32, vp, vp, vp, C.POINTER(RunParams_C), vp, vp,
+                                          vp]
         L.dpps_search_power.argtypes = [vp, i32, vp, vp, vp, C.POINTER(PowerParams_C),
                                         C.POINTER(Outputs_C), vp, vp]
         L.dpps_timing_begin.argtypes = [vp, i32]
@@ -284,6 +307,39 @@ class RayDeviceOutputs:
         return np.frombuffer(self.best.cpu().numpy().tobytes(), RAY_BEST_DT)
 
 
+def run_best_host(t) -> np.ndarray:
+    """RUN_BEST_DT records of a byte tensor written by Searcher.running_points."""
+    return np.frombuffer(t.cpu().numpy().tobytes(), RUN_BEST_DT)
+
+
+def front_zones(ball, p, h: float = 0.1):
+    """Four zones of the front field that move with the ball (Sec. 5.1), as
+    windows of the h lattice.  Reading (the zone figures are not available):
+    x from clamp(ball_x - 1, -2, 3) to goal_x - 0.5 m, split in two halves
+    (I/II behind, III/IV in front), each split at y = 0, y within 0.3 m of
+    the touch lines; the more aggressive zones III and IV come last."""
+    hx, hy = 0.5 * p.field_len, 0.5 * p.field_wid
+    nx_all, ny_all = int(round(p.field_len / h)) + 1, int(round(p.field_wid / h)) + 1
+    xa = min(max(float(ball[0]) - 1.0, -2.0), 3.0)
+    xb = p.goal_x - 0.5
+    xm = 0.5 * (xa + xb)
+    ya, yb = -hy + 0.3, hy - 0.3
+
+    def I(x):
+        return int(round((x + hx) / h))
+
+    def J(y):
+        return int(round((y + hy) / h))
+
+    assert I(xb) < nx_all and J(yb) < ny_all
+    out = []
+    for x0, x1 in ((xa, xm), (xm, xb)):
+        for y0, y1 in ((ya, 0.0), (0.0, yb)):
+            i0, i1, j0, j1 = I(x0), I(x1), J(y0), J(y1)
+            out.append((np.float32(h), i0, j0, i1 - i0 + 1, j1 - j0 + 1))
+    return out
+
+
 def shots_host(t) -> np.ndarray:
     """SHOT_DT records of a byte tensor written by Searcher.shot."""
     return np.frombuffer(t.cpu().numpy().tobytes(), SHOT_DT)
@@ -342,6 +398,44 @@ class Searcher:
         _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
                                  _ptr(pk.variants), C.byref(oc), best.ctypes.data))
         return out, best[0]
+
+    def running_points(self, frames, score: bool = True, stream=None, out=None, **run):
+        """Running points (Sec. 5.2) over each frame's windows as zones
+        (e.g. front_zones()); asynchronous on the stream.  Returns (best,
+        score): best a byte tensor of RUN_BEST_DT records, one per zone in
+        frame then window order (run_best_host() converts it), score a float
+        tensor per zone point (None without score).  Keyword arguments
+        override RUN_DEFAULTS."""
+        import torch
+        if isinstance(frames, Packed):
+            pk = frames
+        else:
+            fr = []
+            for f in frames:
+                g = f.copy()
+                g.variants = [(DPPS_FLAT, 1.0)]
+                fr.append(g)
+            pk = pack(fr, self.params, self.out_flags)
+        n_zones = int(pk.frames["n_windows"].astype(np.int64).sum())
+        if out is not None:
+            best, sc = out
+        else:
+            best = torch.empty(max(n_zones, 1) * RUN_BEST_DT.itemsize, dtype=torch.uint8,
+                               device=self.device)
+            sc = torch.empty(max(pk.total, 1), dtype=torch.float32, device=self.device)
+        if not score:
+            sc = None
+        v = dict(RUN_DEFAULTS)
+        unknown = set(run) - set(v)
+        if unknown:
+            raise TypeError(f"unknown running-point parameters {sorted(unknown)}")
+        v.update(run)
+        rp = RunParams_C(*[float(v[k]) for k, _ in RunParams_C._fields_[:-1]], 0)
+        _check(lib().dpps_running_points(self.h, len(pk.frames), _ptr(pk.frames), _ptr(pk.robots),
+                                         _ptr(pk.windows), C.byref(rp),
+                                         sc.data_ptr() if sc is not None else None,
+                                         best.data_ptr(), _stream_ptr(stream)))
+        return best, sc
 
     def pack_shots(self, frames, v_shot: float = 6.5, map: bool = True) -> "Packed":
         """Pack frames for shot(): one flat variant at v_shot per frame, and

@@ -470,6 +470,7 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
     c->fallback.ctx = c;
     c->rays.ctx = c;
     c->shots.ctx = c;
+    c->runs.ctx = c;
     if (hipSetDevice(device) != hipSuccess) {
         delete c;
         return fail(DPPS_E_DEVICE, "hipSetDevice(%d) failed", device);
@@ -516,6 +517,7 @@ void dpps_destroy(dpps_ctx *c)
     batch_free_device(&c->fallback);
     batch_free_device(&c->rays);
     batch_free_device(&c->shots);
+    batch_free_device(&c->runs);
     if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staged) (void)hipEventDestroy(c->staged);
@@ -807,6 +809,55 @@ int dpps_shot_decision(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     a.ball = d_ball;
     a.map = d_map;
     if (launch_shot(a, c->shot_waves, (void *)st)) return fail(DPPS_E_DEVICE, "shot launch failed");
+    return DPPS_OK;
+}
+
+int dpps_running_points(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                        const dpps_robot *robots, const dpps_window *zones,
+                        const dpps_run_params *rp, float *d_score, dpps_run_best *d_best,
+                        void *hip_stream)
+{
+    if (!c || !rp || !d_best) return fail(DPPS_E_INVALID, "NULL argument");
+    const float w[5] = {rp->w_goal, rp->w_ball, rp->w_angle, rp->w_guard, rp->w_defense};
+    for (float x : w)
+        if (!isfinite(x)) return fail(DPPS_E_INVALID, "running points: weights must be finite");
+    if (!finite_pos(rp->ball_norm) || !finite_pos(rp->guard_norm) || !finite_pos(rp->mark_radius) ||
+        !finite_pos(rp->ang_fall) || !(rp->ang_lo >= 0.0f) || !(rp->ang_hi >= rp->ang_lo) ||
+        !isfinite(rp->ang_hi) || !(rp->def_depth >= 0.0f) || !(rp->def_depth <= c->p.field_len) ||
+        !(rp->def_width >= 0.0f) || !(rp->def_width <= c->p.field_wid) || rp->reserved != 0)
+        return fail(DPPS_E_INVALID, "running points: norms and ang_fall > 0, 0 <= ang_lo <= ang_hi, "
+                                    "defense area within the field, reserved 0");
+    if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (n_frames == 0) return DPPS_OK;
+    if (!frames) return fail(DPPS_E_INVALID, "NULL input array");
+    // one (unused) variant per frame; the zones are the frames' windows
+    std::vector<dpps_frame> fr(frames, frames + n_frames);
+    const dpps_variant one = {DPPS_FLAT, 1.0f};
+    for (dpps_frame &F : fr) {
+        F.n_variants = 1;
+        F.variant_off = 0;
+    }
+    dpps_batch *b = &c->runs;
+    int rc = build_tables(&c->p, n_frames, fr.data(), robots, zones, &one, 256, b->T);
+    if (rc) return rc;
+    b->n_frames = n_frames;
+    b->tile_points = 256;
+    rc = stage_tables(c, b, st);
+    if (rc) return rc;
+    RunArgs a;
+    memset(&a, 0, sizeof a);
+    a.P = c->P;
+    a.R = *rp;
+    a.frames = b->d_frames;
+    a.robots = b->d_robots;
+    a.variants = b->d_variants;
+    a.wins = b->d_wins;
+    a.n_wins = (int32_t)b->T.wins.size();
+    a.score = d_score;
+    a.best = d_best;
+    if (launch_run(a, (void *)st)) return fail(DPPS_E_DEVICE, "running-point launch failed");
     return DPPS_OK;
 }
 

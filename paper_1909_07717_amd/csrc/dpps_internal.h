@@ -137,6 +137,19 @@ struct ShotArgs {
     dpps_shot *map;         // one record per window point (may be NULL)
 };
 
+// Running points: one workgroup per zone (window).
+struct RunArgs {
+    DevParams P;
+    dpps_run_params R;
+    const FrameDev *frames;
+    const dpps_robot *robots;
+    const dpps_variant *variants;
+    const WinDev *wins;
+    int32_t n_wins;
+    float *score;           // per point (may be NULL)
+    dpps_run_best *best;    // per zone
+};
+
 // host-side launchers (dpps_kernels.hip)
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the search kernel only.
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
@@ -148,5 +161,6 @@ int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream);
 int ray_occupancy(int K, int waves_per_wg);
 // Shooting decisions: the ball kernel, then (with a.map) the window kernel.
 int launch_shot(const ShotArgs &a, int waves_per_wg, void *stream);
+int launch_run(const RunArgs &a, void *stream);
 
 }  // namespace dpps

@@ -1277,6 +1277,140 @@ int launch_shot(const ShotArgs &a, int waves_per_wg, void *stream)
     }
 }
 
+// ----------------------------------------------------------------------------
+// Running points (Sec. 5.2): five criteria per zone vertex, weighted (Eq. 4);
+// lanes are points, the opponents are looped over from LDS.
+// ----------------------------------------------------------------------------
+
+// Arrival time (seconds) of staged robot r = (x, y, vx, vy) at (px, py): the
+// scaled model of robot_time_h with the offset taken directly.
+__device__ __forceinline__ float robot_time_pt(const DevParams &P, float4 r, float px, float py)
+{
+    const float dx = (px - r.x) * P.A, dy = (py - r.y) * P.A;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-30f));
+    const float inv = rsq(r2);
+    const float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
+    float u = fmaf(dx, r.z, dy * r.w) * (0.70710678118654752f * inv);
+    u = med3(u, -P.Vh, P.Vh);
+    const float st = u * u;
+    const float ss = u * fabsf(u);
+    const bool over = ss >= del;
+    const float Dp = st + (over ? -del : del);
+    const float sg = over ? u : -u;
+    const float rh = Dp > P.V2 ? fmaf(Dp, P.inv2V, P.halfV) : hsqrt(Dp);
+    return fmaf(sg, 0.70710678118654752f, rh) * P.invA2;
+}
+
+// Entry parameter of the segment from c along (dx, dy) into the rectangle
+// [x0, x1] x [y0, y1] that holds its end point (slab form, FP64: a segment
+// that grazes an edge must be decided as the oracle decides it).
+__device__ __forceinline__ double slab_enter(double cx, double cy, double dx, double dy,
+                                             double x0, double x1, double y0, double y1)
+{
+    double t = 0.0;
+    if (dx > 0.0) t = fmax(t, (x0 - cx) / dx);
+    if (dx < 0.0) t = fmax(t, (x1 - cx) / dx);
+    if (dy > 0.0) t = fmax(t, (y0 - cy) / dy);
+    if (dy < 0.0) t = fmax(t, (y1 - cy) / dy);
+    return fmin(t, 1.0);
+}
+
+// The five criteria and the score at (cx, cy); returns -inf inside the
+// defense area (crit untouched).
+__device__ float run_eval(const StageLDS &S, const DevParams &P, const dpps_run_params &R,
+                          double cx, double cy, int n_tm, int n_op, float (&crit)[5])
+{
+    const double x0d = (double)P.goal_x - (double)R.def_depth;
+    const double hwd = 0.5 * (double)R.def_width;
+    if (cx > x0d && cx < (double)P.goal_x && cy > -hwd && cy < hwd) return -INFINITY;
+    const float fx = (float)cx, fy = (float)cy;
+    // the offset to the goal centre in FP64, then rounded once: its sign
+    // decides the bearing's branch for points on the goal line
+    const float gx = (float)((double)P.goal_x - cx), gy = (float)(-cy);
+    crit[0] = fmaf(-sqrtf(fmaf(gx, gx, gy * gy)), P.inv_dist_norm, 1.0f);
+    const double bx = cx - (double)S.bx, by = cy - (double)S.by;
+    const double db2 = bx * bx + by * by;
+    crit[1] = fminf(sqrtf((float)db2) / R.ball_norm, 1.0f);
+    const float phi = fabsf(atan2f(gy, gx));
+    const float off = phi < R.ang_lo ? R.ang_lo - phi : (phi > R.ang_hi ? phi - R.ang_hi : 0.0f);
+    crit[2] = fmaxf(1.0f - off / R.ang_fall, 0.0f);
+    const double gxd = (double)P.goal_x - cx, hwg = (double)P.half_goal_w;
+    const double dpy = hwg - cy, dqy = -hwg - cy;
+    const double tp_ = slab_enter(cx, cy, gxd, dpy, x0d, (double)P.goal_x, -hwd, hwd);
+    const double tq_ = slab_enter(cx, cy, gxd, dqy, x0d, (double)P.goal_x, -hwd, hwd);
+    const float px = (float)(cx + tp_ * gxd), py = (float)(cy + tp_ * dpy);
+    const float qx = (float)(cx + tq_ * gxd), qy = (float)(cy + tq_ * dqy);
+    float tP = INFINITY, tQ = INFINITY, mark = 0.0f;
+    for (int o = 0; o < n_op; ++o) {
+        const float4 r = S.rob[n_tm + o];
+        tP = fminf(tP, robot_time_pt(P, r, px, py));
+        tQ = fminf(tQ, robot_time_pt(P, r, qx, qy));
+        const double ox = (double)r.x - (double)S.bx, oy = (double)r.y - (double)S.by;
+        const float ex = r.x - fx, ey = r.y - fy;
+        const float wgt = fmaxf(1.0f - sqrtf(fmaf(ex, ex, ey * ey)) / R.mark_radius, 0.0f);
+        mark = (ox * ox + oy * oy < db2) ? fmaxf(mark, wgt) : mark;
+    }
+    crit[3] = n_op > 0 ? fminf((tP + tQ) / R.guard_norm, 1.0f) : 1.0f;
+    crit[4] = 1.0f - mark;
+    return fmaf(R.w_goal, crit[0],
+                fmaf(R.w_ball, crit[1],
+                     fmaf(R.w_angle, crit[2], fmaf(R.w_guard, crit[3], R.w_defense * crit[4]))));
+}
+
+__global__ void __launch_bounds__(256) run_kernel(RunArgs a)
+{
+    __shared__ StageLDS S;
+    __shared__ unsigned long long red[4];
+    const DevParams &P = a.P;
+    const WinDev W = a.wins[blockIdx.x];
+    stage_frame(P, a.frames, a.robots, a.variants, W.frame, S);
+    __syncthreads();
+    const int n_tm = S.n_tm, n_op = S.n_op;
+    unsigned long long best = 0ull;
+    for (int p = threadIdx.x; p < W.npts; p += blockDim.x) {
+        const int j = p / W.nx, i = p - j * W.nx;
+        const double cx = (double)W.h * ((double)(W.i0 + i) - (double)W.halfNx);
+        const double cy = (double)W.h * ((double)(W.j0 + j) - (double)W.halfNy);
+        float crit[5];
+        const float sc = run_eval(S, P, a.R, cx, cy, n_tm, n_op, crit);
+        if (a.score) a.score[W.out_base + p] = sc;
+        if (sc > -INFINITY) {
+            const unsigned long long k = ((unsigned long long)ordered_bits(sc) << 32) |
+                                         (unsigned long long)(0xFFFFFFFFu - (uint32_t)p);
+            best = k > best ? k : best;
+        }
+    }
+    best = wave_max_u64(best);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = red[w] > best ? red[w] : best;
+    dpps_run_best r;
+    r.found = 0; r.i = -1; r.j = -1; r.reserved = 0;
+    r.x = 0.0f; r.y = 0.0f; r.score = -INFINITY;
+    r.goal = r.ball = r.angle = r.guard = r.defense = 0.0f;
+    if (best != 0ull) {
+        const int p = (int)(0xFFFFFFFFu - (uint32_t)best);
+        const int j = p / W.nx, i = p - j * W.nx;
+        const double cx = (double)W.h * ((double)(W.i0 + i) - (double)W.halfNx);
+        const double cy = (double)W.h * ((double)(W.j0 + j) - (double)W.halfNy);
+        float crit[5];
+        r.score = run_eval(S, P, a.R, cx, cy, n_tm, n_op, crit);
+        r.found = 1; r.i = i; r.j = j;
+        r.x = (float)cx; r.y = (float)cy;
+        r.goal = crit[0]; r.ball = crit[1]; r.angle = crit[2]; r.guard = crit[3];
+        r.defense = crit[4];
+    }
+    a.best[blockIdx.x] = r;
+}
+
+int launch_run(const RunArgs &a, void *stream)
+{
+    if (a.n_wins > 0)
+        hipLaunchKernelGGL(run_kernel, dim3(a.n_wins), dim3(256), 0, (hipStream_t)stream, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                   void *ev_stop)
 {

@@ -89,6 +89,7 @@ struct dpps_ctx {
     dpps_batch shots;        // tables of dpps_shot_decision
     int shot_tile = 16;      // window points per workgroup of the shot map
     int shot_waves = 4;      // waves per workgroup of the shot map
+    dpps_batch runs;         // tables of dpps_running_points
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;   // pinned staging consumed

@@ -109,3 +109,16 @@ def shot_flops(n_opp: int, K: int) -> int:
     """Flops of one shooting decision against n_opp opponents, K samples."""
     return (n_opp * K * C_ROBOT + K * C_SHOT_SAMPLE + C_SHOT_SET + C_ANGLE
             + (C_ANGLE_OPP + C_SHOT_GAP) * n_opp)
+
+
+# Running points (Sec. 5.2), per zone point: the defense-area test, the goal
+# distance, bearing and angle window, the ball distance, the two entry points
+# P and Q (C_RUN_POINT), then per opponent two robot arrival times and the
+# marking weight (C_RUN_OPP).
+C_RUN_POINT = 90
+C_RUN_OPP = 2 * C_ROBOT + 12
+
+
+def run_flops(n_opp: int) -> int:
+    """Flops of one running-point evaluation against n_opp opponents."""
+    return C_RUN_POINT + C_RUN_OPP * n_opp

@@ -54,6 +54,8 @@ int main(void) {
   S(dpps_power_params); O(dpps_power_params, v_max);
   S(dpps_shot_params); S(dpps_shot); O(dpps_shot_params, margin_s); O(dpps_shot, aim);
   O(dpps_shot, t_goal); O(dpps_shot, slack);
+  S(dpps_run_params); S(dpps_run_best); O(dpps_run_params, mark_radius);
+  O(dpps_run_params, reserved); O(dpps_run_best, score); O(dpps_run_best, defense);
   return 0;
 }
 """
@@ -96,6 +98,12 @@ def test_struct_layouts_match_header(tmp_path):
     assert got["dpps_shot"] == B.SHOT_DT.itemsize
     for f in ("aim", "t_goal", "slack"):
         assert got[f"dpps_shot.{f}"] == B.SHOT_DT.fields[f][1]
+    assert got["dpps_run_params"] == C.sizeof(B.RunParams_C)
+    assert got["dpps_run_params.mark_radius"] == B.RunParams_C.mark_radius.offset
+    assert got["dpps_run_params.reserved"] == B.RunParams_C.reserved.offset
+    assert got["dpps_run_best"] == B.RUN_BEST_DT.itemsize
+    for f in ("score", "defense"):
+        assert got[f"dpps_run_best.{f}"] == B.RUN_BEST_DT.fields[f][1]
 
 
 def test_layout_is_host_only_and_dense():
