@@ -16,9 +16,11 @@
 //                    sample exactly when the first teammate (opponent) does;
 //                    a slower kick is intercepted there, a faster one is not
 //                    (the ball model of Sec. 4.1 is monotone in the kick speed).
-//   3. first crossing per variant, a ballot of "v0 <= critical speed" over the
-//                    samples; the lowest set bit is the first interception
-//                    (SBIP, Sec. 4.2).
+//   3. first crossing per variant (SBIP, Sec. 4.2): the lowest sample whose
+//                    critical speed is at least v0; the running maximum of the
+//                    critical speeds over the samples is non-decreasing, so
+//                    every variant lane finds its crossing by binary search in
+//                    the wave's LDS row of running maxima.
 //   4. finish        lanes become variants: ball time at the crossing sample
 //                    (float64), margin, feasibility and the Eq. (3) score
 //                    (Sec. 4.3); results are staged in LDS and written as whole
@@ -38,6 +40,11 @@ namespace dpps {
 #define MAX_VAR DPPS_MAX_VARIANTS
 #define MAX_TILE 64
 #define MAX_WAVES 8
+#define MAX_K 256
+#define PM_ROWS 4  // running-maximum rows per wave: flat team / opp, chip team / opp
+
+// Dynamic LDS of the search and ray kernels: PM_ROWS rows of K floats per wave.
+static size_t pm_bytes(int K, int waves) { return (size_t)waves * PM_ROWS * K * sizeof(float); }
 
 struct VarConst {
     double va1, a1, va2, a2, soff2, toff2, split, D, sf_reach;
@@ -262,44 +269,80 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
     return (float)(L * (double)P.A);
 }
 
-// First crossing of every variant in `vm` (lane mask of the variants of one
-// kick type, staged by increasing speed; lane v holds variant v's speed in
-// myv0): the lowest sample k whose critical speed is at least v0, for the
-// team (vt) and the opponents (vo); K when there is none.  Sample groups are
-// scanned in order and each side stops at its first hit.  A faster kick
-// never crosses earlier (every sample it passes, a slower kick passes too),
-// so each variant's scan starts at the group where the previous one crossed.
-// Lane 0 stores kt | ko << 16 into xr[v] (this wave's row).
-template <int KPL>
-__device__ __forceinline__ void first_crossings(unsigned long long vm, float myv0,
-                                                const float (&vt)[KPL], const float (&vo)[KPL],
-                                                uint32_t *xr)
+// Inclusive prefix maximum over the 64 lanes of a wave (lane l gets the
+// maximum of lanes 0..l): four DPP row shifts give it within each row of 16
+// lanes (lanes without a source see -inf), then the row totals are carried
+// to the rows after them.
+template <int N>
+__device__ __forceinline__ float row_shr_max(float v)
 {
-    const int K = KPL * 64;
-    const bool lead = lane_id() == 0;
-    int qt = 0, qo = 0;  // group where the previous variant crossed (KPL: none)
-    for (unsigned long long m = vm; m; m &= m - 1) {
-        const int v = __builtin_ctzll(m);
-        const float v0 = readlane_f(myv0, v);
-        int kt = K, ko = K;
-        int gt = qt, go = qo;  // next group to scan (KPL: done)
+    const int u = __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v),
+                                              0x110 + N, 0xf, 0xf, false);
+    return fmaxf(v, __int_as_float(u));
+}
+
+__device__ __forceinline__ float wave_prefix_max(float v)
+{
+    v = row_shr_max<1>(v);
+    v = row_shr_max<2>(v);
+    v = row_shr_max<4>(v);
+    v = row_shr_max<8>(v);
+    const float c1 = readlane_f(v, 15);
+    const float c2 = fmaxf(c1, readlane_f(v, 31));
+    const float c3 = fmaxf(c2, readlane_f(v, 47));
+    const int l = lane_id();
+    return fmaxf(v, l >= 48 ? c3 : (l >= 32 ? c2 : (l >= 16 ? c1 : -INFINITY)));
+}
+
+// Order this wave's accesses to its own LDS row.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First crossings by running maxima.  The first crossing of a variant on
+// one side is the lowest sample k whose critical speed vc_k is at least the
+// kick speed v0 (K: none).  The running maximum of vc over the samples is
+// non-decreasing, so that crossing is the number of samples whose running
+// maximum is still below v0.  The wave writes each side's running maxima to a
+// row of its LDS block (samples are lane-major: lane l holds k = l KPL + q),
+// then every variant lane counts by binary search in its kick type's two rows,
+// the team's and the opponents' searches interleaved.  The decisions are the
+// comparisons v0 <= vc_k of a scan over k.
+template <int KPL>
+__device__ __forceinline__ void store_running_max(const float (&vc)[KPL], float *row)
+{
+    const int l = lane_id();
+    float run[KPL];
+    run[0] = vc[0];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-            if (gt == q) {
-                const unsigned long long mt = __ballot(v0 <= vt[q]);
-                kt = mt ? q * 64 + __builtin_ctzll(mt) : K;
-                gt = mt ? KPL : q + 1;
-            }
-            if (go == q) {
-                const unsigned long long mo = __ballot(v0 <= vo[q]);
-                ko = mo ? q * 64 + __builtin_ctzll(mo) : K;
-                go = mo ? KPL : q + 1;
-            }
-        }
-        qt = kt >> 6;
-        qo = ko >> 6;
-        if (lead) xr[v] = (uint32_t)kt | ((uint32_t)ko << 16);
+    for (int q = 1; q < KPL; ++q) run[q] = fmaxf(run[q - 1], vc[q]);
+    const float incl = wave_prefix_max(run[KPL - 1]);
+    const float prev = __shfl_up(incl, 1, 64);
+    const float excl = l == 0 ? -INFINITY : prev;
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) row[l * KPL + q] = fmaxf(excl, run[q]);
+}
+
+template <int KPL>
+__device__ __forceinline__ void count_below(const float *rt, const float *ro, float v0, int &kt,
+                                            int &ko)
+{
+    constexpr int K = KPL * 64;
+    constexpr int S0 = KPL >= 4 ? 256 : (KPL >= 2 ? 128 : 64);  // largest power of 2 <= K
+    int lt = 0, lo = 0;
+#pragma unroll
+    for (int st = S0; st > 0; st >>= 1) {
+        const int it = lt + st - 1, io = lo + st - 1;
+        const float mt = rt[it < K ? it : K - 1];
+        const float mo = ro[io < K ? io : K - 1];
+        lt = (it < K && mt < v0) ? lt + st : lt;
+        lo = (io < K && mo < v0) ? lo + st : lo;
     }
+    kt = lt;
+    ko = lo;
 }
 
 // Kick speed at which the ball covers distance s in exactly time T (the
@@ -427,9 +470,6 @@ __device__ float open_angle(const StageLDS &S, const DevParams &P, float cx, flo
     return (hi - lo) - blocked;
 }
 
-// Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
-// hold lane v's variant (lanes >= n_var: type -1).  On return lane v
-// (< n_var) holds that variant's results.
 // Passing power (Sec. 4.1, Eq. 1-2) for a pass over d64 metres whose
 // receiver arrives after t_recv seconds: the ball should arrive t_recv +
 // buffer; ignoring the sliding phase, the speed after it is (d + a t^2/2) / t
@@ -448,14 +488,15 @@ __device__ __forceinline__ double pass_power(const DevParams &P, double d64, flo
 
 // SBIP of every staged variant along one path of length d (metres; LA = d
 // scaled by amax) whose path frame is in pr: robot stage over the lane's
-// samples (lanes = samples), critical speeds, first crossings through xr.  On
+// samples (lanes = samples, K/64 consecutive samples per lane), critical
+// speeds, first crossings (pm: this wave's LDS block of 4 K floats).  On
 // return lane v (a staged variant) holds its first team / opponent crossing
 // samples (K: none).  With POWER the frame's variants are replaced by one
 // flat pass at the power of Eq. 1-2 (lane 0), whose receiver is the first
 // teammate at the last sample, the point itself; its speed is returned in v0.
 template <int KPL, bool POWER>
 __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParams &P,
-                                               const float4 *pr, uint32_t *xr, float myv0,
+                                               const float4 *pr, float *pm, float myv0,
                                                int mytype, float d, float LA, int &my_kt,
                                                int &my_ko, double d64 = 0.0, double buffer = 0.0,
                                                double vmin = 0.0, double vmax = 0.0,
@@ -469,7 +510,7 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
     float fs[KPL], sk[KPL], Tt[KPL], To[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-        fs[q] = (float)(q * 64 + l + 1) * invK;
+        fs[q] = (float)(l * KPL + q + 1) * invK;
         sk[q] = fs[q] * d;
         Tt[q] = INFINITY;
         To[q] = INFINITY;
@@ -482,9 +523,8 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
         robot_stage<KPL, true>(pr, P, 0, n_tm, fs, LA, Tt);
         robot_stage<KPL, true>(pr, P, n_tm, n_op, fs, LA, To);
     }
-    // 2-3. critical kick speeds per sample, then the first crossing per
-    // variant by ballot, through xr to lane v
-    // (a side with no robot never intercepts: critical speed 0)
+    // 2-3. critical kick speeds per sample, then the first crossing of each
+    // lane's variant (a side with no robot never intercepts: critical speed 0)
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         Tt[q] *= P.invA2;  // seconds
@@ -499,11 +539,14 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
     }
     const unsigned long long flat_m = __ballot(mytype == DPPS_FLAT);
     const unsigned long long chip_m = __ballot(mytype == DPPS_CHIP);
+    float *const pf = pm, *const pc = pm + 2 * K;  // flat rows, chip rows
+    wave_lds_sync();  // the previous path's searches are done with the rows
     if (flat_m) {
         float vt[KPL], vo[KPL];
         side_vcrit<KPL, false>(P, n_tm, Tt, sk, sk, vt);
         side_vcrit<KPL, false>(P, n_op, To, sk, sk, vo);
-        first_crossings<KPL>(flat_m, myv0, vt, vo, xr);
+        store_running_max<KPL>(vt, pf);
+        store_running_max<KPL>(vo, pf + K);
     }
     if (chip_m) {
         float vt[KPL], vo[KPL], vair[KPL];
@@ -511,17 +554,15 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
         for (int q = 0; q < KPL; ++q) vair[q] = hsqrt(sk[q] * P.lam1_inv);
         side_vcrit<KPL, true>(P, n_tm, Tt, sk, vair, vt);
         side_vcrit<KPL, true>(P, n_op, To, sk, vair, vo);
-        first_crossings<KPL>(chip_m, myv0, vt, vo, xr);
+        store_running_max<KPL>(vt, pc);
+        store_running_max<KPL>(vo, pc + K);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
     my_kt = K;
     my_ko = K;
     if ((mytype == DPPS_FLAT) | (mytype == DPPS_CHIP)) {
-        const uint32_t x = xr[l];
-        my_kt = (int)(x & 0xFFFFu);
-        my_ko = (int)(x >> 16);
+        const float *r = mytype == DPPS_CHIP ? pc : pf;
+        count_below<KPL>(r, r + K, myv0, my_kt, my_ko);
     }
 }
 
@@ -531,7 +572,7 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
 // variant at its own passing power (returned in o_v0), computed from the
 // launch's buffer and kick range.
 template <int KPL, bool POWER>
-__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
+__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, float *pm,
                            float myv0, int mytype, float cx, float cy, double cx64,
                            double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to,
                            float &o_v0, const LaunchArgs &a)
@@ -547,7 +588,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, ui
     const double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
     int my_kt, my_ko;
     double v0 = 0.0;
-    sbip_crossings<KPL, POWER>(S, P, pr, xr, myv0, mytype, d, LA, my_kt, my_ko, d64,
+    sbip_crossings<KPL, POWER>(S, P, pr, pm, myv0, mytype, d, LA, my_kt, my_ko, d64,
                                (double)a.p_buffer, (double)a.p_vmin, (double)a.p_vmax, &v0);
     o_v0 = (float)v0;
     // open goal angle (lanes = opponents)
@@ -589,7 +630,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     __shared__ StageLDS S;
     __shared__ OutLDS O;
     __shared__ float4 PR[MAX_WAVES][MAX_ROB];  // each wave's path frame of its point
-    __shared__ uint32_t XR[MAX_WAVES][64];     // each wave's first crossings per variant
+    extern __shared__ float PMX[];              // each wave's running maxima: 4 rows of K
     __shared__ int s_tile;
     const DevParams &P = a.P;
     const int nw = blockDim.x >> 6;
@@ -640,7 +681,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
             float sc, tt, to, pv0;
             int fe;
-            eval_point<KPL, POWER>(S, P, PR[w], XR[w], myv0, mytype, cx, cy, cx64, cy64, sc, fe,
+            eval_point<KPL, POWER>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0, mytype, cx,
+                                   cy, cx64, cy64, sc, fe,
                                    tt, to, pv0, a);
             if (POWER && l == 0 && a.v0_out) a.v0_out[W.out_base + p] = pv0;
             unsigned long long key = 0ull;
@@ -785,11 +827,11 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
     if (e0) (void)hipEventRecord(e0, st);
     if (a.n_tiles > 0 && grid > 0) {
         if (a.power)
-            hipLaunchKernelGGL((search_kernel<KPL, true>), dim3(grid), dim3(64 * waves_per_wg), 0,
-                               st, a);
+            hipLaunchKernelGGL((search_kernel<KPL, true>), dim3(grid), dim3(64 * waves_per_wg),
+                               pm_bytes(KPL * 64, waves_per_wg), st, a);
         else
-            hipLaunchKernelGGL((search_kernel<KPL, false>), dim3(grid), dim3(64 * waves_per_wg), 0,
-                               st, a);
+            hipLaunchKernelGGL((search_kernel<KPL, false>), dim3(grid), dim3(64 * waves_per_wg),
+                               pm_bytes(KPL * 64, waves_per_wg), st, a);
     }
     if (e1) (void)hipEventRecord(e1, st);
     if (a.n_frames > 0)
@@ -837,7 +879,7 @@ struct RayOut {
 
 // Every staged variant (lanes) for direction d of the staged frame.
 template <int KPL>
-__device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *pr, uint32_t *xr,
+__device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *pr, float *pm,
                                 float myv0, int mytype, int myvid, int d, int n_dirs,
                                 float w_time, float w_refract)
 {
@@ -850,7 +892,7 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
     const double L = ray_length(P, bx, by, ux, uy);
     path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, bx, by);
     int my_kt, my_ko;
-    sbip_crossings<KPL, false>(S, P, pr, xr, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
+    sbip_crossings<KPL, false>(S, P, pr, pm, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
                         my_ko);
 
     RayOut o;
@@ -919,7 +961,7 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
 {
     __shared__ StageLDS S;
     __shared__ float4 PR[MAX_WAVES][MAX_ROB];
-    __shared__ uint32_t XR[MAX_WAVES][64];
+    extern __shared__ float PMX[];
     __shared__ RayRec WB[MAX_WAVES];
     __shared__ int s_tile;
     const DevParams &P = a.P;
@@ -957,7 +999,8 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
         best.open_angle = best.refract = best.pad = 0.0f;
         for (int slot = w; slot < nd; slot += nw) {
             const int d = tile.p0 + slot;
-            const RayOut o = ray_direction<KPL>(S, P, PR[w], XR[w], myv0, mytype, myvid, d,
+            const RayOut o = ray_direction<KPL>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0,
+                                                mytype, myvid, d,
                                                 a.n_dirs, a.w_time, a.w_refract);
             if (l < n_var) {
                 const int64_t e = base + (int64_t)d * n_var + myvid;
@@ -1061,7 +1104,8 @@ template <int KPL>
 static int launch_ray_kpl(const RayArgs &a, int waves_per_wg, int grid, hipStream_t st)
 {
     if (a.n_tiles > 0 && grid > 0)
-        hipLaunchKernelGGL(ray_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg), 0, st, a);
+        hipLaunchKernelGGL(ray_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg),
+                           pm_bytes(KPL * 64, waves_per_wg), st, a);
     if (a.n_frames > 0)
         hipLaunchKernelGGL(ray_finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1085,10 +1129,10 @@ int ray_occupancy(int K, int waves_per_wg)
     hipError_t e = hipErrorInvalidValue;
     const int bs = 64 * waves_per_wg;
     switch (K / 64) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<1>, bs, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<2>, bs, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<3>, bs, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<4>, bs, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<1>, bs, pm_bytes(1 * 64, waves_per_wg)); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<2>, bs, pm_bytes(2 * 64, waves_per_wg)); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<3>, bs, pm_bytes(3 * 64, waves_per_wg)); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, ray_kernel<4>, bs, pm_bytes(4 * 64, waves_per_wg)); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;
@@ -1431,10 +1475,10 @@ int search_occupancy(int K, int waves_per_wg)
     hipError_t e = hipErrorInvalidValue;
     const int bs = 64 * waves_per_wg;
     switch (K / 64) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1, false>, bs, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2, false>, bs, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3, false>, bs, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4, false>, bs, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1, false>, bs, pm_bytes(1 * 64, waves_per_wg)); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2, false>, bs, pm_bytes(2 * 64, waves_per_wg)); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3, false>, bs, pm_bytes(3 * 64, waves_per_wg)); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4, false>, bs, pm_bytes(4 * 64, waves_per_wg)); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;
