@@ -844,6 +844,47 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
 // received at the first teammate's interception, five-feature score.
 // ----------------------------------------------------------------------------
 
+// Open goal angle at up to four points at once: lane 16 g + o looks at
+// point g (its own cx, cy) and opponent o (at most 16 opponents).  The same
+// construction as open_angle within each group of 16 lanes; returns on every
+// lane the angle of its group's point.
+__device__ float open_angle4(const StageLDS &S, const DevParams &P, float cx, float cy, int n_op,
+                             int n_tm)
+{
+    const int l = lane_id();
+    const int o = l & 15, base = l & 48;
+    const float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
+    const float lo = atan2f(-P.half_goal_w - cy, dxg);
+    const float hi = atan2f(P.half_goal_w - cy, dxg);
+    const float4 r = S.rob[n_tm + (o < n_op ? o : 0)];
+    const float ox = r.x - cx, oy = r.y - cy;
+    const bool valid = o < n_op && r.x < P.goal_x;
+    const float rho2 = fmaf(ox, ox, oy * oy);
+    const bool inside = valid && rho2 <= P.R * P.R;
+    const float ang = atan2f(oy, ox);
+    const float al = asinf(fminf(P.R * rsq(fmaxf(rho2, 1e-30f)), 1.0f));
+    const float s = fmaxf(ang - al, lo);
+    const float e = fminf(ang + al, hi);
+    const bool has = valid && e > s;
+    // each interval adds what the group's intervals sorted before it (by
+    // start, then index) have not covered
+    float M = -INFINITY;
+    for (int j = 0; j < n_op; ++j) {
+        const float sj = __shfl(s, base | j, 64);
+        const float ej = __shfl(e, base | j, 64);
+        const int hj = __shfl((int)has, base | j, 64);
+        const bool before = hj && (sj < s || (sj == s && j < o));
+        M = before ? fmaxf(M, ej) : M;
+    }
+    float c = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
+    c += __shfl_xor(c, 1, 64);
+    c += __shfl_xor(c, 2, 64);
+    c += __shfl_xor(c, 4, 64);
+    c += __shfl_xor(c, 8, 64);
+    const bool gin = ((__ballot(inside) >> base) & 0xFFFFull) != 0ull;
+    return gin ? 0.0f : (hi - lo) - c;
+}
+
 // Order-preserving map of a float's bits to an unsigned key (negative scores
 // order below positive ones).
 __device__ __forceinline__ uint32_t ordered_bits(float x)
@@ -921,22 +962,42 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
         px = bx + st * ux;
         py = by + st * uy;
     }
-    // open goal angle at each feasible passing point (lanes = opponents), once
-    // per distinct passing sample
+    // open goal angle at each feasible passing point: a feasible lane whose
+    // passing sample differs from the previous feasible lane's leads; the
+    // leaders' points go four at a time through open_angle4, and the other
+    // feasible lanes take their leader's angle
     const unsigned long long fm = __ballot(o.feas != 0);
-    float ang = 0.0f, my_ang = 0.0f;
-    int last_k = -1;
-    for (unsigned long long mm = fm; mm; mm &= mm - 1) {
-        const int v = __builtin_ctzll(mm);
-        const int kv = readlane_i(my_kt, v);
-        if (kv != last_k) {
-            const float pxv = __int_as_float(readlane_i(__float_as_int((float)px), v));
-            const float pyv = __int_as_float(readlane_i(__float_as_int((float)py), v));
-            ang = open_angle(S, P, pxv, pyv, n_op, n_tm);
-            last_k = kv;
+    const unsigned long long below = fm & ((1ull << l) - 1ull);
+    const int prevl = below ? 63 - __builtin_clzll(below) : 0;
+    const int kprev = __shfl(my_kt, prevl, 64);
+    const bool lead = o.feas && (below == 0ull || kprev != my_kt);
+    const unsigned long long lm = __ballot(lead);
+    const float pxf = (float)px, pyf = (float)py;
+    float my_ang = 0.0f;
+    for (unsigned long long mm = lm; mm;) {
+        int lv[4];
+        float gx4[4], gy4[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            lv[g] = mm ? __builtin_ctzll(mm) : -1;
+            mm = mm ? mm & (mm - 1) : mm;
+            gx4[g] = lv[g] >= 0 ? readlane_f(pxf, lv[g]) : (float)bx;
+            gy4[g] = lv[g] >= 0 ? readlane_f(pyf, lv[g]) : (float)by;
         }
-        my_ang = l == v ? ang : my_ang;
+        const int g = l >> 4;
+        const float cxg = g == 0 ? gx4[0] : (g == 1 ? gx4[1] : (g == 2 ? gx4[2] : gx4[3]));
+        const float cyg = g == 0 ? gy4[0] : (g == 1 ? gy4[1] : (g == 2 ? gy4[2] : gy4[3]));
+        const float a4 = open_angle4(S, P, cxg, cyg, n_op, n_tm);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float aq = readlane_f(a4, 16 * q);
+            my_ang = (lv[q] >= 0 && l == lv[q]) ? aq : my_ang;
+        }
     }
+    const unsigned long long upto = l == 63 ? lm : lm & ((2ull << l) - 1ull);
+    const int lead_l = upto ? 63 - __builtin_clzll(upto) : l;
+    const float la = __shfl(my_ang, lead_l, 64);
+    my_ang = o.feas ? la : 0.0f;
     if (o.feas) {
         const double gx = (double)P.goal_x - px, gy = -py;
         const float dg = (float)sqrt(gx * gx + gy * gy);

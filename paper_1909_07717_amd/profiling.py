@@ -22,7 +22,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def run_search(steps: int, seed: int = 100, reduced: bool = False):
+def run_search(steps: int, seed: int = 100, reduced: bool = False, launch=None):
+    """The full frame of the benchmark (8v8, 5 cm, 32 variants, K = 256),
+    inputs resident, `steps` launches; `launch` = (tile_points, waves per
+    workgroup, workgroups per CU) or None for the context's default."""
     import torch
 
     from paper_1909_07717_amd import binding as Bn
@@ -30,6 +33,8 @@ def run_search(steps: int, seed: int = 100, reduced: bool = False):
 
     p = Params(n_samples=256).as_f32()
     s = Bn.Searcher(p, out_flags=Bn.DPPS_OUT_REDUCED if reduced else 0)
+    if launch:
+        s.set_launch(*launch)
     bt = s.batch([config_full(seed)])
     out = s.outputs_for(bt.pk)
     st = torch.cuda.Stream()
@@ -109,6 +114,8 @@ def main():
     a.add_argument("--steps", type=int, default=20)
     a.add_argument("--seed", type=int, default=100)
     a.add_argument("--reduced", action="store_true")
+    a.add_argument("--launch", type=int, nargs=3, default=None,
+                   metavar=("TILE", "WAVES", "WG_PER_CU"))
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=int, default=512)
     c.add_argument("--reps", type=int, default=4)
@@ -117,7 +124,7 @@ def main():
     m.add_argument("--steps", type=int, default=20)
     args = ap.parse_args()
     if args.cmd == "search":
-        run_search(args.steps, args.seed, args.reduced)
+        run_search(args.steps, args.seed, args.reduced, args.launch)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
     else:
