@@ -37,6 +37,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def progress(msg: str):
+    """One line per finished section on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def measured_traffic(flops_kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source; else None."""
@@ -432,6 +437,7 @@ def main() -> int:
     # launch shape (tile size, waves, persistent grid) from the autotuner, cached
     tuned = bt.autotune(out, args.tune_cache, reps=3, stream=st)
     shape = s.get_launch()
+    progress(f"launch shape {shape} ({'tuned' if tuned >= 0 else 'cached'})")
     with torch.cuda.stream(st):
         for _ in range(args.warmup):
             bt.run(out, stream=st)
@@ -450,6 +456,7 @@ def main() -> int:
     ms_step = (t1 - t0) * 1e3 / args.steps
     kern_avg_ms = kern_ms / max(n_runs, 1)
     value = evals / (ms_step * 1e-3)
+    progress(f"timed {args.steps} steps: {ms_step:.4f} ms/step, kernel {kern_avg_ms:.4f} ms")
 
     # the same steps replayed from a captured HIP graph
     with torch.cuda.stream(st):
@@ -484,19 +491,30 @@ def main() -> int:
                 lat.append((b - a) * 1e3)
     lat = np.array(lat) if lat else np.array([float("nan")])
 
+    progress(f"latency over {lat.size} frames")
+
     batch = None
     if args.batch_frames > 0:
         batch = batch_bench(args.batch_frames, args.batch_steps, args.tune_cache, st)
-    rays = (ray_bench(args.ray_frames, 5, min(args.latency_frames, 2000), st)
-            if args.ray_frames > 0 else None)
-    power = power_bench(20, st) if args.ray_frames > 0 else None
-    shots = (shot_bench(4096, 20, min(args.latency_frames, 2000), st)
-             if args.ray_frames > 0 else None)
-    running = (run_bench(4096, 20, min(args.latency_frames, 2000), st)
-               if args.ray_frames > 0 else None)
-    sur = (surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
-           if args.surrogate_frames > 0 else None)
+        progress("batch done")
+    rays = power = shots = running = None
+    if args.ray_frames > 0:
+        lf = min(args.latency_frames, 2000)
+        rays = ray_bench(args.ray_frames, 5, lf, st)
+        progress("direction sweep done")
+        power = power_bench(20, st)
+        progress("passing power done")
+        shots = shot_bench(4096, 20, lf, st)
+        progress("shots done")
+        running = run_bench(4096, 20, lf, st)
+        progress("running points done")
+    sur = None
+    if args.surrogate_frames > 0:
+        sur = surrogate_bench(args.surrogate_frames, args.weights, max(args.latency_frames, 100))
+        progress("surrogate done")
     serving = serving_bench(args.serve_seconds, args.weights) if args.serve_seconds > 0 else None
+    if serving is not None:
+        progress("serving done")
 
     achieved = fl / (kern_avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
@@ -508,6 +526,8 @@ def main() -> int:
                 "nonpacked_peak": FL.PEAK_FP32_NONPACKED_TFLOPS,
                 "frac_of_nonpacked": round(achieved / FL.PEAK_FP32_NONPACKED_TFLOPS, 4)}
     cpu = None if args.no_cpu else cpu_baseline(frame, p, args.cpu_seconds)
+    if cpu is not None:
+        progress("cpu baseline done")
     rec = {
         "metric": METRIC, "value": round(value, 1), "unit": "pass evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),

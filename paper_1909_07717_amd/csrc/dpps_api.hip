@@ -707,7 +707,8 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
                           b->T);
     if (rc) return rc;
     // tiles of ray_tile_dirs directions of one frame; outputs frame by frame
-    const int td = c->ray_tile_dirs;
+    // at least one direction per wave of a workgroup
+    const int td = c->ray_tile_dirs > c->waves ? c->ray_tile_dirs : c->waves;
     b->T.tiles.clear();
     int64_t base = 0;
     for (int32_t f = 0; f < n_frames; ++f) {
