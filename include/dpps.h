@@ -284,12 +284,15 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
  * validated but not searched): the tables go through the context's pinned
  * staging into device memory the context keeps, so a steady stream of
  * requests allocates nothing.  n_frames must not exceed the network's
- * max_frames. */
+ * max_frames.  h_best (host, n_frames records, may be NULL): when given, the
+ * best records are also written there and the call returns once the stream
+ * has finished them (the fallback check reads them anyway). */
 int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
                                  const dpps_frame *frames, const dpps_robot *robots,
                                  const dpps_window *windows, const dpps_variant *variants,
                                  int32_t k, dpps_best *d_best, int fallback, float fallback_below,
-                                 int32_t *n_fallback, void *hip_stream);
+                                 int32_t *n_fallback, dpps_best *h_best,
+                                 void *hip_stream);
 
 /* ---- passing power per point (Sec. 4.1, Eq. 1-2) ------------------------
  * Instead of a list of kick speeds, every candidate point gets its own flat

@@ -162,7 +162,7 @@ def lib():
         L.dpps_surrogate_search.argtypes = [vp, vp, vp, i32, vp, C.c_int, C.c_float,
                                             C.POINTER(i32), vp]
         L.dpps_surrogate_search_frames.argtypes = [vp, vp, i32, vp, vp, vp, vp, i32, vp, C.c_int,
-                                                   C.c_float, C.POINTER(i32), vp]
+                                                   C.c_float, C.POINTER(i32), vp, vp]
         L.dpps_ray_search.argtypes = [vp, i32, vp, vp, vp, C.POINTER(RayParams_C),
                                       C.POINTER(RayOutputs_C), vp]
         L.dpps_shot_decision.argtypes = [vp, i32, vp, vp, vp, C.POINTER(ShotParams_C), vp, vp,
@@ -711,20 +711,24 @@ class Mlp:
         return best, int(nfb.value)
 
     def search_frames(self, frames, k: int = 64, fallback: bool = True, best=None, stream=None,
-                      fallback_below: float = float("-inf")):
+                      fallback_below: float = float("-inf"), host=None):
         """Surrogate search of host frames (a Packed request or framegen
         frames) through the context's own staging; same results as search()
-        on a batch of the same frames."""
+        on a batch of the same frames.  With `host` (a numpy BEST_DT array of
+        at least n_frames records) the records are also written there and
+        the call returns when they are final."""
         import torch
         pk = frames if isinstance(frames, Packed) else pack(frames, self.s.params)
         nf = len(pk.frames)
         if best is None:
             best = torch.empty(nf * BEST_DT.itemsize, dtype=torch.uint8, device=self.s.device)
+        if host is not None:
+            assert host.dtype == BEST_DT and host.size >= nf and host.flags["C_CONTIGUOUS"]
         nfb = C.c_int32()
         _check(lib().dpps_surrogate_search_frames(
             self.s.h, self.h, nf, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
             _ptr(pk.variants), k, best.data_ptr(), int(fallback), float(fallback_below),
-            C.byref(nfb), _stream_ptr(stream)))
+            C.byref(nfb), host.ctypes.data if host is not None else None, _stream_ptr(stream)))
         return best, int(nfb.value)
 
 

@@ -486,19 +486,14 @@ int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, vo
     return DPPS_OK;
 }
 
-int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
-                          int fallback, float fallback_below, int32_t *n_fallback,
-                          void *hip_stream)
+}  // extern "C"
+
+// Forward pass, top-k cells, re-score tables and the exact re-score of the
+// proposed windows (kernel launches only), best records into res.
+static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *res,
+                   hipStream_t st)
 {
-    if (!c || !m || !b || !d_best) return fail(DPPS_E_INVALID, "NULL argument");
-    if (fallback_below != fallback_below) return fail(DPPS_E_INVALID, "fallback_below is NaN");
-    if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
-    if (k < 1 || k > m->k_cap) return fail(DPPS_E_INVALID, "k must be in [1, %d]", m->k_cap);
-    HIP_OK(hipSetDevice(c->device));
-    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
     const int nf = b->n_frames;
-    if (n_fallback) *n_fallback = 0;
-    if (nf == 0) return DPPS_OK;
     int rc = forward(m, b, st);
     if (rc) return rc;
     if (launch_topk(m->y, OUT_PAD, nf, OUT, k, m->cells, (void *)st) ||
@@ -521,17 +516,48 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     a.persistent = 1;
     a.counter = m->rcounter;
     a.tile_rec = m->rrec;
-    a.best = d_best;
+    a.best = res;
     int per_cu = search_occupancy(c->p.n_samples, c->waves);
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (launch_search(a, c->waves, grid, (void *)st, nullptr, nullptr))
         return fail(DPPS_E_DEVICE, "re-score launch failed");
-    if (!fallback) return DPPS_OK;
+    return DPPS_OK;
+}
+
+// The surrogate search of a staged batch; with h_best the records also go to
+// host memory and the call returns after the stream has finished them.
+static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
+                          int fallback, float fallback_below, int32_t *n_fallback,
+                          dpps_best *h_best, void *hip_stream)
+{
+    if (!c || !m || !b || !d_best) return fail(DPPS_E_INVALID, "NULL argument");
+    if (fallback_below != fallback_below) return fail(DPPS_E_INVALID, "fallback_below is NaN");
+    if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
+    if (k < 1 || k > m->k_cap) return fail(DPPS_E_INVALID, "k must be in [1, %d]", m->k_cap);
+    HIP_OK(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    const int nf = b->n_frames;
+    if (n_fallback) *n_fallback = 0;
+    if (nf == 0) return DPPS_OK;
+    int rc = propose(c, m, b, k, d_best, st);
+    if (rc) return rc;
+    if (!fallback) {
+        if (h_best) {
+            HIP_OK(hipMemcpyAsync(h_best, d_best, nf * sizeof(dpps_best), hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+        }
+        return DPPS_OK;
+    }
     // frames whose proposals are all infeasible: exact search of the full
     // fine lattice (the frame's own variants)
-    std::vector<dpps_best> hb(nf);
-    HIP_OK(hipMemcpyAsync(hb.data(), d_best, nf * sizeof(dpps_best), hipMemcpyDeviceToHost, st));
+    std::vector<dpps_best> own;
+    dpps_best *hb = h_best;
+    if (!hb) {
+        own.resize(nf);
+        hb = own.data();
+    }
+    HIP_OK(hipMemcpyAsync(hb, d_best, nf * sizeof(dpps_best), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     std::vector<int> redo;
     for (int f = 0; f < nf; ++f)
@@ -572,18 +598,32 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     memset(&o, 0, sizeof o);
     rc = run_batch(c, fb, &o, st, false);
     if (rc) return rc;
-    for (size_t i = 0; i < redo.size(); ++i)
+    for (size_t i = 0; i < redo.size(); ++i) {
         HIP_OK(hipMemcpyAsync(d_best + redo[i], fb->d_best + i, sizeof(dpps_best),
                               hipMemcpyDeviceToDevice, st));
+        if (h_best)
+            HIP_OK(hipMemcpyAsync(h_best + redo[i], fb->d_best + i, sizeof(dpps_best),
+                                  hipMemcpyDeviceToHost, st));
+    }
     HIP_OK(hipStreamSynchronize(st));
     return DPPS_OK;
+}
+
+extern "C" {
+
+int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
+                          int fallback, float fallback_below, int32_t *n_fallback,
+                          void *hip_stream)
+{
+    return surrogate_core(c, m, b, k, d_best, fallback, fallback_below, n_fallback, nullptr,
+                          hip_stream);
 }
 
 int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
                                  const dpps_frame *frames, const dpps_robot *robots,
                                  const dpps_window *windows, const dpps_variant *variants,
                                  int32_t k, dpps_best *d_best, int fallback, float fallback_below,
-                                 int32_t *n_fallback, void *hip_stream)
+                                 int32_t *n_fallback, dpps_best *h_best, void *hip_stream)
 {
     if (!c || !m) return fail(DPPS_E_INVALID, "NULL argument");
     if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
@@ -591,8 +631,8 @@ int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
     int rc = stage_batch(c, &c->scratch, n_frames, frames, robots, windows, variants, st);
     if (rc) return rc;
-    return dpps_surrogate_search(c, m, &c->scratch, k, d_best, fallback, fallback_below,
-                                 n_fallback, hip_stream);
+    return surrogate_core(c, m, &c->scratch, k, d_best, fallback, fallback_below, n_fallback,
+                          h_best, hip_stream);
 }
 
 }  // extern "C"

@@ -436,92 +436,151 @@ __global__ void cast_kernel(const float *__restrict__ w, int64_t n, uint16_t *__
     }
 }
 
-// Feature vector of a frame (one thread per frame): teammates with the passer
+// Feature vector of a frame (one wave per row): teammates with the passer
 // first and the rest by distance to the ball, zero-padded to 8 slots; then
 // the opponents by distance to the ball in slots 8-15; then the ball.
 // Positions are divided by the field's half length / half width, velocities
 // by 3.25 m/s.  Columns 66..in_pad-1 are zero; rows >= n_frames are zero.
-__global__ void featurize_kernel(const FrameDev *__restrict__ frames,
-                                 const dpps_robot *__restrict__ robots, int n_frames,
-                                 int rows_pad, int in_pad, float inv_hl, float inv_hw, float inv_v,
-                                 uint16_t *__restrict__ x)
+// Lanes 0-15 rank the team, lanes 16-31 the opponents (ties to the lower
+// robot index); the slot table goes through LDS; each lane then writes
+// columns l and l + 64 of the row.
+__global__ void __launch_bounds__(64) featurize_kernel(const FrameDev *__restrict__ frames,
+                                                       const dpps_robot *__restrict__ robots,
+                                                       int n_frames, int rows_pad, int in_pad,
+                                                       float inv_hl, float inv_hw, float inv_v,
+                                                       uint16_t *__restrict__ x)
 {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int slot_robot[16];
+    const int f = blockIdx.x;
+    const int l = threadIdx.x;
     if (f >= rows_pad) return;
     uint16_t *row = x + (size_t)f * in_pad;
-    for (int c = 0; c < in_pad; ++c) row[c] = 0;
-    if (f >= n_frames) return;
-    const FrameDev F = frames[f];
-    const float bx = F.ball_x, by = F.ball_y;
-    for (int side = 0; side < 2; ++side) {
-        const int base = side == 0 ? 0 : F.n_team;
+    const bool real = f < n_frames;
+    FrameDev F;
+    if (real) F = frames[f];
+    if (l < 16) slot_robot[l] = -1;
+    __syncthreads();
+    if (real) {
+        const int side = l >> 4, r = l & 15;
         const int cnt = side == 0 ? F.n_team : F.n_opp;
-        int order[DPPS_MAX_SIDE];
-        float key[DPPS_MAX_SIDE];
-        int n = 0;
-        for (int r = 0; r < cnt && r < DPPS_MAX_SIDE; ++r) {
+        const int base = side == 0 ? 0 : F.n_team;
+        const bool have = l < 32 && r < cnt;
+        float key = INFINITY;
+        if (have) {
             const dpps_robot R = robots[F.robot_off + base + r];
-            float dx = R.x - bx, dy = R.y - by;
-            float k = dx * dx + dy * dy;
-            if (side == 0 && r == F.passer) k = -1.0f;
-            int j = n++;
-            while (j > 0 && (key[j - 1] > k || (key[j - 1] == k && order[j - 1] > r))) {
-                key[j] = key[j - 1];
-                order[j] = order[j - 1];
-                --j;
-            }
-            key[j] = k;
-            order[j] = r;
+            const float dx = R.x - F.ball_x, dy = R.y - F.ball_y;
+            key = (side == 0 && r == F.passer) ? -1.0f : dx * dx + dy * dy;
         }
-        for (int s = 0; s < n && s < 8; ++s) {
-            const dpps_robot R = robots[F.robot_off + base + order[s]];
-            uint16_t *o = row + (side * 8 + s) * 4;
-            o[0] = f2bf(R.x * inv_hl);
-            o[1] = f2bf(R.y * inv_hw);
-            o[2] = f2bf(R.vx * inv_v);
-            o[3] = f2bf(R.vy * inv_v);
+        int rank = 0;
+        for (int j = 0; j < 16; ++j) {
+            const float kj = __shfl(key, (l & 48) | j, 64);
+            rank += (kj < key || (kj == key && j < r)) ? 1 : 0;
         }
-    }
-    row[64] = f2bf(bx * inv_hl);
-    row[65] = f2bf(by * inv_hw);
-}
-
-// Top-k cells of each frame's predicted map (one block per frame): sort
-// (score, index) keys descending with a bitonic network in LDS; ties go to
-// the lower index.  Keys of cells >= n_cells sort last.
-__global__ void __launch_bounds__(256) topk_kernel(const float *__restrict__ y, int ldy,
-                                                   int n_cells, int k, int32_t *__restrict__ out)
-{
-    __shared__ unsigned long long key[TOPK_SORT];
-    const int f = blockIdx.x;
-    for (int i = threadIdx.x; i < TOPK_SORT; i += blockDim.x) {
-        unsigned long long kk = 0ull;
-        if (i < n_cells) {
-            uint32_t u = __float_as_uint(y[(size_t)f * ldy + i]);
-            u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);  // order-preserving
-            kk = ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-        }
-        key[i] = kk;
+        if (have && rank < 8) slot_robot[side * 8 + rank] = base + r;
     }
     __syncthreads();
-    for (int size = 2; size <= TOPK_SORT; size <<= 1) {
+    for (int c = l; c < in_pad; c += 64) {
+        float v = 0.0f;
+        if (real && c < 64) {
+            const int rb = slot_robot[c >> 2];
+            if (rb >= 0) {
+                const dpps_robot R = robots[F.robot_off + rb];
+                const int comp = c & 3;
+                v = comp == 0 ? R.x * inv_hl : comp == 1 ? R.y * inv_hw
+                                             : comp == 2 ? R.vx * inv_v : R.vy * inv_v;
+            }
+        } else if (real && c == 64) {
+            v = F.ball_x * inv_hl;
+        } else if (real && c == 65) {
+            v = F.ball_y * inv_hw;
+        }
+        row[c] = f2bf(v);
+    }
+}
+
+// Top-k cells of each frame's predicted map (one wave per frame), ordered by
+// (score, index) descending with ties to the lower index.  The cells' keys
+// (order-preserving score bits) stay in registers (lane l holds cells
+// l, l + 64, ...); a binary search over the 32 key bits finds the k-th
+// largest key T (the largest T with at least k keys >= T); the cells above T
+// and the lowest-index cells at T are gathered in LDS and sorted by a
+// bitonic network there.
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(64) topk_kernel(const float *__restrict__ y, int ldy,
+                                                  int n_cells, int k, int32_t *__restrict__ out)
+{
+    constexpr int PER = TOPK_SORT / 64;
+    __shared__ unsigned long long buf[TOPK_MAX];
+    const int f = blockIdx.x;
+    const int l = threadIdx.x;
+    const int per = (n_cells + 63) >> 6;
+    uint32_t u[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * 64 + l;
+        uint32_t b = 0u;
+        if (j < per && i < n_cells) {
+            b = __float_as_uint(y[(size_t)f * ldy + i]);
+            b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        }
+        u[j] = b;
+    }
+    uint32_t T = 0u;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = T | (1u << bit);
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) c += (j < per && u[j] >= cand) ? 1 : 0;
+        if (wave_sum_i(c) >= k) T = cand;
+    }
+    int greater = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) greater += (j < per && u[j] > T) ? 1 : 0;
+    const int need = k - wave_sum_i(greater);
+    const unsigned long long below = (1ull << l) - 1ull;
+    int base = 0, ties = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (j < per) {  // uniform
+            const int i = j * 64 + l;
+            const bool eq = i < n_cells && u[j] == T;
+            const unsigned long long em = __ballot(eq);
+            const bool sel = u[j] > T || (eq && ties + __popcll(em & below) < need);
+            ties += __popcll(em);
+            const unsigned long long sm = __ballot(sel);
+            if (sel)
+                buf[base + __popcll(sm & below)] = ((unsigned long long)u[j] << 32) |
+                                                   (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+            base += __popcll(sm);
+        }
+    }
+    int P = 1;
+    while (P < k) P <<= 1;
+    for (int i = k + l; i < P; i += 64) buf[i] = 0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < TOPK_SORT; i += blockDim.x) {
-                int j = i ^ stride;
+            for (int i = l; i < P; i += 64) {
+                const int j = i ^ stride;
                 if (j > i) {
-                    bool desc = (i & size) == 0;
-                    unsigned long long a = key[i], b = key[j];
+                    const bool desc = (i & size) == 0;
+                    const unsigned long long a = buf[i], b = buf[j];
                     if (desc ? (a < b) : (a > b)) {
-                        key[i] = b;
-                        key[j] = a;
+                        buf[i] = b;
+                        buf[j] = a;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < k; i += blockDim.x)
-        out[(size_t)f * k + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)key[i]);
+    for (int i = l; i < k; i += 64) out[(size_t)f * k + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)buf[i]);
 }
 
 // Re-score tables for the top-k cells (one block per frame): each coarse
@@ -641,15 +700,16 @@ int launch_cast(const float *w, int64_t n, uint16_t *wb, uint16_t *wbt, int rows
 int launch_featurize(const FrameDev *frames, const dpps_robot *robots, int n_frames, int rows_pad,
                      int in_pad, float inv_hl, float inv_hw, float inv_v, uint16_t *x, void *st)
 {
-    hipLaunchKernelGGL(featurize_kernel, dim3((rows_pad + 63) / 64), dim3(64), 0, (hipStream_t)st,
-                       frames, robots, n_frames, rows_pad, in_pad, inv_hl, inv_hw, inv_v, x);
+    if (rows_pad == 0) return 0;
+    hipLaunchKernelGGL(featurize_kernel, dim3(rows_pad), dim3(64), 0, (hipStream_t)st, frames,
+                       robots, n_frames, rows_pad, in_pad, inv_hl, inv_hw, inv_v, x);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out, void *st)
 {
     if (n_cells > TOPK_SORT || k > n_cells || k > TOPK_MAX) return -1;
-    hipLaunchKernelGGL(topk_kernel, dim3(n_frames), dim3(256), 0, (hipStream_t)st, y, ldy, n_cells,
+    hipLaunchKernelGGL(topk_kernel, dim3(n_frames), dim3(64), 0, (hipStream_t)st, y, ldy, n_cells,
                        k, out);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -186,14 +186,39 @@ def test_surrogate_search_of_host_frames_equals_batch_search(B):
     net = B.Mlp(s, 16, seed=5)
     for n, base, fb in ((12, 700, True), (5, 900, False), (9, 1100, True)):
         frames = _frames(n, base)
-        got_t, nfb_a = net.search_frames(frames, k=64, fallback=fb)
+        host = np.zeros(n, B.BEST_DT)
+        got_t, nfb_a = net.search_frames(frames, k=64, fallback=fb, host=host)
         got = B.best_records(got_t).copy()
+        # the records returned in host memory are the device ones
+        assert host.tobytes() == got.tobytes()
         bt = s.batch(frames)
         ref_t, nfb_b = net.search(bt, k=64, fallback=fb)
         ref = B.best_records(ref_t)
         bt.close()
         assert nfb_a == nfb_b
         assert got.tobytes() == ref.tobytes()
+    net.close(); s.close()
+
+
+def test_single_frames_through_staging_match_batch_search(B):
+    # one frame per call through the context's staging, alternating fallback,
+    # each against the batch search of the same frame
+    s = B.Searcher(P)
+    net = B.Mlp(s, 16, seed=7)
+    host = np.zeros(1, B.BEST_DT)
+    for rep, f in enumerate(_frames(6, 1300)):
+        fb = rep % 2 == 0
+        got_t, nfb_a = net.search_frames([f], k=64, fallback=fb, host=host)
+        torch.cuda.synchronize()
+        got = B.best_records(got_t).copy()
+        assert host.tobytes() == got.tobytes()
+        bt = s.batch([f])
+        ref_t, nfb_b = net.search(bt, k=64, fallback=fb)
+        torch.cuda.synchronize()
+        ref = B.best_records(ref_t)
+        bt.close()
+        assert nfb_a == nfb_b, rep
+        assert got.tobytes() == ref.tobytes(), rep
     net.close(); s.close()
 
 
