@@ -435,7 +435,7 @@ def main() -> int:
     bt = s.batch([frame])
     out = s.outputs_for(bt.pk)
     # launch shape (tile size, waves, persistent grid) from the autotuner, cached
-    tuned = bt.autotune(out, args.tune_cache, reps=3, stream=st)
+    tuned = bt.autotune(out, args.tune_cache, reps=10, stream=st)
     shape = s.get_launch()
     progress(f"launch shape {shape} ({'tuned' if tuned >= 0 else 'cached'})")
     with torch.cuda.stream(st):

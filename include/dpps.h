@@ -183,7 +183,8 @@ int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_
                     int32_t *wg_per_cu);
 
 /* Autotuner: time every launch shape (tile points 8/16/32/64 x waves 1/2/4/8
- * x persistent / one workgroup per tile) on batch b with `reps` timed runs
+ * x {persistent at occupancy, persistent with 2 or 4 workgroups per CU, one
+ * workgroup per tile}) on batch b with `reps` timed runs
  * each, keep the fastest on the context and re-tile b for it.  With
  * cache_path, a previous result for the same class (architecture, K, largest
  * variant and interceptor counts, log2 points per frame, log2 frames, output

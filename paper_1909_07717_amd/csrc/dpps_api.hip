@@ -932,7 +932,8 @@ static std::string tune_key(const dpps_ctx *c, const dpps_batch *b)
     for (int64_t x = pts / nf; x > 1; x >>= 1) ++lp;
     for (int x = nf; x > 1; x >>= 1) ++lf;
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|rev%s|K%d|V%d|R%d|P2^%d|F2^%d|%s", arch.c_str(), DPPS_KERNEL_REV,
+    // t2: the candidate set with explicit persistent grids
+    snprintf(buf, sizeof buf, "%s|rev%s|t2|K%d|V%d|R%d|P2^%d|F2^%d|%s", arch.c_str(), DPPS_KERNEL_REV,
              c->p.n_samples, vmax, rmax, lp, lf,
              (c->p.out_flags & DPPS_OUT_REDUCED) ? "reduced" : "full");
     return buf;
@@ -982,7 +983,10 @@ int dpps_autotune(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip
     }
     const int tps[] = {8, 16, 32, 64};
     const int wvs[] = {1, 2, 4, 8};
-    const int pcs[] = {-2, -1};
+    // persistent with the occupancy grid, one workgroup per tile, and
+    // persistent grids of 2 and 4 workgroups per CU (a grid larger than what
+    // fits waits for free slots, which can balance better)
+    const int pcs[] = {-2, -1, 2, 4};
     float best = 1e30f;
     int btp = c->tile_points, bwv = c->waves, bpc = c->persistent ? (c->wg_per_cu ? c->wg_per_cu : -2) : -1;
     for (int t : tps) {
