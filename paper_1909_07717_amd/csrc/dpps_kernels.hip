@@ -216,7 +216,16 @@ template <int KPL, bool CLAMP>
 __device__ __forceinline__ void robot_stage(const float4 *pr, const DevParams &P, int j0, int n,
                                             const float (&fs)[KPL], float LA, float (&T)[KPL])
 {
-    for (int j = j0; j < j0 + n; ++j) {
+    // robots in pairs: two independent chains, joined by a three-way minimum
+    int j = j0;
+    for (; j + 1 < j0 + n; j += 2) {
+        const float4 ra = pr[j], rb = pr[j + 1];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q)
+            T[q] = fminf(T[q], fminf(robot_time_h<CLAMP>(ra, fs[q], LA, P),
+                                     robot_time_h<CLAMP>(rb, fs[q], LA, P)));
+    }
+    if (j < j0 + n) {
         const float4 r = pr[j];
 #pragma unroll
         for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_h<CLAMP>(r, fs[q], LA, P));
