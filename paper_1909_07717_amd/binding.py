@@ -389,10 +389,15 @@ class Searcher:
     def outputs_for(self, pk: Packed, mask=True, score=True, times=False) -> DeviceOutputs:
         return DeviceOutputs(pk.total, len(pk.frames), self.device, mask, score, times)
 
-    def search(self, frame, mask=True, score=True, times=False):
-        """One frame, synchronous.  Returns (DeviceOutputs, best record)."""
-        pk = pack([frame], self.params, self.out_flags)
-        out = self.outputs_for(pk, mask, score, times)
+    def search(self, frame, mask=True, score=True, times=False, out=None):
+        """One frame (a framegen frame or a one-frame Packed request),
+        synchronous.  Returns (DeviceOutputs, best record); `out` reuses the
+        DeviceOutputs of an earlier call of the same size."""
+        pk = frame if isinstance(frame, Packed) else pack([frame], self.params, self.out_flags)
+        if len(pk.frames) != 1:
+            raise ValueError("search() takes one frame")
+        if out is None:
+            out = self.outputs_for(pk, mask, score, times)
         oc = out.c()
         best = np.zeros(1, BEST_DT)
         _check(lib().dpps_search(self.h, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),

@@ -225,7 +225,8 @@ int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frame
             if (elem >= 0x7FFFFFFF)
                 return fail(DPPS_E_UNSUPPORTED, "frame %d: more than 2^31 output elements", f);
             int32_t widx = (int32_t)T.wins.size();
-            for (int32_t p0 = 0; p0 < W.npts; p0 += tile_points) T.tiles.push_back({widx, p0});
+            if (tile_points > 0)
+                for (int32_t p0 = 0; p0 < W.npts; p0 += tile_points) T.tiles.push_back({widx, p0});
             T.points += W.npts;
             T.wins.push_back(W);
         }
@@ -490,6 +491,7 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
         c->own_stream = true;
     }
     if (hipEventCreateWithFlags(&c->staged, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->landed, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         dpps_destroy(c);
         return fail(DPPS_E_DEVICE, "hipEventCreate failed");
@@ -520,7 +522,9 @@ void dpps_destroy(dpps_ctx *c)
     batch_free_device(&c->runs);
     if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->pinned_best) (void)hipHostFree(c->pinned_best);
     if (c->staged) (void)hipEventDestroy(c->staged);
+    if (c->landed) (void)hipEventDestroy(c->landed);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -607,6 +611,31 @@ int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *
     b->n_frames = n_frames;
     b->tile_points = c->tile_points;
     return stage_tables(c, b, st);
+}
+
+int read_best(dpps_ctx *c, dpps_best *h, const dpps_best *d, int n, hipStream_t st)
+{
+    if (n <= 0) return DPPS_OK;
+    if (n > c->pinned_best_cap) {
+        // the previous read has completed (every read waits for its copy)
+        if (c->pinned_best) HIP_OK(hipHostFree(c->pinned_best));
+        c->pinned_best = nullptr;
+        c->pinned_best_cap = 0;
+        const int64_t want = n < 64 ? 64 : n;
+        if (hipHostMalloc((void **)&c->pinned_best, (size_t)want * sizeof(dpps_best),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(DPPS_E_NOMEM, "hipHostMalloc of %lld best records failed", (long long)want);
+        c->pinned_best_cap = want;
+    }
+    HIP_OK(hipMemcpyAsync(c->pinned_best, d, (size_t)n * sizeof(dpps_best), hipMemcpyDeviceToHost,
+                          st));
+    HIP_OK(hipEventRecord(c->landed, st));
+    hipError_t e;
+    while ((e = hipEventQuery(c->landed)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) return fail(DPPS_E_DEVICE, "waiting for the best records: %s", hipGetErrorString(e));
+    memcpy(h, c->pinned_best, (size_t)n * sizeof(dpps_best));
+    return DPPS_OK;
 }
 
 // Copy the host tables already in b->T to the batch's device memory through
@@ -871,10 +900,7 @@ int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,
     o.best = nullptr;
     int rc = dpps_search_batch(c, 1, frame, robots, windows, variants, &o, c->stream);
     if (rc) return rc;
-    HIP_OK(hipMemcpyAsync(h_best, c->scratch.d_best, sizeof(dpps_best), hipMemcpyDeviceToHost,
-                          c->stream));
-    HIP_OK(hipStreamSynchronize(c->stream));
-    return DPPS_OK;
+    return read_best(c, h_best, c->scratch.d_best, 1, c->stream);
 }
 
 int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,

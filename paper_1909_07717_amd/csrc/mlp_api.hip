@@ -104,9 +104,16 @@ static int params_xfer(dpps_mlp *m, float *const *dw, float *const *db, float *h
     return DPPS_OK;
 }
 
-static int forward(dpps_mlp *m, const dpps_batch *bt, hipStream_t st)
+// Batches of at most SMALL_ROWS frames are run, for inference, by the few-row
+// GEMM over the frames' rows rounded up to 16 (identical results, one wave
+// per output tile instead of a handful of 64 x 64 tiles); training needs
+// every padded row and uses the tiled GEMM.
+constexpr int SMALL_ROWS = 64;
+
+static int forward(dpps_mlp *m, const dpps_batch *bt, hipStream_t st, bool training)
 {
     const int nf = bt->n_frames, R = rows_pad(nf);
+    const bool small = !training && nf >= 1 && nf <= SMALL_ROWS;
     if (nf > m->rows_cap) return fail(DPPS_E_INVALID, "batch of %d frames exceeds the network's %d",
                                       nf, m->rows_cap);
     const dpps_params &p = m->ctx->p;
@@ -121,7 +128,7 @@ static int forward(dpps_mlp *m, const dpps_batch *bt, hipStream_t st)
         g.lda = IN_DIM[l];
         g.B = m->wb[l];
         g.ldb = IN_DIM[l];
-        g.M = R;
+        g.M = small ? (nf + 15) / 16 * 16 : R;
         g.N = OUT_DIM[l];
         g.K = IN_DIM[l];
         g.ldc = OUT_DIM[l];
@@ -136,7 +143,8 @@ static int forward(dpps_mlp *m, const dpps_batch *bt, hipStream_t st)
             g.Cf = m->y;
             epi = EPI_BIAS;
         }
-        if (gemm(g, true, true, epi, (void *)st)) return fail(DPPS_E_DEVICE, "gemm launch failed");
+        if (small ? gemm_rows(g, epi, (void *)st) : gemm(g, true, true, epi, (void *)st))
+            return fail(DPPS_E_DEVICE, "gemm launch failed");
     }
     return DPPS_OK;
 }
@@ -390,7 +398,7 @@ int dpps_mlp_forward(dpps_mlp *m, dpps_batch *b, float *d_out, int64_t ld_out, v
     if (d_out && ld_out < OUT) return fail(DPPS_E_INVALID, "ld_out must be >= %d", OUT);
     HIP_OK(hipSetDevice(m->ctx->device));
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : m->ctx->stream;
-    int rc = forward(m, b, st);
+    int rc = forward(m, b, st, false);
     if (rc) return rc;
     if (d_out && b->n_frames > 0)
         HIP_OK(hipMemcpy2DAsync(d_out, (size_t)ld_out * 4, m->y, (size_t)OUT_PAD * 4, (size_t)OUT * 4,
@@ -409,7 +417,7 @@ int dpps_mlp_loss_grad(dpps_mlp *m, dpps_batch *b, const float *d_target, int64_
     if (ld_target < OUT) return fail(DPPS_E_INVALID, "ld_target must be >= %d", OUT);
     HIP_OK(hipSetDevice(m->ctx->device));
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : m->ctx->stream;
-    int rc = forward(m, b, st);
+    int rc = forward(m, b, st, true);
     if (rc) return rc;
     rc = backward_loss(m, b->n_frames, d_target, ld_target, LossCfg{pos_weight, ce_weight, tau}, st);
     if (rc) return rc;
@@ -481,7 +489,7 @@ int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, vo
     if (k < 1 || k > m->k_cap || n_frames < 0 || n_frames > m->rows_cap)
         return fail(DPPS_E_INVALID, "bad top-k request");
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : m->ctx->stream;
-    if (n_frames > 0 && launch_topk(m->y, OUT_PAD, n_frames, OUT, k, d_cells, (void *)st))
+    if (n_frames > 0 && launch_topk(m->y, OUT_PAD, n_frames, OUT, k, d_cells, nullptr, (void *)st))
         return fail(DPPS_E_DEVICE, "top-k launch failed");
     return DPPS_OK;
 }
@@ -494,12 +502,20 @@ static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best
                    hipStream_t st)
 {
     const int nf = b->n_frames;
-    int rc = forward(m, b, st);
+    int rc = forward(m, b, st, false);
     if (rc) return rc;
-    if (launch_topk(m->y, OUT_PAD, nf, OUT, k, m->cells, (void *)st) ||
-        launch_rescore_tables(b->d_frames, nf, m->cells, k, m->coarse_nx, m->fine_nx, m->fine_ny,
-                              (float)FINE_H, m->rf, m->rw, m->rt, (void *)st))
-        return fail(DPPS_E_DEVICE, "top-k / table launch failed");
+    // top-k cells and, in the same kernel, their re-score tables
+    RescoreTables rt;
+    rt.src = b->d_frames;
+    rt.coarse_nx = m->coarse_nx;
+    rt.fine_nx = m->fine_nx;
+    rt.fine_ny = m->fine_ny;
+    rt.fine_h = (float)FINE_H;
+    rt.frames = m->rf;
+    rt.wins = m->rw;
+    rt.tiles = m->rt;
+    if (launch_topk(m->y, OUT_PAD, nf, OUT, k, m->cells, &rt, (void *)st))
+        return fail(DPPS_E_DEVICE, "top-k launch failed");
     // exact re-score of the proposed windows: one 16-point tile per window
     LaunchArgs a;
     memset(&a, 0, sizeof a);
@@ -517,10 +533,13 @@ static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best
     a.counter = m->rcounter;
     a.tile_rec = m->rrec;
     a.best = res;
-    int per_cu = search_occupancy(c->p.n_samples, c->waves);
+    // few windows (small batches): eight waves share each window's 16
+    // points, two points per wave, instead of the context's shape
+    const int wv = (int64_t)a.n_tiles <= (int64_t)c->n_cu ? 8 : c->waves;
+    int per_cu = search_occupancy(c->p.n_samples, wv);
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
-    if (launch_search(a, c->waves, grid, (void *)st, nullptr, nullptr))
+    if (launch_search(a, wv, grid, (void *)st, nullptr, nullptr))
         return fail(DPPS_E_DEVICE, "re-score launch failed");
     return DPPS_OK;
 }
@@ -542,13 +561,7 @@ static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     if (nf == 0) return DPPS_OK;
     int rc = propose(c, m, b, k, d_best, st);
     if (rc) return rc;
-    if (!fallback) {
-        if (h_best) {
-            HIP_OK(hipMemcpyAsync(h_best, d_best, nf * sizeof(dpps_best), hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
-        }
-        return DPPS_OK;
-    }
+    if (!fallback) return h_best ? read_best(c, h_best, d_best, nf, st) : DPPS_OK;
     // frames whose proposals are all infeasible: exact search of the full
     // fine lattice (the frame's own variants)
     std::vector<dpps_best> own;
@@ -557,8 +570,8 @@ static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
         own.resize(nf);
         hb = own.data();
     }
-    HIP_OK(hipMemcpyAsync(hb, d_best, nf * sizeof(dpps_best), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    rc = read_best(c, hb, d_best, nf, st);
+    if (rc) return rc;
     std::vector<int> redo;
     for (int f = 0; f < nf; ++f)
         if (!hb[f].found || hb[f].score < fallback_below) redo.push_back(f);
@@ -598,13 +611,10 @@ static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     memset(&o, 0, sizeof o);
     rc = run_batch(c, fb, &o, st, false);
     if (rc) return rc;
-    for (size_t i = 0; i < redo.size(); ++i) {
+    for (size_t i = 0; i < redo.size(); ++i)
         HIP_OK(hipMemcpyAsync(d_best + redo[i], fb->d_best + i, sizeof(dpps_best),
                               hipMemcpyDeviceToDevice, st));
-        if (h_best)
-            HIP_OK(hipMemcpyAsync(h_best + redo[i], fb->d_best + i, sizeof(dpps_best),
-                                  hipMemcpyDeviceToHost, st));
-    }
+    if (h_best) return read_best(c, h_best, d_best, nf, st);
     HIP_OK(hipStreamSynchronize(st));
     return DPPS_OK;
 }
@@ -629,10 +639,16 @@ int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
     if (m->ctx != c) return fail(DPPS_E_INVALID, "network belongs to another context");
     HIP_OK(hipSetDevice(c->device));
     hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
-    int rc = stage_batch(c, &c->scratch, n_frames, frames, robots, windows, variants, st);
+    // the windows are validated but not searched: tables without tiles
+    dpps_batch *b = &c->scratch;
+    int rc = build_tables(&c->p, n_frames, frames, robots, windows, variants, 0, b->T);
     if (rc) return rc;
-    return surrogate_core(c, m, &c->scratch, k, d_best, fallback, fallback_below, n_fallback,
-                          h_best, hip_stream);
+    b->n_frames = n_frames;
+    b->tile_points = c->tile_points;
+    rc = stage_tables(c, b, st);
+    if (rc) return rc;
+    return surrogate_core(c, m, b, k, d_best, fallback, fallback_below, n_fallback, h_best,
+                          hip_stream);
 }
 
 }  // extern "C"

@@ -27,6 +27,9 @@ struct GemmArgs {
 };
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream);
+// Inference GEMM of a few rows (A, B k-contiguous; EPI_BIAS or EPI_BIAS_GELU),
+// bit-identical per element to gemm(g, true, true, epi, stream).
+int gemm_rows(const GemmArgs &g, int epi, void *stream);
 // Column sums (bias gradients); part holds colsum_chunks(M) x N floats.
 int launch_colsum(const uint16_t *dz, int M, int N, int ld, float *db, float *part, void *st);
 int colsum_chunks(int M);
@@ -41,9 +44,19 @@ int launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float l
 int launch_cast(const float *w, int64_t n, uint16_t *wb, uint16_t *wbt, int rows, int cols, void *st);
 int launch_featurize(const FrameDev *frames, const dpps_robot *robots, int n_frames, int rows_pad,
                      int in_pad, float inv_hl, float inv_hw, float inv_v, uint16_t *x, void *st);
-int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out, void *st);
-int launch_rescore_tables(const FrameDev *src, int n_frames, const int32_t *cells, int k,
-                          int coarse_nx, int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
-                          WinDev *wins, TileDev *tiles, void *st);
+// Re-score tables written by the top-k kernel: per frame f, its copy
+// frames[f] (n_windows = tile_count = k), k windows and k tiles.
+struct RescoreTables {
+    const FrameDev *src;
+    int coarse_nx, fine_nx, fine_ny;
+    float fine_h;
+    FrameDev *frames;
+    WinDev *wins;
+    TileDev *tiles;
+};
+// Top-k cells of each frame's map into out [n_frames][k]; with rt, also the
+// re-score tables of those cells.
+int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out,
+                const RescoreTables *rt, void *st);
 
 }  // namespace dpps

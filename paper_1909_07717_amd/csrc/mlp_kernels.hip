@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "mlp_internal.h"
 
@@ -227,6 +228,71 @@ static void launch_shape(GemmArgs g, hipStream_t st)
         launch_gemm<128, 128, A_K, B_K, EPI>(g, 1, st);
     else
         launch_gemm<64, 64, A_K, B_K, EPI>(g, 1, st);
+}
+
+// Few-row GEMM for inference on small batches (A and B k-contiguous): one
+// wave per 16 x 16 output tile, operands loaded straight from global memory,
+// the same v_mfma_f32_16x16x32_bf16 sequence over K (K steps of 32 from 0,
+// zero-filled past K) and the same epilogue as gemm_kernel, so each output
+// element is computed exactly as gemm_kernel computes it.
+#define ROWS_KSTEPS 16   // K <= 512 for the few-row GEMM
+
+template <int EPI>
+__global__ void __launch_bounds__(64) gemm_rows_kernel(GemmArgs g)
+{
+    const int n0 = blockIdx.x * 16, m0 = blockIdx.y * 16;
+    const int l = threadIdx.x;
+    const int fr = l & 15, fk = (l >> 4) * 8;
+    const bool arow = m0 + fr < g.M, brow = n0 + fr < g.N;
+    const uint16_t *pa = g.A + (size_t)(m0 + fr) * g.lda + fk;
+    const uint16_t *pb = g.B + (size_t)(n0 + fr) * g.ldb + fk;
+    // every K step's operands are loaded before the first product
+    uint4 va[ROWS_KSTEPS], vb[ROWS_KSTEPS];
+#pragma unroll
+    for (int s = 0; s < ROWS_KSTEPS; ++s) {
+        const int k0 = s * GK;
+        const bool kin = k0 + fk < g.K;
+        va[s] = make_uint4(0, 0, 0, 0);
+        vb[s] = make_uint4(0, 0, 0, 0);
+        if (arow && kin) va[s] = *(const uint4 *)(pa + k0);
+        if (brow && kin) vb[s] = *(const uint4 *)(pb + k0);
+    }
+    f32x4_t acc = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < ROWS_KSTEPS; ++s)
+        if (s * GK < g.K)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, va[s]),
+                                                          __builtin_bit_cast(bf16x8_t, vb[s]), acc,
+                                                          0, 0, 0);
+    const int n = n0 + (l & 15);
+    if (n >= g.N) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + (l >> 4) * 4 + i;
+        if (m >= g.M) continue;
+        const float v = acc[i];
+        const size_t o = (size_t)m * g.ldc + n;
+        if (EPI == EPI_BIAS_GELU) {
+            const float z = v + g.bias[n];
+            g.Cf[o] = z;
+            g.Cb[o] = f2bf(gelu(z));
+        } else {
+            g.Cf[o] = v + g.bias[n];
+        }
+    }
+}
+
+int gemm_rows(const GemmArgs &g, int epi, void *stream)
+{
+    if ((g.M | g.N | g.K) & 7 || g.M < 1 || g.K > ROWS_KSTEPS * GK) return -1;
+    const dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 15) / 16));
+    if (epi == EPI_BIAS_GELU)
+        hipLaunchKernelGGL(gemm_rows_kernel<EPI_BIAS_GELU>, grid, dim3(64), 0, (hipStream_t)stream, g);
+    else if (epi == EPI_BIAS)
+        hipLaunchKernelGGL(gemm_rows_kernel<EPI_BIAS>, grid, dim3(64), 0, (hipStream_t)stream, g);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int gemm(const GemmArgs &g, bool a_k, bool b_k, int epi, void *stream)
@@ -498,142 +564,72 @@ __global__ void __launch_bounds__(64) featurize_kernel(const FrameDev *__restric
     }
 }
 
-// Top-k cells of each frame's predicted map (one wave per frame), ordered by
-// (score, index) descending with ties to the lower index.  The cells' keys
-// (order-preserving score bits) stay in registers (lane l holds cells
-// l, l + 64, ...); a binary search over the 32 key bits finds the k-th
-// largest key T (the largest T with at least k keys >= T); the cells above T
-// and the lowest-index cells at T are gathered in LDS and sorted by a
-// bitonic network there.
-__device__ __forceinline__ int wave_sum_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// Top-k cells of each frame's predicted map (one 256-thread workgroup per
+// frame), ordered by (score, index) descending with ties to the lower index.
+// The cells' keys (order-preserving score bits) stay in registers (thread t
+// holds cells t, t + 256, ...).  Four radix passes of 8 bits find the k-th
+// largest key T: each pass histograms the digit of the keys that match the
+// digits chosen so far and picks the digit where the count of larger keys
+// reaches k.  All keys above T are taken, and of the keys equal to T the
+// lowest-index ones; the k winners are sorted by a bitonic network in LDS.
+constexpr int TOPK_THREADS = 256;
 
-__global__ void __launch_bounds__(64) topk_kernel(const float *__restrict__ y, int ldy,
-                                                  int n_cells, int k, int32_t *__restrict__ out)
+// Inclusive prefix sum over the 256 threads of a workgroup (sh: 4 ints).
+__device__ __forceinline__ int block_scan_256(int v, int *sh)
 {
-    constexpr int PER = TOPK_SORT / 64;
-    __shared__ unsigned long long buf[TOPK_MAX];
-    const int f = blockIdx.x;
-    const int l = threadIdx.x;
-    const int per = (n_cells + 63) >> 6;
-    uint32_t u[PER];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int i = j * 64 + l;
-        uint32_t b = 0u;
-        if (j < per && i < n_cells) {
-            b = __float_as_uint(y[(size_t)f * ldy + i]);
-            b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-        }
-        u[j] = b;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (l >= o) v += u;
     }
-    uint32_t T = 0u;
-    for (int bit = 31; bit >= 0; --bit) {
-        const uint32_t cand = T | (1u << bit);
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) c += (j < per && u[j] >= cand) ? 1 : 0;
-        if (wave_sum_i(c) >= k) T = cand;
-    }
-    int greater = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) greater += (j < per && u[j] > T) ? 1 : 0;
-    const int need = k - wave_sum_i(greater);
-    const unsigned long long below = (1ull << l) - 1ull;
-    int base = 0, ties = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        if (j < per) {  // uniform
-            const int i = j * 64 + l;
-            const bool eq = i < n_cells && u[j] == T;
-            const unsigned long long em = __ballot(eq);
-            const bool sel = u[j] > T || (eq && ties + __popcll(em & below) < need);
-            ties += __popcll(em);
-            const unsigned long long sm = __ballot(sel);
-            if (sel)
-                buf[base + __popcll(sm & below)] = ((unsigned long long)u[j] << 32) |
-                                                   (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-            base += __popcll(sm);
-        }
-    }
-    int P = 1;
-    while (P < k) P <<= 1;
-    for (int i = k + l; i < P; i += 64) buf[i] = 0ull;
+    if (l == 63) sh[w] = v;
     __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = l; i < P; i += 64) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool desc = (i & size) == 0;
-                    const unsigned long long a = buf[i], b = buf[j];
-                    if (desc ? (a < b) : (a > b)) {
-                        buf[i] = b;
-                        buf[j] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = l; i < k; i += 64) out[(size_t)f * k + i] = (int32_t)(0xFFFFFFFFu - (uint32_t)buf[i]);
+    int add = 0;
+    for (int i = 0; i < w; ++i) add += sh[i];
+    __syncthreads();
+    return v + add;
 }
 
-// Re-score tables for the top-k cells (one block per frame): each coarse
-// cell (ci, cj) of the coarse lattice becomes the window of fine points
-// {4 ci - 2 .. 4 ci + 1} x {4 cj - 2 .. 4 cj + 1} clipped to the fine
-// lattice, one tile per window.
-__global__ void rescore_tables_kernel(const FrameDev *__restrict__ src, int n_frames,
-                                      const int32_t *__restrict__ cells, int k, int coarse_nx,
-                                      int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
-                                      WinDev *wins, TileDev *tiles)
+// Re-score tables of frame f from its top-k cells (the whole workgroup;
+// thread t < k holds cell t): each coarse cell (ci, cj) becomes the window
+// of fine points {4 ci - 2 .. 4 ci + 1} x {4 cj - 2 .. 4 cj + 1} clipped to
+// the fine lattice, one tile per window, and the frame's copy points at
+// its k windows.
+__device__ void rescore_windows(const RescoreTables &rt, int f, int k, int cell, int *scan_sh)
 {
-    __shared__ int npts_s[TOPK_MAX];
-    __shared__ int base_s[TOPK_MAX];
-    const int f = blockIdx.x;
-    if (f >= n_frames) return;
-    const FrameDev F = src[f];
+    const FrameDev F = rt.src[f];
     const int t = threadIdx.x;
     int i0 = 0, j0 = 0, nx = 0, ny = 0;
     if (t < k) {
-        const int c = cells[(size_t)f * k + t];
-        const int ci = c % coarse_nx, cj = c / coarse_nx;
-        int a0 = 4 * ci - 2, a1 = 4 * ci + 1, b0 = 4 * cj - 2, b1 = 4 * cj + 1;
-        a0 = max(a0, 0); b0 = max(b0, 0);
-        a1 = min(a1, fine_nx - 1); b1 = min(b1, fine_ny - 1);
-        i0 = a0; j0 = b0;
+        const int ci = cell % rt.coarse_nx, cj = cell / rt.coarse_nx;
+        const int a0 = max(4 * ci - 2, 0), b0 = max(4 * cj - 2, 0);
+        const int a1 = min(4 * ci + 1, rt.fine_nx - 1), b1 = min(4 * cj + 1, rt.fine_ny - 1);
+        i0 = a0;
+        j0 = b0;
         nx = max(a1 - a0 + 1, 0);
         ny = max(b1 - b0 + 1, 0);
-        npts_s[t] = nx * ny;
     }
-    __syncthreads();
-    if (t == 0) {
-        int e = 0;
-        for (int w = 0; w < k; ++w) {
-            base_s[w] = e;
-            e += npts_s[w] * F.n_variants;
-        }
-    }
-    __syncthreads();
+    // element offsets: windows in rank order, each with all the frame's variants
+    const int incl = block_scan_256(nx * ny, scan_sh);
     if (t < k) {
         WinDev W;
-        W.h = fine_h;
-        W.i0 = i0; W.j0 = j0; W.nx = nx; W.ny = ny;
-        W.halfNx = 0.5f * (float)(fine_nx - 1);
-        W.halfNy = 0.5f * (float)(fine_ny - 1);
+        W.h = rt.fine_h;
+        W.i0 = i0;
+        W.j0 = j0;
+        W.nx = nx;
+        W.ny = ny;
+        W.halfNx = 0.5f * (float)(rt.fine_nx - 1);
+        W.halfNy = 0.5f * (float)(rt.fine_ny - 1);
         W.frame = f;
         W.npts = nx * ny;
-        W.elem_base = base_s[t];
+        W.elem_base = (incl - nx * ny) * F.n_variants;
         W.out_base = 0;
-        wins[(size_t)f * k + t] = W;
+        rt.wins[(size_t)f * k + t] = W;
         TileDev T;
         T.win = f * k + t;
         T.p0 = 0;
-        tiles[(size_t)f * k + t] = T;
+        rt.tiles[(size_t)f * k + t] = T;
     }
     if (t == 0) {
         FrameDev G = F;
@@ -641,8 +637,129 @@ __global__ void rescore_tables_kernel(const FrameDev *__restrict__ src, int n_fr
         G.win_off = f * k;
         G.tile_begin = f * k;
         G.tile_count = k;
-        frames[f] = G;
+        rt.frames[f] = G;
     }
+}
+
+__global__ void __launch_bounds__(TOPK_THREADS) topk_kernel(const float *__restrict__ y, int ldy,
+                                                            int n_cells, int k,
+                                                            int32_t *__restrict__ out, RescoreTables rt)
+{
+    constexpr int PER = TOPK_SORT / TOPK_THREADS;
+    __shared__ int hist[256];
+    __shared__ int scan_sh[4];
+    __shared__ int pick[3];   // digit, keys still to take at it, keys at it
+    __shared__ int n_sel;
+    __shared__ unsigned long long buf[TOPK_MAX];
+    const int f = blockIdx.x;
+    const int t = threadIdx.x;
+    uint32_t u[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * TOPK_THREADS + t;
+        uint32_t b = 0u;
+        if (i < n_cells) {
+            b = __float_as_uint(y[(size_t)f * ldy + i]);
+            b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        }
+        u[j] = b;
+    }
+    uint32_t prefix = 0u, pmask = 0u;
+    int rem = k, at_T = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        hist[t] = 0;
+        __syncthreads();
+        // a wave whose counted keys share one digit (typical of the leading
+        // digits: sign and exponent) adds them with one atomic
+        const int lane = t & 63;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const bool act = j * TOPK_THREADS + t < n_cells && (u[j] & pmask) == prefix;
+            const uint32_t dg = (u[j] >> shift) & 255u;
+            const unsigned long long am = __ballot(act);
+            if (am == 0ull) continue;
+            const int first = __builtin_ctzll(am);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)dg, first);
+            if (__ballot(act && dg != d0) == 0ull) {
+                if (lane == first) atomicAdd(&hist[d0], (int)__popcll(am));
+            } else if (act) {
+                atomicAdd(&hist[dg], 1);
+            }
+        }
+        __syncthreads();
+        // thread t holds digit 255 - t: the inclusive scan counts the keys
+        // whose digit is >= that digit
+        const int d = 255 - t;
+        const int c = hist[d];
+        const int incl = block_scan_256(c, scan_sh);
+        const int excl = incl - c;
+        if (excl < rem && incl >= rem) {
+            pick[0] = d;
+            pick[1] = rem - excl;
+            pick[2] = c;
+        }
+        __syncthreads();
+        prefix |= (uint32_t)pick[0] << shift;
+        pmask |= 255u << shift;
+        rem = pick[1];
+        at_T = pick[2];
+        __syncthreads();
+    }
+    const uint32_t T = prefix;
+    // keys equal to T to take: all of them, or (ties) the rem lowest indices
+    uint32_t take = 0u;
+    if (rem == at_T) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (j * TOPK_THREADS + t < n_cells && u[j] == T) take |= 1u << j;
+    } else {
+        int before = 0;
+        for (int j = 0; j < PER; ++j) {
+            const int e = (j * TOPK_THREADS + t < n_cells && u[j] == T) ? 1 : 0;
+            const int incl = block_scan_256(e, scan_sh);
+            if (e && before + incl <= rem) take |= 1u << j;
+            if (t == TOPK_THREADS - 1) scan_sh[0] = incl;
+            __syncthreads();
+            before += scan_sh[0];
+            __syncthreads();
+        }
+    }
+    if (t == 0) n_sel = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * TOPK_THREADS + t;
+        if (i < n_cells && (u[j] > T || ((take >> j) & 1u))) {
+            const int pos = atomicAdd(&n_sel, 1);
+            buf[pos] = ((unsigned long long)u[j] << 32) |
+                       (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        }
+    }
+    int P = 1;
+    while (P < k) P <<= 1;
+    for (int i = k + t; i < P; i += TOPK_THREADS) buf[i] = 0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int i = t, j = t ^ stride;
+            if (i < P && j > i) {
+                const bool desc = (i & size) == 0;
+                const unsigned long long a = buf[i], b = buf[j];
+                if (desc ? (a < b) : (a > b)) {
+                    buf[i] = b;
+                    buf[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int cell = 0;
+    if (t < k) {
+        cell = (int32_t)(0xFFFFFFFFu - (uint32_t)buf[t]);
+        out[(size_t)f * k + t] = cell;
+    }
+    if (rt.frames) rescore_windows(rt, f, k, cell, scan_sh);
 }
 
 // host launchers -------------------------------------------------------------
@@ -706,22 +823,15 @@ int launch_featurize(const FrameDev *frames, const dpps_robot *robots, int n_fra
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out, void *st)
+int launch_topk(const float *y, int ldy, int n_frames, int n_cells, int k, int32_t *out,
+                const RescoreTables *rt, void *st)
 {
     if (n_cells > TOPK_SORT || k > n_cells || k > TOPK_MAX) return -1;
-    hipLaunchKernelGGL(topk_kernel, dim3(n_frames), dim3(64), 0, (hipStream_t)st, y, ldy, n_cells,
-                       k, out);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-int launch_rescore_tables(const FrameDev *src, int n_frames, const int32_t *cells, int k,
-                          int coarse_nx, int fine_nx, int fine_ny, float fine_h, FrameDev *frames,
-                          WinDev *wins, TileDev *tiles, void *st)
-{
-    if (k > TOPK_MAX) return -1;
-    hipLaunchKernelGGL(rescore_tables_kernel, dim3(n_frames), dim3(TOPK_MAX), 0, (hipStream_t)st,
-                       src, n_frames, cells, k, coarse_nx, fine_nx, fine_ny, fine_h, frames, wins,
-                       tiles);
+    RescoreTables r;
+    memset(&r, 0, sizeof r);
+    if (rt) r = *rt;
+    hipLaunchKernelGGL(topk_kernel, dim3(n_frames), dim3(TOPK_THREADS), 0, (hipStream_t)st, y, ldy,
+                       n_cells, k, out, r);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

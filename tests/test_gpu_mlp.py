@@ -152,6 +152,43 @@ def test_topk_matches_sort(B):
     bt.close(); net.close(); s.close()
 
 
+def test_topk_ties_take_the_lower_indices(B):
+    # a zero output layer: every frame's map is the bias, 7 levels over 2806
+    # cells, so the k-th largest value is shared by hundreds of cells
+    s = B.Searcher(P)
+    net = B.Mlp(s, 8, max_k=128, seed=5)
+    parts = M.split(net.get_params())
+    W3, b3 = parts[3]
+    rng = np.random.default_rng(9)
+    parts[3] = (np.zeros_like(W3), rng.integers(-3, 4, b3.size).astype(np.float64) * 0.25)
+    net.set_params(M.join(parts).astype(np.float32))
+    frames = _frames(3, 500)
+    bt = s.batch(frames)
+    y = net.forward(bt).cpu().numpy()
+    assert (y == y[0]).all() and np.unique(y[0]).size == 7
+    for k in (1, 17, 64, 100, 128):
+        cells = net.topk(len(frames), k).cpu().numpy()
+        for i in range(len(frames)):
+            assert list(cells[i]) == list(M.topk(y[i], k)), (k, i)
+    bt.close(); net.close(); s.close()
+
+
+def test_small_batch_forward_is_bit_identical_to_the_tiled_forward(B):
+    # up to 64 frames run through the few-row GEMM, larger batches through
+    # the tiled one: the same frames give the same outputs bit for bit
+    s = B.Searcher(P)
+    net = B.Mlp(s, 80, seed=11)
+    frames = _frames(70, 600)
+    big = s.batch(frames)
+    yb = net.forward(big).cpu().numpy()
+    for n in (1, 5, 16, 17, 64):
+        small = s.batch(frames[:n])
+        ys = net.forward(small).cpu().numpy()
+        assert ys.tobytes() == yb[:n].tobytes(), n
+        small.close()
+    big.close(); net.close(); s.close()
+
+
 def _windows_of_cells(cells):
     wins = []
     for c in cells:
