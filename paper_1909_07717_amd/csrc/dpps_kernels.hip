@@ -766,6 +766,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
 {
     __shared__ TileRec red[256];
+    __shared__ int s_wi;
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
     if (f == 0 && tid == 0 && a.counter) *a.counter = 0u;
@@ -776,28 +777,42 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
     r.pad = 0.0f;
     r.t_team = INFINITY;
     r.t_opp = INFINITY;
-    for (int k = tid; k < F.tile_count; k += blockDim.x) {
-        const TileRec x = a.tile_rec[F.tile_begin + k];
-        if (x.key > r.key) r = x;
+    // four records in flight per thread (the keys are unique: order-free)
+    for (int k0 = tid; k0 < F.tile_count; k0 += 4 * blockDim.x) {
+        TileRec x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + q * blockDim.x;
+            x[q].key = 0ull;
+            if (k < F.tile_count) x[q] = a.tile_rec[F.tile_begin + k];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (x[q].key > r.key) r = x[q];
     }
     red[tid] = r;
+    if (tid == 0) s_wi = 0;
     __syncthreads();
     for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
         if (tid < s && red[tid + s].key > red[tid].key) red[tid] = red[tid + s];
         __syncthreads();
     }
-    if (tid != 0) return;
     const TileRec bestr = red[0];
+    // the window of the best element: the last window whose element base is
+    // not above it (bases increase with the window), searched in parallel
+    const uint32_t lin = 0xFFFFFFFFu - (uint32_t)bestr.key;
+    if (bestr.key != 0ull)
+        for (int k = tid; k < F.n_windows; k += blockDim.x)
+            if ((uint32_t)a.wins[F.win_off + k].elem_base <= lin) atomicMax(&s_wi, k);
+    __syncthreads();
+    if (tid != 0) return;
     dpps_best b;
     b.found = 0; b.window = -1; b.variant = -1; b.i = -1; b.j = -1; b.type = -1;
     b.x = b.y = b.v0 = 0.0f;
     b.score = -INFINITY; b.t_team = INFINITY; b.t_opp = INFINITY; b.t_ball = INFINITY;
     b.pad = 0;
     if (bestr.key != 0ull) {
-        const uint32_t lin = 0xFFFFFFFFu - (uint32_t)bestr.key;
-        int wi = 0;
-        for (int k = 0; k < F.n_windows; ++k)
-            if ((uint32_t)a.wins[F.win_off + k].elem_base <= lin) wi = k;
+        const int wi = s_wi;
         const WinDev W = a.wins[F.win_off + wi];
         const uint32_t rel = lin - (uint32_t)W.elem_base;
         const int v = (int)(rel / (uint32_t)W.npts);

@@ -567,22 +567,36 @@ __global__ void __launch_bounds__(64) featurize_kernel(const FrameDev *__restric
 // Top-k cells of each frame's predicted map (one 256-thread workgroup per
 // frame), ordered by (score, index) descending with ties to the lower index.
 // The cells' keys (order-preserving score bits) stay in registers (thread t
-// holds cells t, t + 256, ...).  Four radix passes of 8 bits find the k-th
-// largest key T: each pass histograms the digit of the keys that match the
-// digits chosen so far and picks the digit where the count of larger keys
-// reaches k.  All keys above T are taken, and of the keys equal to T the
-// lowest-index ones; the k winners are sorted by a bitonic network in LDS.
+// holds cells t, t + 256, ...).  Radix passes of 8 bits narrow down the bin
+// of key prefixes that holds the k-th largest key: each pass histograms the
+// next digit of the keys in the current bin and picks the digit where the
+// count of larger keys reaches k.  Keys above the bin are all taken; once the
+// bin holds at most 256 keys, its best ones are found by ranking them
+// (composite key: score bits, then the inverted index); a bin of more than
+// 256 exactly equal keys gives its lowest indices.  The k winners are
+// ordered by their ranks among themselves.
 constexpr int TOPK_THREADS = 256;
 
-// Inclusive prefix sum over the 256 threads of a workgroup (sh: 4 ints).
+// Inclusive prefix sum over the 256 threads of a workgroup (sh: 4 ints):
+// DPP row shifts within each row of 16 lanes (lanes without a source add 0),
+// the row totals carried by lane reads, then the wave totals through LDS.
+template <int N>
+__device__ __forceinline__ int row_shr_add(int v)
+{
+    return v + __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xf, 0xf, false);
+}
+
 __device__ __forceinline__ int block_scan_256(int v, int *sh)
 {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int u = __shfl_up(v, o, 64);
-        if (l >= o) v += u;
-    }
+    v = row_shr_add<1>(v);
+    v = row_shr_add<2>(v);
+    v = row_shr_add<4>(v);
+    v = row_shr_add<8>(v);
+    const int r0 = __builtin_amdgcn_readlane(v, 15);
+    const int r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47);
+    v += (l >= 16 ? r0 : 0) + (l >= 32 ? r1 : 0) + (l >= 48 ? r2 : 0);
     if (l == 63) sh[w] = v;
     __syncthreads();
     int add = 0;
@@ -646,13 +660,17 @@ __global__ void __launch_bounds__(TOPK_THREADS) topk_kernel(const float *__restr
                                                             int32_t *__restrict__ out, RescoreTables rt)
 {
     constexpr int PER = TOPK_SORT / TOPK_THREADS;
+    constexpr int RANK_MAX = TOPK_THREADS;
     __shared__ int hist[256];
     __shared__ int scan_sh[4];
     __shared__ int pick[3];   // digit, keys still to take at it, keys at it
-    __shared__ int n_sel;
+    __shared__ int n_sel, n_cand;
+    __shared__ unsigned long long cand[RANK_MAX];
     __shared__ unsigned long long buf[TOPK_MAX];
+    __shared__ unsigned long long sorted[TOPK_MAX];
     const int f = blockIdx.x;
     const int t = threadIdx.x;
+    const int lane = t & 63;
     uint32_t u[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
@@ -666,13 +684,13 @@ __global__ void __launch_bounds__(TOPK_THREADS) topk_kernel(const float *__restr
     }
     uint32_t prefix = 0u, pmask = 0u;
     int rem = k, at_T = 0;
+    bool ranked = false;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         hist[t] = 0;
         __syncthreads();
         // a wave whose counted keys share one digit (typical of the leading
         // digits: sign and exponent) adds them with one atomic
-        const int lane = t & 63;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const bool act = j * TOPK_THREADS + t < n_cells && (u[j] & pmask) == prefix;
@@ -705,58 +723,66 @@ __global__ void __launch_bounds__(TOPK_THREADS) topk_kernel(const float *__restr
         rem = pick[1];
         at_T = pick[2];
         __syncthreads();
+        if (at_T <= RANK_MAX) {
+            ranked = true;
+            break;
+        }
     }
-    const uint32_t T = prefix;
-    // keys equal to T to take: all of them, or (ties) the rem lowest indices
-    uint32_t take = 0u;
-    if (rem == at_T) {
+    if (t == 0) {
+        n_sel = 0;
+        n_cand = 0;
+    }
+    __syncthreads();
+    // keys above the bin are taken, the bin's keys are candidates
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (j * TOPK_THREADS + t < n_cells && u[j] == T) take |= 1u << j;
-    } else {
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * TOPK_THREADS + t;
+        if (i >= n_cells) continue;
+        const uint32_t m = u[j] & pmask;
+        const unsigned long long ck =
+            ((unsigned long long)u[j] << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        if (m > prefix)
+            buf[atomicAdd(&n_sel, 1)] = ck;
+        else if (ranked && m == prefix)
+            cand[atomicAdd(&n_cand, 1)] = ck;
+    }
+    if (!ranked) {
+        // more than RANK_MAX keys equal the k-th largest: the rem lowest
+        // indices among them, in index order (row j holds indices 256 j + t)
         int before = 0;
         for (int j = 0; j < PER; ++j) {
-            const int e = (j * TOPK_THREADS + t < n_cells && u[j] == T) ? 1 : 0;
+            const int i = j * TOPK_THREADS + t;
+            const int e = (i < n_cells && u[j] == prefix) ? 1 : 0;
             const int incl = block_scan_256(e, scan_sh);
-            if (e && before + incl <= rem) take |= 1u << j;
+            if (e && before + incl <= rem)
+                buf[atomicAdd(&n_sel, 1)] = ((unsigned long long)u[j] << 32) |
+                                            (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
             if (t == TOPK_THREADS - 1) scan_sh[0] = incl;
             __syncthreads();
             before += scan_sh[0];
             __syncthreads();
         }
     }
-    if (t == 0) n_sel = 0;
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int i = j * TOPK_THREADS + t;
-        if (i < n_cells && (u[j] > T || ((take >> j) & 1u))) {
-            const int pos = atomicAdd(&n_sel, 1);
-            buf[pos] = ((unsigned long long)u[j] << 32) |
-                       (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-        }
+    if (ranked && t < at_T) {
+        // composite keys are unique: the rem highest candidates
+        const unsigned long long my = cand[t];
+        int r = 0;
+        for (int q = 0; q < at_T; ++q) r += cand[q] > my ? 1 : 0;
+        if (r < rem) buf[atomicAdd(&n_sel, 1)] = my;
     }
-    int P = 1;
-    while (P < k) P <<= 1;
-    for (int i = k + t; i < P; i += TOPK_THREADS) buf[i] = 0ull;
     __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int i = t, j = t ^ stride;
-            if (i < P && j > i) {
-                const bool desc = (i & size) == 0;
-                const unsigned long long a = buf[i], b = buf[j];
-                if (desc ? (a < b) : (a > b)) {
-                    buf[i] = b;
-                    buf[j] = a;
-                }
-            }
-            __syncthreads();
-        }
+    // the k winners in order: each one's rank among them
+    if (t < k) {
+        const unsigned long long my = buf[t];
+        int r = 0;
+        for (int q = 0; q < k; ++q) r += buf[q] > my ? 1 : 0;
+        sorted[r] = my;
     }
+    __syncthreads();
     int cell = 0;
     if (t < k) {
-        cell = (int32_t)(0xFFFFFFFFu - (uint32_t)buf[t]);
+        cell = (int32_t)(0xFFFFFFFFu - (uint32_t)sorted[t]);
         out[(size_t)f * k + t] = cell;
     }
     if (rt.frames) rescore_windows(rt, f, k, cell, scan_sh);
