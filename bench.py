@@ -417,7 +417,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the search shards by frame with no exchange, and "
-              "this build runs on a single MI355X; run with --gpus 1.", file=sys.stderr)
+              "it is measured on a single MI355X; run with --gpus 1.", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -630,9 +630,7 @@ int read_best(dpps_ctx *c, dpps_best *h, const dpps_best *d, int n, hipStream_t 
     HIP_OK(hipMemcpyAsync(c->pinned_best, d, (size_t)n * sizeof(dpps_best), hipMemcpyDeviceToHost,
                           st));
     HIP_OK(hipEventRecord(c->landed, st));
-    hipError_t e;
-    while ((e = hipEventQuery(c->landed)) == hipErrorNotReady) {
-    }
+    const hipError_t e = hipEventSynchronize(c->landed);
     if (e != hipSuccess) return fail(DPPS_E_DEVICE, "waiting for the best records: %s", hipGetErrorString(e));
     memcpy(h, c->pinned_best, (size_t)n * sizeof(dpps_best));
     return DPPS_OK;

@@ -125,6 +125,6 @@ int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *
                 const dpps_variant *variants, hipStream_t st);
 int stage_tables(dpps_ctx *c, dpps_batch *b, hipStream_t st);
 // Copy n best records from device memory to h (host) after the work queued
-// on st, through the context's pinned buffer; the host polls an event rather
-// than sleeping in a stream synchronisation (single-frame latency).
+// on st, through the context's pinned buffer (no staging of pageable memory),
+// waiting on an event recorded after the copy.
 int read_best(dpps_ctx *c, dpps_best *h, const dpps_best *d, int n, hipStream_t st);
