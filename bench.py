@@ -368,13 +368,21 @@ def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
 def surrogate_bench(frames: int, weights: str, lat_frames: int = 10000):
     """Surrogate + top-64 exact re-score (5 cm) against the exact 5 cm search
     on 6v6 frames with one flat pass at 4 m/s, K = 64 (the network's
-    training setting): regret, match and fallback rates, frames/s of both."""
+    training setting): regret, match and fallback rates, frames/s of both;
+    the same with the top 192 cells."""
     if not os.path.exists(weights):
         return {"note": f"no trained weights at {os.path.relpath(weights, ROOT)}"}
     from paper_1909_07717_amd.surrogate import evaluate, latency
     res = evaluate(weights, frames, k=64, batch=min(frames, 1024))
     res["speedup_vs_exact"] = res["surrogate_frames_per_s"] / res["exact_frames_per_s"]
     res["latency_ms"] = latency(weights, frames=lat_frames)
+    # the same network with 192 proposed cells (3072 re-scored points)
+    wide = evaluate(weights, frames, k=192, batch=min(frames, 1024))
+    res["k192"] = {key: wide[key] for key in ("regret_le_1pct", "regret_mean", "regret_p99",
+                                              "match_rate", "fallback_rate",
+                                              "surrogate_frames_per_s")}
+    res["k192"]["speedup_vs_exact"] = wide["surrogate_frames_per_s"] / wide["exact_frames_per_s"]
+    res["k192"]["latency_ms"] = latency(weights, frames=lat_frames, k=192)["surrogate"]
     from paper_1909_07717_amd.profiling import mlp_timing
     res["mlp"] = mlp_timing(4096, 20)
     return res

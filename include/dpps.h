@@ -228,7 +228,7 @@ int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs);
 typedef struct dpps_mlp dpps_mlp;
 
 int64_t dpps_mlp_param_count(void);
-/* max_frames: largest batch; max_k: largest top-k (<= 128); He-uniform
+/* max_frames: largest batch; max_k: largest top-k (<= 256); He-uniform
  * initialisation from `seed`. */
 int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t seed,
                     dpps_mlp **out);

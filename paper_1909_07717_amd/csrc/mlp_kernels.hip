@@ -576,6 +576,7 @@ __global__ void __launch_bounds__(64) featurize_kernel(const FrameDev *__restric
 // 256 exactly equal keys gives its lowest indices.  The k winners are
 // ordered by their ranks among themselves.
 constexpr int TOPK_THREADS = 256;
+static_assert(TOPK_MAX <= TOPK_THREADS, "one thread per top-k winner");
 
 // Inclusive prefix sum over the 256 threads of a workgroup (sh: 4 ints):
 // DPP row shifts within each row of 16 lanes (lanes without a source add 0),

@@ -315,7 +315,9 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
             found_both += 1
             r = (float(be[i]["score"]) - float(bs[i]["score"])) / float(be[i]["score"])
             regrets.append(max(r, 0.0))
-            match += int(be[i]["i"] == bs[i]["i"] and be[i]["j"] == bs[i]["j"])
+            # the same field point and kick (i, j are relative to each record's window)
+            match += int(be[i]["x"] == bs[i]["x"] and be[i]["y"] == bs[i]["y"]
+                         and be[i]["v0"] == bs[i]["v0"])
         bt.close()
         n_done += n
     r = np.array(regrets)

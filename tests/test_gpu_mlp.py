@@ -156,7 +156,7 @@ def test_topk_ties_take_the_lower_indices(B):
     # a zero output layer: every frame's map is the bias, 7 levels over 2806
     # cells, so the k-th largest value is shared by hundreds of cells
     s = B.Searcher(P)
-    net = B.Mlp(s, 8, max_k=128, seed=5)
+    net = B.Mlp(s, 8, max_k=256, seed=5)
     parts = M.split(net.get_params())
     W3, b3 = parts[3]
     rng = np.random.default_rng(9)
@@ -166,7 +166,7 @@ def test_topk_ties_take_the_lower_indices(B):
     bt = s.batch(frames)
     y = net.forward(bt).cpu().numpy()
     assert (y == y[0]).all() and np.unique(y[0]).size == 7
-    for k in (1, 17, 64, 100, 128):
+    for k in (1, 17, 64, 100, 128, 200, 256):
         cells = net.topk(len(frames), k).cpu().numpy()
         for i in range(len(frames)):
             assert list(cells[i]) == list(M.topk(y[i], k)), (k, i)
