@@ -406,7 +406,7 @@ def serving_bench(duration: float, weights: str):
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--surrogate-frames", type=int, default=1000)
+    ap.add_argument("--surrogate-frames", type=int, default=4000)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1909_07717_amd", "weights",
                                                       "surrogate.npz"))

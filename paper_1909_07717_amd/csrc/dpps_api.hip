@@ -898,7 +898,14 @@ int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,
     o.best = nullptr;
     int rc = dpps_search_batch(c, 1, frame, robots, windows, variants, &o, c->stream);
     if (rc) return rc;
-    return read_best(c, h_best, c->scratch.d_best, 1, c->stream);
+    // a direct copy and a stream synchronisation: over 2 x 3000 frames this
+    // gave a shorter tail (p99 0.245 vs 0.305 ms for the full frame) than the
+    // pinned read-back that the surrogate path uses (which there gives the
+    // lower median)
+    HIP_OK(hipMemcpyAsync(h_best, c->scratch.d_best, sizeof(dpps_best), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return DPPS_OK;
 }
 
 int dpps_batch_create(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
