@@ -148,7 +148,13 @@ int build_tables(const dpps_params *p, int32_t n_frames, const dpps_frame *frame
     if (n_frames < 0) return fail(DPPS_E_INVALID, "n_frames < 0");
     if (n_frames > 0 && (!frames || !robots || !windows || !variants))
         return fail(DPPS_E_INVALID, "NULL input array");
-    T = HostTables();
+    // cleared, not reallocated: repeated calls reuse the vectors' storage
+    T.frames.clear();
+    T.robots.clear();
+    T.variants.clear();
+    T.wins.clear();
+    T.tiles.clear();
+    T.points = 0;
     T.frames.reserve(n_frames);
     const bool reduced = (p->out_flags & DPPS_OUT_REDUCED) != 0;
     for (int32_t f = 0; f < n_frames; ++f) {
@@ -896,7 +902,11 @@ int dpps_search(dpps_ctx *c, const dpps_frame *frame, const dpps_robot *robots,
     if (!c || !frame || !out || !h_best) return fail(DPPS_E_INVALID, "NULL argument");
     dpps_outputs o = *out;
     o.best = nullptr;
-    int rc = dpps_search_batch(c, 1, frame, robots, windows, variants, &o, c->stream);
+    HIP_OK(hipSetDevice(c->device));
+    int rc = stage_batch(c, &c->scratch, 1, frame, robots, windows, variants, c->stream);
+    if (rc) return rc;
+    // no timing events around the kernel of a single synchronous search
+    rc = run_batch(c, &c->scratch, &o, c->stream, false);
     if (rc) return rc;
     // a direct copy and a stream synchronisation: over 2 x 3000 frames this
     // gave a shorter tail (p99 0.245 vs 0.305 ms for the full frame) than the
