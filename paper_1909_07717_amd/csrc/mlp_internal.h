@@ -9,7 +9,7 @@ namespace dpps {
 
 enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3, EPI_PARTIAL = 4 };
 
-#define TOPK_SORT 4096   // cells sorted per frame (>= coarse lattice size)
+#define TOPK_SORT 4096   // most cells per frame for the top-k (>= coarse lattice size)
 #define TOPK_MAX 256     // largest k (one workgroup thread per winner)
 
 struct GemmArgs {
