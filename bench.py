@@ -232,6 +232,8 @@ def shot_bench(n_frames: int, steps: int, lat_frames: int, st):
     res["map"] = {"workload": "shot map of the full 5 cm lattice 241x181, 8 opponents, K = 256",
                   "ms_per_frame": round(ms, 4), "positions_per_s": round(n / (ms * 1e-3), 1),
                   "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+                  "frac": round(FL.tflops(fl, ms) / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
+                  "frac_of_nonpacked": round(FL.tflops(fl, ms) / FL.PEAK_FP32_NONPACKED_TFLOPS, 4),
                   "shoot_fraction": round(n_shoot / n, 4)}
     s.close()
     return res
@@ -290,7 +292,10 @@ def run_bench(n_frames: int, steps: int, lat_frames: int, st):
                         f"({pts // n_frames} points per frame)",
             "ms_per_call": round(ms, 4), "points_per_s": round(pts / (ms * 1e-3), 1),
             "zones_per_s": round(4 * n_frames / (ms * 1e-3), 1),
-            "tflops": round(fl / (ms * 1e-3) / 1e12, 3), "found_fraction": round(found, 4),
+            "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+            "frac": round(FL.tflops(fl, ms) / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
+            "frac_of_nonpacked": round(FL.tflops(fl, ms) / FL.PEAK_FP32_NONPACKED_TFLOPS, 4),
+            "found_fraction": round(found, 4),
             "score_map_bytes": 4 * pts,
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                            "p99": round(float(np.percentile(lat, 99)), 4),
@@ -358,6 +363,8 @@ def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
             "frames_per_s": round(n_frames / (ms * 1e-3), 1),
             "pass_evals_per_s": round(evals / (ms * 1e-3), 1),
             "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
+            "frac": round(FL.tflops(fl, ms) / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
+            "frac_of_nonpacked": round(FL.tflops(fl, ms) / FL.PEAK_FP32_NONPACKED_TFLOPS, 4),
             "feasible_fraction": round(float(n_feas.sum()) / (n_frames * n_dirs * speeds), 4),
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                            "p99": round(float(np.percentile(lat, 99)), 4),

@@ -122,3 +122,8 @@ C_RUN_OPP = 2 * C_ROBOT + 12
 def run_flops(n_opp: int) -> int:
     """Flops of one running-point evaluation against n_opp opponents."""
     return C_RUN_POINT + C_RUN_OPP * n_opp
+
+
+def tflops(flop: float, ms: float) -> float:
+    """TFLOP/s of `flop` operations in `ms` milliseconds."""
+    return flop / (ms * 1e-3) / 1e12

@@ -10,6 +10,10 @@
         the surrogate network: `steps` forward passes, then `steps` training
         steps (forward, loss, backward, Adam) on one batch of 6 v 6 frames
         with synthetic labels;
+    python3 -m paper_1909_07717_amd.profiling rows --steps 5
+        the benchmark's workloads of the next rows, `steps` calls each: the
+        passing-power search of the full frame, the shot decisions and map,
+        the running points, the direction x power sweep;
     python3 -m paper_1909_07717_amd.profiling latency --frames 300
         one frame per call (6 v 6, one flat pass at 4 m/s, K = 64, 5 cm):
         the exact search, then the surrogate search with fallback, host
@@ -126,6 +130,8 @@ def main():
     m = sub.add_parser("mlp")
     m.add_argument("--batch", type=int, default=4096)
     m.add_argument("--steps", type=int, default=20)
+    w = sub.add_parser("rows")
+    w.add_argument("--steps", type=int, default=5)
     q = sub.add_parser("latency")
     q.add_argument("--frames", type=int, default=300)
     q.add_argument("--warmup", type=int, default=50)
@@ -134,6 +140,18 @@ def main():
         run_search(args.steps, args.seed, args.reduced, args.launch)
     elif args.cmd == "copy":
         run_copy(args.mib, args.reps)
+    elif args.cmd == "rows":
+        import json
+
+        import torch
+
+        import bench
+        st = torch.cuda.Stream()
+        out = {"power": bench.power_bench(args.steps, st),
+               "shots": bench.shot_bench(4096, args.steps, 20, st),
+               "running": bench.run_bench(4096, args.steps, 20, st),
+               "rays": bench.ray_bench(512, args.steps, 20, st)}
+        print(json.dumps({k: v.get("workload", "") for k, v in out.items()}), flush=True)
     elif args.cmd == "latency":
         import json
 
