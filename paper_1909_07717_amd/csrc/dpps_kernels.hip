@@ -868,6 +868,14 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
 // received at the first teammate's interception, five-feature score.
 // ----------------------------------------------------------------------------
 
+// Lane n of each row of 16 lanes, broadcast to its row (DPP row_newbcast).
+template <int N>
+__device__ __forceinline__ float row_newbcast(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xf, 0xf,
+                                                      false));
+}
+
 // Open goal angle at up to four points at once: lane 16 g + o looks at
 // point g (its own cx, cy) and opponent o (at most 16 opponents).  The same
 // construction as open_angle within each group of 16 lanes; returns on every
@@ -891,15 +899,22 @@ __device__ float open_angle4(const StageLDS &S, const DevParams &P, float cx, fl
     const float e = fminf(ang + al, hi);
     const bool has = valid && e > s;
     // each interval adds what the group's intervals sorted before it (by
-    // start, then index) have not covered
+    // start, then index) have not covered; interval j of the group comes
+    // from lane j of the row by a DPP row broadcast (a start of +inf marks
+    // no interval)
+    const float sh = has ? s : INFINITY;
     float M = -INFINITY;
-    for (int j = 0; j < n_op; ++j) {
-        const float sj = __shfl(s, base | j, 64);
-        const float ej = __shfl(e, base | j, 64);
-        const int hj = __shfl((int)has, base | j, 64);
-        const bool before = hj && (sj < s || (sj == s && j < o));
-        M = before ? fmaxf(M, ej) : M;
+#define OA4_STEP(J)                                                      \
+    if (J < n_op) {                                                      \
+        const float sj = row_newbcast<J>(sh), ej = row_newbcast<J>(e);   \
+        const bool before = sj < sh || (sj == sh && J < o);              \
+        M = before ? fmaxf(M, ej) : M;                                   \
     }
+    OA4_STEP(0) OA4_STEP(1) OA4_STEP(2) OA4_STEP(3)
+    OA4_STEP(4) OA4_STEP(5) OA4_STEP(6) OA4_STEP(7)
+    OA4_STEP(8) OA4_STEP(9) OA4_STEP(10) OA4_STEP(11)
+    OA4_STEP(12) OA4_STEP(13) OA4_STEP(14) OA4_STEP(15)
+#undef OA4_STEP
     float c = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
     c += __shfl_xor(c, 1, 64);
     c += __shfl_xor(c, 2, 64);
