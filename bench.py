@@ -42,7 +42,7 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(flops_kernel: str):
+def measured_traffic():
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "search_kernel_full_frame_traffic.json")
@@ -535,7 +535,7 @@ def main() -> int:
     roofline = {"bound": "alu", "achieved": round(achieved, 3),
                 "peak": FL.PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": measured_traffic("search_kernel"),
+                "traffic": measured_traffic(),
                 "kernel": "search_kernel", "kernel_ms": round(kern_avg_ms, 5),
                 "flops_per_launch": fl,
                 "nonpacked_peak": FL.PEAK_FP32_NONPACKED_TFLOPS,
