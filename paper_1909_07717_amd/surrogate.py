@@ -139,7 +139,8 @@ def load_checkpoint(path):
 def train(frames: int, batch: int, lr: float, out: str, resume: str | None = None,
           log_every: int = 20, seed: int = 0, epochs: int = 1, pos_weight: float = 0.0,
           ce_weight: float = 0.0, tau: float = 0.02, labels: str = "pooled",
-          params_only: bool = False, mirror: bool = False):
+          params_only: bool = False, mirror: bool = False, init: str | None = None,
+          data_seed: int = TRAIN_SEED):
     """`frames` distinct frames (frames // batch seeded batches) seen `epochs`
     times, batch order reshuffled every epoch.  With mirror, every batch also
     appears reflected about the field's long axis (its labels computed
@@ -149,7 +150,11 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
     the 5 cm points its re-score would visit (exact search of the 5 cm
     lattice, then dpps_pool_cells); "center": the exact score at the cell's
     centre (the 20 cm search).  Labels are computed once per batch by the
-    exact kernel and kept in device memory for later epochs."""
+    exact kernel and kept in device memory for later epochs.
+
+    init: start from the parameters of a checkpoint (fresh Adam state, the
+    schedule from the start); data_seed: the seed of the first training
+    batch (batch b uses data_seed + b)."""
     import torch
 
     from paper_1909_07717_amd import binding as B
@@ -166,6 +171,8 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
                             for e in range(epochs)])
     steps = len(order)
     start = 0
+    if init and not resume:
+        net.set_params(load_checkpoint(init)["params"])
     if resume:
         ck = load_checkpoint(resume)
         net.set_params(ck["params"])
@@ -181,7 +188,7 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
     for step in range(start, steps):
         bi = int(order[step])
         if bi not in tables:
-            team, opp, passer = uniform_batch_arrays(TRAIN_SEED + bi % n_batches, batch)
+            team, opp, passer = uniform_batch_arrays(data_seed + bi % n_batches, batch)
             if bi >= n_batches:
                 team, opp = mirror_arrays(team, opp)
             tables[bi] = s.batch(B.pack_uniform(team, opp, passer, windows, variants, p))
@@ -213,7 +220,8 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
             print(json.dumps(rec), flush=True)
     meta = {"frames": n_batches * batch, "epochs": epochs, "batch": batch, "lr": lr,
             "pos_weight": pos_weight, "ce_weight": ce_weight, "tau": tau, "labels": labels,
-            "steps": steps, "train_seed": TRAIN_SEED, "mirror": mirror, "log": log}
+            "steps": steps, "train_seed": data_seed, "mirror": mirror, "log": log,
+            "init": os.path.basename(init) if init else None}
     for t in tables.values():
         t.close()
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
@@ -407,6 +415,8 @@ def main():
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--params-only", action="store_true")
     t.add_argument("--mirror", action="store_true")
+    t.add_argument("--init", default=None)
+    t.add_argument("--data-seed", type=int, default=TRAIN_SEED)
     e = sub.add_parser("eval")
     e.add_argument("--weights", default=WEIGHTS)
     e.add_argument("--frames", type=int, default=2000)
@@ -420,7 +430,7 @@ def main():
         train(args.frames, args.batch, args.lr, args.out, args.resume, seed=args.seed,
               epochs=args.epochs, pos_weight=args.pos_weight, ce_weight=args.ce_weight,
               tau=args.tau, labels=args.labels, params_only=args.params_only,
-              mirror=args.mirror)
+              mirror=args.mirror, init=args.init, data_seed=args.data_seed)
     else:
         print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random,
                                   dump=args.dump, proposals=args.proposals,
