@@ -38,6 +38,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate.npz")
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.jsonl")
+
+
+def _tune(s, B, pk, cache):
+    """Set the context's launch shape from the autotuner for requests like
+    pk (cached per request class in `cache`; None keeps the default)."""
+    if cache is None:
+        return
+    bt = s.batch(pk)
+    bt.autotune(s.outputs_for(pk, mask=False, score=False), cache, reps=5)
+    bt.close()
 TRAIN_SEED = 1_000_000
 EVAL_SEED = 20_000_000
 
@@ -233,7 +244,7 @@ def train(frames: int, batch: int, lr: float, out: str, resume: str | None = Non
 
 def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, random_net=False,
              seed0: int = EVAL_SEED, dump: str | None = None, proposals: str = "network",
-             fallback_below: float = -math.inf):
+             fallback_below: float = -math.inf, tune_cache: str | None = TUNE_CACHE):
     """Regret statistics of the surrogate search against the exact 5 cm search.
 
     proposals = "network": the trained (or, with random_net, untrained)
@@ -256,6 +267,9 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
     variants = variants_for([4.0], flat=True, chip=False)
     fine = [full_window(0.05)]
     s = B.Searcher(p)
+    # the exact path at its autotuned launch shape (the surrogate shares it)
+    t0, o0, p0 = uniform_batch_arrays(seed0, min(batch, frames))
+    _tune(s, B, B.pack_uniform(t0, o0, p0, fine, variants, p), tune_cache)
     net = B.Mlp(s, batch, max_k=max(k, 1), seed=12345)
     if weights and not random_net:
         net.set_params(load_checkpoint(weights)["params"])
@@ -348,7 +362,7 @@ def evaluate(weights: str | None, frames: int, k: int = 64, batch: int = 512, ra
 
 
 def latency(weights: str | None, frames: int = 10000, warmup: int = 100, k: int = 64,
-            seed0: int = EVAL_SEED):
+            seed0: int = EVAL_SEED, tune_cache: str | None = TUNE_CACHE):
     """Frame latency, host inputs to the best pass on the host, one frame at
     a time (6 v 6, one flat pass at 4 m/s, K = 64): the exact search of the
     whole 5 cm lattice (dpps_search) and the surrogate search with exact
@@ -373,6 +387,7 @@ def latency(weights: str | None, frames: int = 10000, warmup: int = 100, k: int 
     team, opp, passer = uniform_batch_arrays(seed0 + 7777, n)
     fr = frames_from_arrays(team, opp, passer, fine, variants)
     pks = [B.pack([f], p) for f in fr]
+    _tune(s, B, pks[0], tune_cache)
     best = torch.empty(B.BEST_DT.itemsize, dtype=torch.uint8, device=s.device)
     host = np.zeros(1, B.BEST_DT)
     dev = s.outputs_for(pks[0], mask=False, score=False)
@@ -425,6 +440,7 @@ def main():
     e.add_argument("--dump", default=None)
     e.add_argument("--proposals", choices=["network", "mirror", "geometric"], default="network")
     e.add_argument("--fallback-below", type=float, default=-math.inf)
+    e.add_argument("--tune-cache", default=TUNE_CACHE)
     args = ap.parse_args()
     if args.cmd == "train":
         train(args.frames, args.batch, args.lr, args.out, args.resume, seed=args.seed,
@@ -434,7 +450,8 @@ def main():
     else:
         print(json.dumps(evaluate(args.weights, args.frames, args.k, random_net=args.random,
                                   dump=args.dump, proposals=args.proposals,
-                                  fallback_below=args.fallback_below)), flush=True)
+                                  fallback_below=args.fallback_below,
+                                  tune_cache=args.tune_cache)), flush=True)
 
 
 if __name__ == "__main__":
