@@ -429,6 +429,20 @@ __device__ __forceinline__ double ball_time64(const VarConst &c, double s)
     return to + 2.0 * x / (va + sqrt(q));
 }
 
+// Order-preserving map of a float's bits to an unsigned key (negative scores
+// order below positive ones); a finite score never maps to 0, which marks
+// "no feasible pass" in the argmax keys.
+__device__ __forceinline__ uint32_t ordered_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return u ^ ((u & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u);
+}
+
+__device__ __forceinline__ float unordered_bits(uint32_t k)
+{
+    return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
+}
+
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 {
 #pragma unroll
@@ -697,7 +711,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             unsigned long long key = 0ull;
             if (fe) {
                 uint32_t lin = (uint32_t)(W.elem_base + myvid * W.npts + p);
-                key = ((unsigned long long)__float_as_uint(sc) << 32) |
+                key = ((unsigned long long)ordered_bits(sc) << 32) |
                       (unsigned long long)(0xFFFFFFFFu - lin);
             }
             if (key > bkey) {
@@ -711,7 +725,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                 if (l == 0) {
                     int64_t o = W.out_base + p;
                     if (a.score)
-                        a.score[o] = pk ? __uint_as_float((uint32_t)(pk >> 32)) : -INFINITY;
+                        a.score[o] = pk ? unordered_bits((uint32_t)(pk >> 32)) : -INFINITY;
                     if (a.mask) {
                         uint32_t lin = 0xFFFFFFFFu - (uint32_t)pk;
                         a.mask[o] = pk ? (uint8_t)((lin - (uint32_t)W.elem_base) / (uint32_t)W.npts)
@@ -836,7 +850,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
         b.x = W.h * mi;
         b.y = W.h * mj;
         b.v0 = pv0;
-        b.score = __uint_as_float((uint32_t)(bestr.key >> 32));
+        b.score = unordered_bits((uint32_t)(bestr.key >> 32));
         b.t_team = bestr.t_team;
         b.t_opp = bestr.t_opp;
         b.t_ball = (float)ball_time64(c, sqrt(ex64 * ex64 + ey64 * ey64));
@@ -922,19 +936,6 @@ __device__ float open_angle4(const StageLDS &S, const DevParams &P, float cx, fl
     c += __shfl_xor(c, 8, 64);
     const bool gin = ((__ballot(inside) >> base) & 0xFFFFull) != 0ull;
     return gin ? 0.0f : (hi - lo) - c;
-}
-
-// Order-preserving map of a float's bits to an unsigned key (negative scores
-// order below positive ones).
-__device__ __forceinline__ uint32_t ordered_bits(float x)
-{
-    const uint32_t u = __float_as_uint(x);
-    return u ^ ((u & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u);
-}
-
-__device__ __forceinline__ float unordered_bits(uint32_t k)
-{
-    return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
 }
 
 // Distance from the ball along (ux, uy) to the edge of the field (0 when the

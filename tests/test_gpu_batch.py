@@ -1,21 +1,33 @@
 """The batched workload at full size: 4096 frames with 6-8 robots a side,
 random windows on the 5 cm lattice (uneven point counts), 8 flat speeds,
 K = 128, in one persistent launch with the autotuned shape, replayed from a
-HIP graph.  Checked against the oracle on sampled frames and points, and
-bitwise against the default launch shape."""
+HIP graph.  Checked bitwise against the default launch shape, against the
+oracle on sampled points of 12 frames, and on every entry of a seeded
+32-frame subset (full windows, best passes)."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1909_07717_amd.framegen import Params, config_batch
-from tests.parity import compare_maps
+from tests.parity import BandPool, check_best, compare_maps
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# the seeded 32-frame subset of the 4096-frame batch (seed 0) that the oracle
+# checks in full
+SUBSET_SEED = 12345
+SUBSET_N = 32
 
-def test_full_batch_autotuned_graph(tmp_path):
+
+def subset_indices(n_frames: int = 4096) -> np.ndarray:
+    return np.sort(np.random.default_rng(SUBSET_SEED).choice(n_frames, SUBSET_N, replace=False))
+
+
+@pytest.fixture(scope="module")
+def run():
     from paper_1909_07717_amd import binding as B
+    assert torch.cuda.is_available()
     p = Params(n_samples=128).as_f32()
     print("[batch] generating 4096 frames", flush=True)
     frames = config_batch(0, n_frames=4096)
@@ -28,6 +40,13 @@ def test_full_batch_autotuned_graph(tmp_path):
     with torch.cuda.stream(st):
         bt.run(ref, stream=st)
     st.synchronize()
+    yield dict(B=B, p=p, frames=frames, s=s, bt=bt, ref=ref, st=st)
+    bt.close()
+    s.close()
+
+
+def test_full_batch_autotuned_graph(run, tmp_path):
+    s, bt, ref, st, frames, p = (run[k] for k in ("s", "bt", "ref", "st", "frames", "p"))
     cache = str(tmp_path / "tune.jsonl")
     out = s.outputs_for(bt.pk)
     ms = bt.autotune(out, cache, reps=1, stream=st)
@@ -44,6 +63,7 @@ def test_full_batch_autotuned_graph(tmp_path):
         assert torch.equal(out.best, ref.best), rep
     bests = out.best_host()
     rng = np.random.default_rng(1)
+    pool = BandPool("batch sampled points")
     for fi in sorted(rng.choice(len(frames), 12, replace=False)):
         f = frames[fi]
         a = int(bt.pk.frames["out_off"][fi])
@@ -56,7 +76,7 @@ def test_full_batch_autotuned_graph(tmp_path):
         g = dict(mask=out.mask[sel].cpu().numpy().reshape(-1, V),
                  score=out.score[sel].cpu().numpy().reshape(-1, V))
         o = O.search_points(f, p, O.points_of_window(p, win)[idx], bands=True)
-        compare_maps(g, o, f"batch frame {fi}")
+        compare_maps(g, o, f"batch frame {fi}", pool=pool)
         # the frame's best equals the argmax of its own score map
         sc = out.score[a:a + npts * V]
         if bests[fi]["found"]:
@@ -65,5 +85,25 @@ def test_full_batch_autotuned_graph(tmp_path):
             assert e == bests[fi]["variant"] * npts + bests[fi]["j"] * win[3] + bests[fi]["i"]
         else:
             assert not torch.isfinite(sc).any()
-    bt.close()
-    s.close()
+    pool.check()
+    del out
+
+
+def test_subset_full_windows(run):
+    """Every entry of 32 seeded frames of the batch (about 4.1e5 points,
+    3.3e6 entries) and each frame's best pass, against the oracle."""
+    frames, p, bt, ref = (run[k] for k in ("frames", "p", "bt", "ref"))
+    bests = ref.best_host()
+    pool = BandPool("batch 32-frame subset")
+    for fi in subset_indices(len(frames)):
+        f = frames[fi]
+        a, n = int(bt.pk.frames["out_off"][fi]), int(bt.pk.frame_elems[fi])
+        print(f"[batch] subset frame {fi}: {f.n_points()} points", flush=True)
+        g = dict(mask=ref.mask[a:a + n].cpu().numpy(), score=ref.score[a:a + n].cpu().numpy())
+        o = O.search_frame(f, p, bands=True)
+        compare_maps(g, o, f"batch frame {fi}", pool=pool)
+        b = bests[fi]
+        win = f.windows[0]
+        e = b["variant"] * win[3] * win[4] + b["j"] * win[3] + b["i"] if b["found"] else -1
+        check_best(b, o, e, f"batch frame {fi}")
+    pool.check()

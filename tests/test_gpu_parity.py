@@ -2,7 +2,10 @@
 
 Inputs are the seeded synthetic frames of the workloads; sizes are chosen so
 the oracle finishes in seconds while the GPU still runs several tiles with a
-ragged tail.  The full-size 5 cm frame is checked on sampled points.
+ragged tail, and the two workloads the tolerances are stated for at their
+full size: the 20 cm frame on seeds 0-999 and the 5 cm frame on seeds 0-7,
+every entry of every map.  The reach, landing and crossing bands are capped
+at 1e-3 of each test's pooled entries.
 """
 import math
 
@@ -13,7 +16,7 @@ from oracle import oracle as O
 from paper_1909_07717_amd.framegen import (Params, Frame, FLAT, CHIP, config_small, config_full,
                                            config_batch, full_window, random_frame, random_window,
                                            speeds_linear, variants_for)
-from tests.parity import compare_maps, check_best
+from tests.parity import BandPool, compare_maps, check_best
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -50,43 +53,90 @@ def _elem(frame, best):
     raise AssertionError("bad window")
 
 
-@pytest.mark.parametrize("seed", range(12))
-def test_small_frame_full_maps(B, seed):
-    print(f"[parity] small frame seed={seed}", flush=True)
+def test_small_frame_single_calls(B):
+    """Seeds 0-11 of the small workload through the synchronous one-frame
+    call (the batched test covers seeds 0-999)."""
     p = Params(n_samples=64).as_f32()
-    f = config_small(seed)
-    g, best = _run(B, f, p)
-    o = O.search_frame(f, p, bands=True)
-    compare_maps(g, o, f"small seed {seed}")
-    check_best(best, o, _elem(f, best) if best["found"] else -1)
-
-
-@pytest.mark.parametrize("K", [64, 128, 192, 256])
-def test_flat_and_chip_many_speeds(B, K):
-    print(f"[parity] flat+chip K={K}", flush=True)
-    p = Params(n_samples=K).as_f32()
-    f = random_frame(np.random.default_rng(1000 + K), 8, 8)
-    f.windows = [full_window(0.5)]
-    f.variants = variants_for(speeds_linear(8), flat=True, chip=True)
-    g, best = _run(B, f, p)
-    o = O.search_frame(f, p, bands=True)
-    compare_maps(g, o, f"K={K}")
-    check_best(best, o, _elem(f, best) if best["found"] else -1)
-
-
-@pytest.mark.parametrize("seed", range(3))
-def test_several_ragged_windows(B, seed):
-    print(f"[parity] ragged windows seed={seed}", flush=True)
-    p = Params(n_samples=128).as_f32()
-    rng = np.random.default_rng(2000 + seed)
-    f = random_frame(rng, 7, 6)
-    f.windows = [random_window(rng, 0.25), random_window(rng, 0.3), (np.float32(0.1).item(), 37, 11, 13, 7)]
-    f.variants = variants_for([1.5, 3.25, 5.0], flat=True, chip=True)
-    for launch in [(8, 1, 1), (40, 4, 2), (64, 8, -1)]:
-        g, best = _run(B, f, p, launch=launch)
+    pool = BandPool("small frames single calls")
+    for seed in range(12):
+        print(f"[parity] small frame seed={seed}", flush=True)
+        f = config_small(seed)
+        g, best = _run(B, f, p)
         o = O.search_frame(f, p, bands=True)
-        compare_maps(g, o, f"ragged {seed} {launch}")
+        compare_maps(g, o, f"small seed {seed}", pool=pool)
         check_best(best, o, _elem(f, best) if best["found"] else -1)
+    pool.check()
+
+
+def test_small_frames_seeds_0_999(B):
+    """The 6v6, 20 cm, one-flat-pass workload on seeds 0-999: full maps
+    (mask, score, both times) of one batched launch against the oracle, and
+    every frame's best pass."""
+    print("[parity] small frames seeds 0-999", flush=True)
+    p = Params(n_samples=64).as_f32()
+    frames = [config_small(seed) for seed in range(1000)]
+    s = B.Searcher(p)
+    pk, out = s.search_batch(frames, times=True)
+    torch.cuda.synchronize()
+    gm, gs = out.mask.cpu().numpy(), out.score.cpu().numpy()
+    gt, go = out.t_team.cpu().numpy(), out.t_opp.cpu().numpy()
+    bests = out.best_host()
+    s.close()
+    pool = BandPool("small frames seeds 0-999")
+    for seed, f in enumerate(frames):
+        a, n = int(pk.frames["out_off"][seed]), int(pk.frame_elems[seed])
+        o = O.search_frame(f, p, bands=True)
+        g = dict(mask=gm[a:a + n], score=gs[a:a + n], t_team=gt[a:a + n], t_opp=go[a:a + n])
+        compare_maps(g, o, f"small seed {seed}", pool=pool)
+        b = bests[seed]
+        check_best(b, o, _elem(f, b) if b["found"] else -1, f"small seed {seed}")
+    pool.check()
+
+
+def test_flat_and_chip_many_speeds(B):
+    pool = BandPool("flat+chip K=64..256")
+    for K in (64, 128, 192, 256):
+        print(f"[parity] flat+chip K={K}", flush=True)
+        p = Params(n_samples=K).as_f32()
+        f = random_frame(np.random.default_rng(1000 + K), 8, 8)
+        f.windows = [full_window(0.5)]
+        f.variants = variants_for(speeds_linear(8), flat=True, chip=True)
+        g, best = _run(B, f, p)
+        o = O.search_frame(f, p, bands=True)
+        compare_maps(g, o, f"K={K}", pool=pool)
+        check_best(best, o, _elem(f, best) if best["found"] else -1)
+    pool.check()
+
+
+def test_several_ragged_windows(B):
+    pool = BandPool("ragged windows")
+    for seed in range(3):
+        print(f"[parity] ragged windows seed={seed}", flush=True)
+        p = Params(n_samples=128).as_f32()
+        rng = np.random.default_rng(2000 + seed)
+        f = random_frame(rng, 7, 6)
+        f.windows = [random_window(rng, 0.25), random_window(rng, 0.3),
+                     (np.float32(0.1).item(), 37, 11, 13, 7)]
+        f.variants = variants_for([1.5, 3.25, 5.0], flat=True, chip=True)
+        o = O.search_frame(f, p, bands=True)
+        for launch in [(8, 1, 1), (40, 4, 2), (64, 8, -1)]:
+            g, best = _run(B, f, p, launch=launch)
+            compare_maps(g, o, f"ragged {seed} {launch}", pool=pool)
+            check_best(best, o, _elem(f, best) if best["found"] else -1)
+    pool.check()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_full_frame_full_maps(B, seed):
+    """The 8v8, 5 cm, 16 speeds x {flat, chip}, K = 256 frame on seeds 0-7:
+    every entry of the four maps against the oracle, and the best pass."""
+    print(f"[parity] full frame seed={seed}", flush=True)
+    p = Params(n_samples=256).as_f32()
+    f = config_full(seed)
+    g, best = _run(B, f, p)
+    o = O.search_frame(f, p, bands=True)
+    compare_maps(g, o, f"full frame seed {seed}")
+    check_best(best, o, _elem(f, best) if best["found"] else -1, f"full frame seed {seed}")
 
 
 def test_full_frame_sampled_points(B):
@@ -130,6 +180,7 @@ def test_batch_uneven_windows_matches_single_and_oracle(B):
     gt, go = out.t_team.cpu().numpy(), out.t_opp.cpu().numpy()
     bests = out.best_host()
     rng = np.random.default_rng(3)
+    pool = BandPool("batch uneven windows")
     for fi in range(0, 24, 3):
         f = frames[fi]
         a, n = int(pk.frames["out_off"][fi]), int(pk.frame_elems[fi])
@@ -145,7 +196,8 @@ def test_batch_uneven_windows_matches_single_and_oracle(B):
         V = len(f.variants)
         sel = a + np.arange(V)[None, :] * npts + idx[:, None]
         compare_maps(dict(mask=gm[sel], score=gs[sel], t_team=gt[sel], t_opp=go[sel]), o,
-                     f"batch frame {fi}")
+                     f"batch frame {fi}", pool=pool)
+    pool.check()
     s.close()
 
 

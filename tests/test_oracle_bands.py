@@ -21,16 +21,16 @@ def test_band_rate_of_small_frames_seeds_0_999():
         n += o["ambig"].size
     rate = banded / n
     print(f"banded {banded} of {n}: {rate:.2e}")
-    # measured 4.2e-4 (1189 of 2 806 000)
+    # measured 1.0e-4 (284 of 2 806 000)
     assert 0 < rate <= 1e-3
-    assert banded == 1189
+    assert banded == 284
 
 
 def test_bands_are_narrow():
     """The widths are the stated ones (reach 1e-4 m, landing 1e-5 m,
-    crossing 1e-5 s / 1e-5 m, margin 1e-3 s)."""
-    assert O.DEFAULT_BANDS == dict(eps_reach=1e-4, eps_land=1e-5, eps_cross_t=1e-5,
-                                   eps_cross_s=1e-5, eps_margin=1e-3)
+    crossing 2e-6 s / 2e-6 m, margin 1e-3 s)."""
+    assert O.DEFAULT_BANDS == dict(eps_reach=1e-4, eps_land=1e-5, eps_cross_t=2e-6,
+                                   eps_cross_s=2e-6, eps_margin=1e-3)
     # a map with the bands switched off marks nothing
     p = Params(n_samples=64).as_f32()
     o = O.search_frame(config_small(3), p, bands=False)
