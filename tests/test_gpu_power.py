@@ -37,8 +37,11 @@ def _check(p, f, out, v0, i, off, n):
     v = v0[sl].cpu().numpy().astype(np.float64)
     amb = o["ambig"] > 0
     # where the speed is clamped the margin field can be flat near the 0.1 s
-    # threshold, so its band covers more points (1.5 % on one 5 cm window)
-    assert amb.mean() < 3e-2, amb.mean()
+    # threshold, so its band covers more points (1.48 % on one 5 cm window,
+    # the largest share measured on this file's frames; the cap is twice
+    # that); the reach / landing / crossing bands alone stay under 1e-3
+    assert amb.mean() <= 3e-2, amb.mean()
+    assert ((o["ambig"].astype(np.int64) & ~O.AMB_MARGIN) != 0).mean() <= 1e-3
     ok = ~amb
     np.testing.assert_allclose(v, o["v0"], rtol=1e-5, atol=0)
     assert (mask[ok] == o["mask"][ok]).all()

@@ -21,6 +21,11 @@ torch = pytest.importorskip("torch")
 
 W_TIME, W_REFR = 0.05, 0.1
 BANDS = dict(eps_reach=1e-5)
+# Share of (direction, variant) entries in the oracle's bands: at most twice
+# the largest share measured on this file's frames (1.95e-3, margin band
+# included), and the reach / landing / crossing bands alone at most 1e-3.
+AMB_CAP = 4e-3
+AMB_CAP_NONMARGIN = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +73,8 @@ def _close_inf(a, b, tol):
 def _compare(p, f, g, n_dirs):
     o = O.ray_search(f, p, n_dirs, W_TIME, W_REFR, bands=True, **BANDS)
     amb = o["ambig"] > 0
-    assert amb.mean() < 5e-3, amb.mean()
+    assert amb.mean() <= AMB_CAP, amb.mean()
+    assert ((o["ambig"].astype(np.int64) & ~O.AMB_MARGIN) != 0).mean() <= AMB_CAP_NONMARGIN
     ok = ~amb
     assert (g["mask"][ok] == o["mask"][ok]).all()
     for key, tol in (("t_team", 1e-4), ("t_opp", 1e-4), ("s_recv", 1e-5)):

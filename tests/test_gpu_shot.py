@@ -39,10 +39,13 @@ def _close(a, b, tol):
     return bool((np.abs(a[~ia] - b[~ib]) <= tol).all())
 
 
-def _compare(g, o, max_amb=3e-2):
-    """g: SHOT_DT records; o: oracle dict of arrays (same order)."""
+def _compare(g, o, max_amb=2.2e-3):
+    """g: SHOT_DT records; o: oracle dict of arrays (same order).  The banded
+    share is capped at twice the largest measured on this file's maps
+    (1.07e-3); the few single-record comparisons take no band at all."""
     amb = o["ambig"]
     assert (amb != 0).mean() <= max_amb, (amb != 0).mean()
+    assert ((amb.astype(np.int64) & ~O.AMB_MARGIN) != 0).mean() <= 1e-3
     ang_ok = (amb & O.AMB_ANGLE) == 0
     reach_ok = (amb & O.AMB_REACH) == 0
     ok = amb == 0
@@ -99,7 +102,7 @@ def test_shot_map_full_field(B, seed):
     _compare(g, o)
     gb = B.shots_host(ball)[:1]
     ob = _stack([O.shot(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)])
-    _compare(gb, ob, max_amb=1.0)
+    _compare(gb, ob, max_amb=0.0)
     assert 0 < g["shoot"].sum() < 2806
     s.close()
 
@@ -156,7 +159,7 @@ def test_shot_edge_cases_and_invalid_arguments(B):
     g = B.shots_host(ball)[:len(frames)]
     o = _stack([O.shot(f, p, v_shot=V_SHOT, min_angle=MIN_ANGLE, margin_s=MARGIN, bands=True)
                 for f in frames])
-    _compare(g, o, max_amb=1.0)
+    _compare(g, o, max_amb=0.0)
     assert np.isinf(g["slack"][0]) and g["gap"][1] == 0 and g["shoot"][1] == 0
     for args in ((0.0, MIN_ANGLE, MARGIN), (V_SHOT, -0.1, MARGIN), (V_SHOT, float("nan"), MARGIN),
                  (V_SHOT, MIN_ANGLE, -1.0), (float("inf"), MIN_ANGLE, MARGIN)):
