@@ -158,6 +158,32 @@ int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
                       const dpps_variant *variants, const dpps_outputs *out,
                       void *hip_stream);
 
+/* Size in bytes of the fixed device array behind dpps_search_batch_noalloc. */
+#define DPPS_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* For callers that cannot allocate while they run (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * search as dpps_search_batch, with the same kernels and outputs, that calls
+ * no hipMalloc, hipFree, hipHostMalloc or other allocating routine.  Its
+ * device state (the frames' tables, the tile list, one best record per tile
+ * and the persistent work counter) lives in one fixed array of
+ * DPPS_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on
+ * holds until the process ends; the tables are staged through host storage
+ * and a pinned buffer that dpps_create reserved.  The caller passes the host
+ * inputs (read during the call) and the device outputs; out->best is
+ * required.  A request whose tables and tile records do not fit the array
+ * (a few hundred thousand points at 8 points per tile, e.g. one 5 cm full
+ * frame) fails with DPPS_E_BUDGET before anything is copied or launched.
+ * Asynchronous on `hip_stream` (NULL: the context's stream); results are
+ * valid once the stream has completed.  Every call on one GPU, from any
+ * context, shares that GPU's array, which keeps the last call's contents
+ * (the work counter is cleared on the stream at the start of each call):
+ * calls that overlap on one GPU race, so callers serialise them. */
+int dpps_search_batch_noalloc(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
+                              const dpps_robot *robots, const dpps_window *windows,
+                              const dpps_variant *variants, const dpps_outputs *out,
+                              void *hip_stream);
+
 /* Device-resident batches: dpps_batch_create validates the frames, builds the
  * tile list and copies everything to device memory owned by the batch
  * (synchronous).  dpps_batch_run only launches (inputs already in HBM);

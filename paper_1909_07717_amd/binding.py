@@ -125,6 +125,8 @@ def lib():
         L.dpps_layout.argtypes = [C.POINTER(Params_C), i32, vp, vp, C.POINTER(i64)]
         L.dpps_search.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
         L.dpps_search_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
+        L.dpps_search_batch_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Outputs_C),
+                                                vp]
         L.dpps_batch_create.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(vp)]
         L.dpps_batch_set_robots.argtypes = [vp, vp, vp, vp]
         L.dpps_batch_run.argtypes = [vp, vp, C.POINTER(Outputs_C), vp, C.c_int]
@@ -533,6 +535,17 @@ class Searcher:
                                        _ptr(pk.windows), _ptr(pk.variants), C.byref(oc),
                                        _stream_ptr(stream)))
         return pk, out
+
+    def search_batch_noalloc(self, frames, out, stream=None):
+        """search_batch with the library's fixed device array as its only
+        device state (no allocation in the call); `out` is caller-owned."""
+        pk = frames if isinstance(frames, Packed) else pack(frames, self.params, self.out_flags)
+        oc = out.c()
+        _check(lib().dpps_search_batch_noalloc(self.h, len(pk.frames), _ptr(pk.frames),
+                                               _ptr(pk.robots), _ptr(pk.windows),
+                                               _ptr(pk.variants), C.byref(oc),
+                                               _stream_ptr(stream)))
+        return pk
 
     def batch(self, frames) -> "Batch":
         pk = frames if isinstance(frames, Packed) else pack(frames, self.params, self.out_flags)

@@ -29,6 +29,7 @@ COMMON = [
 SOURCES = {
     "dpps_api.hip": [],
     "dpps_kernels.hip": ["-Xarch_device", "-fno-honor-nans", "-Xarch_device", "-mno-amdgpu-ieee"],
+    "dpps_noalloc.hip": [],
     "mlp_api.hip": [],
     "mlp_kernels.hip": [],
 }

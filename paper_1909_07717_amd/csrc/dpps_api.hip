@@ -502,6 +502,12 @@ int dpps_create(dpps_ctx **out, const dpps_params *p, int device, void *hip_stre
         dpps_destroy(c);
         return fail(DPPS_E_DEVICE, "hipEventCreate failed");
     }
+    rc = noalloc_setup(c);
+    if (rc) {
+        const std::string msg = dpps_last_error();
+        dpps_destroy(c);
+        return fail(rc, "%s", msg.c_str());
+    }
     *out = c;
     return DPPS_OK;
 }
@@ -527,6 +533,7 @@ void dpps_destroy(dpps_ctx *c)
     batch_free_device(&c->shots);
     batch_free_device(&c->runs);
     if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
+    noalloc_release(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->pinned_best) (void)hipHostFree(c->pinned_best);
     if (c->staged) (void)hipEventDestroy(c->staged);

@@ -1556,6 +1556,22 @@ int launch_run(const RunArgs &a, void *stream)
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Clears n words (one thread each): a kernel rather than a memset node, so
+// that a caller may capture it in a graph.
+__global__ void __launch_bounds__(64) zero_words_kernel(uint32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+int launch_zero_words(uint32_t *p, int n, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream,
+                       p, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                   void *ev_stop)
 {

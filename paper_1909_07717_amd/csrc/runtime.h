@@ -104,6 +104,13 @@ struct dpps_ctx {
     // optional ring of event pairs bracketing the search kernel of each run
     std::vector<hipEvent_t> ring0, ring1;
     int ring_used = 0;
+    // dpps_search_batch_noalloc: the device's fixed array (its address on
+    // this context's device), host tables reserved for its largest request,
+    // and a pinned staging buffer of its size, all set up by dpps_create
+    unsigned char *na_scratch = nullptr;
+    dpps_batch na;
+    void *na_pinned = nullptr;
+    hipEvent_t na_staged = nullptr;  // na_pinned consumed by the last copy
 };
 
 // Sizes of the table section of the arena.
@@ -124,6 +131,9 @@ int stage_batch(dpps_ctx *c, dpps_batch *b, int32_t n_frames, const dpps_frame *
                 const dpps_robot *robots, const dpps_window *windows,
                 const dpps_variant *variants, hipStream_t st);
 int stage_tables(dpps_ctx *c, dpps_batch *b, hipStream_t st);
+// Set up the fixed-array search on the context's (current) device.
+int noalloc_setup(dpps_ctx *c);
+void noalloc_release(dpps_ctx *c);
 // Copy n best records from device memory to h (host) after the work queued
 // on st, through the context's pinned buffer (no staging of pageable memory),
 // waiting on an event recorded after the copy.
