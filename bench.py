@@ -405,8 +405,8 @@ def serving_bench(duration: float, weights: str):
         if kind == "surrogate" and not os.path.exists(weights):
             out[kind] = None
             continue
-        st, _ = run_serving(kind, duration=duration, n_matches=64, slots=4, max_batch=64,
-                            weights=weights if kind == "surrogate" else None)
+        st, _, _ = run_serving(kind, duration=duration, n_matches=64, slots=4, max_batch=64,
+                               weights=weights if kind == "surrogate" else None)
         out[kind] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
     return out
 

@@ -142,6 +142,18 @@ void dpps_destroy(dpps_ctx *c);
 int dpps_layout(const dpps_params *p, int32_t n_frames, dpps_frame *frames,
                 const dpps_window *windows, int64_t *total);
 
+/* Device bytes the context's memory needs to hold one dpps_search_batch
+ * request of these frames with tile_points points per tile (0: 8): its
+ * tables, per-tile records and per-frame best records, without the
+ * caller-owned outputs.  Host-only.  A context's memory grows to a quarter
+ * above the largest request so far (rounded up to 64 KiB) when its budget
+ * allows, else to the request's size exactly. */
+int dpps_request_bytes(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
+                       const dpps_window *windows, int32_t tile_points, uint64_t *bytes);
+
+/* Device bytes the context holds now (the figure hbm_budget_bytes limits). */
+uint64_t dpps_device_bytes(const dpps_ctx *c);
+
 /* One frame, synchronous: copy the inputs, search, write the maps to the
  * device outputs and the best pass to *h_best (host).  out->best may be NULL
  * here (the context keeps a device record).  frame->out_off is honoured. */
@@ -172,8 +184,7 @@ int dpps_search_batch(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
  * and a pinned buffer that dpps_create reserved.  The caller passes the host
  * inputs (read during the call) and the device outputs; out->best is
  * required.  A request whose tables and tile records do not fit the array
- * (a few hundred thousand points at 8 points per tile, e.g. one 5 cm full
- * frame) fails with DPPS_E_BUDGET before anything is copied or launched.
+ * (about 10^6 points at 8 points per tile, or 24 full 5 cm frames) fails with DPPS_E_BUDGET before anything is copied or launched.
  * Asynchronous on `hip_stream` (NULL: the context's stream); results are
  * valid once the stream has completed.  Every call on one GPU, from any
  * context, shares that GPU's array, which keeps the last call's contents

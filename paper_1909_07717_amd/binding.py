@@ -123,6 +123,10 @@ def lib():
         L.dpps_destroy.argtypes = [vp]
         L.dpps_destroy.restype = None
         L.dpps_layout.argtypes = [C.POINTER(Params_C), i32, vp, vp, C.POINTER(i64)]
+        L.dpps_request_bytes.argtypes = [C.POINTER(Params_C), i32, vp, vp, i32,
+                                         C.POINTER(C.c_uint64)]
+        L.dpps_device_bytes.argtypes = [vp]
+        L.dpps_device_bytes.restype = C.c_uint64
         L.dpps_search.argtypes = [vp, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
         L.dpps_search_batch.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Outputs_C), vp]
         L.dpps_search_batch_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Outputs_C),
@@ -256,6 +260,16 @@ def _ptr(a):
     return None if a is None or a.size == 0 else a.ctypes.data
 
 
+def request_bytes(pk: Packed, p, tile_points: int = 0) -> int:
+    """Device bytes a search context needs for the request `pk` (host-only)."""
+    pc = params_c(p)
+    n = C.c_uint64()
+    wl = pk.windows if pk.windows.size else np.zeros(1, WINDOW_DT)
+    _check(lib().dpps_request_bytes(C.byref(pc), len(pk.frames), _ptr(pk.frames), _ptr(wl),
+                                    tile_points, C.byref(n)))
+    return int(n.value)
+
+
 def _tptr(t):
     return None if t is None else t.data_ptr()
 
@@ -379,6 +393,10 @@ class Searcher:
             self.close()
         except Exception:
             pass
+
+    def device_bytes(self) -> int:
+        """Device memory the context holds now."""
+        return int(lib().dpps_device_bytes(self.h))
 
     def set_launch(self, tile_points=0, waves=0, wg_per_cu=0):
         _check(lib().dpps_set_launch(self.h, tile_points, waves, wg_per_cu))

@@ -567,6 +567,45 @@ int dpps_layout(const dpps_params *p, int32_t n_frames, dpps_frame *frames,
     return DPPS_OK;
 }
 
+int dpps_request_bytes(const dpps_params *p, int32_t n_frames, const dpps_frame *frames,
+                       const dpps_window *windows, int32_t tile_points, uint64_t *bytes)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!bytes || n_frames < 0 || (n_frames > 0 && (!frames || !windows)))
+        return fail(DPPS_E_INVALID, "bad request-size arguments");
+    if (tile_points == 0) tile_points = 8;
+    if (tile_points < 1) return fail(DPPS_E_INVALID, "tile_points %d", tile_points);
+    int64_t nr = 0, nv = 0, nw = 0, nt = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const dpps_frame &F = frames[f];
+        if (F.n_team < 0 || F.n_opp < 0 || F.n_variants < 0 || F.n_windows < 0 || F.window_off < 0)
+            return fail(DPPS_E_INVALID, "frame %d: negative count or offset", f);
+        nr += F.n_team + F.n_opp;
+        nv += F.n_variants;
+        nw += F.n_windows;
+        for (int w = 0; w < F.n_windows; ++w) {
+            const dpps_window &W = windows[F.window_off + w];
+            if (W.nx < 0 || W.ny < 0) return fail(DPPS_E_INVALID, "frame %d: negative window", f);
+            nt += ((int64_t)W.nx * W.ny + tile_points - 1) / tile_points;
+        }
+    }
+    // the table arena (table_layout) and the record arena (batch_reserve)
+    size_t t = 0;
+    t = align_up(t + (size_t)n_frames * sizeof(FrameDev), 256);
+    t = align_up(t + (size_t)nr * sizeof(dpps_robot), 256);
+    t = align_up(t + (size_t)nv * sizeof(dpps_variant), 256);
+    t = align_up(t + (size_t)nw * sizeof(WinDev), 256);
+    t = align_up(t + (size_t)nt * sizeof(TileDev), 256);
+    if (t < 256) t = 256;
+    const size_t aux = 256 + align_up((size_t)(nt > 0 ? nt : 1) * sizeof(TileRec), 256) +
+                       (size_t)(n_frames > 0 ? n_frames : 1) * sizeof(dpps_best);
+    *bytes = (uint64_t)(t + aux);
+    return DPPS_OK;
+}
+
+uint64_t dpps_device_bytes(const dpps_ctx *c) { return c ? c->budget_used : 0; }
+
 int dpps_set_launch(dpps_ctx *c, int32_t tile_points, int32_t waves_per_wg, int32_t wg_per_cu)
 {
     if (!c) return fail(DPPS_E_INVALID, "ctx is NULL");

@@ -101,6 +101,7 @@ class Request:
     result: object = field(default=None, compare=False, repr=False)
     done: float = field(default=math.nan, compare=False)
     slot: int = field(default=-1, compare=False)
+    nbytes: int = field(default=-1, compare=False)  # device bytes (admission)
 
 
 def request_schedule(sim: MatchSim, duration: float):
@@ -116,7 +117,8 @@ def request_schedule(sim: MatchSim, duration: float):
     reqs = []
     for t, m in ev:
         sim.step(m)
-        reqs.append(Request(float(t), rid, m, sim.request_frame(m)))
+        f = sim.request_frame(m)
+        reqs.append(Request(float(t), rid, m, f, nbytes=request_bytes(f, sim.p)))
         rid += 1
     return reqs
 
@@ -125,13 +127,24 @@ def request_schedule(sim: MatchSim, duration: float):
 # executors
 # ---------------------------------------------------------------------------
 
-def request_bytes(frame: Frame, tile_points: int = 8) -> int:
-    """Device bytes a request needs in a slot (tables, tile records, best):
-    mirrors the library's arena layout closely enough for admission."""
-    pts = frame.n_points()
-    tiles = sum(math.ceil(w[3] * w[4] / tile_points) for w in frame.windows)
-    return (48 + 16 * (frame.n_team + frame.n_opp) + 40 * len(frame.windows)
-            + 8 * len(frame.variants) + 24 * tiles + 56 + 0 * pts)
+# bytes of one best record (dpps_best), the only output a served request writes
+BEST_BYTES = 56
+
+
+def request_bytes(frame: Frame, params: Params = Params(), tile_points: int = 8) -> int:
+    """Device bytes a request needs in a slot: the search library's own
+    figure for its tables, tile records and best record (dpps_request_bytes),
+    plus the record the executor writes out for it."""
+    from paper_1909_07717_amd import binding as B
+    return B.request_bytes(B.pack([frame], params.as_f32()), params.as_f32(), tile_points) + BEST_BYTES
+
+
+def library_budget(slot_budget: int) -> int:
+    """The search context's own device-memory cap for a slot that admits up
+    to slot_budget bytes of requests at once: its memory may grow a quarter
+    beyond the largest request and round up to 64 KiB in each of its two
+    regions, so the cap is a backstop the admitted batches never reach."""
+    return int(slot_budget * 1.25) + (1 << 18)
 
 
 class MockExecutor:
@@ -162,40 +175,45 @@ class MockExecutor:
 
 
 class ExactExecutor:
-    """One library context and stream; dpps_search_batch, best records only."""
+    """One library context and stream; dpps_search_batch, best records only.
+    The device best records, their pinned host copy and the completion event
+    are allocated once for max_batch requests."""
 
-    def __init__(self, params: Params, budget: int = 1 << 34, device: int = 0):
+    def __init__(self, params: Params, budget: int = 1 << 26, device: int = 0,
+                 max_batch: int = 64, library_cap: bool = True):
         import torch
 
         from paper_1909_07717_amd import binding as B
         self.B = B
         self.torch = torch
         self.stream = torch.cuda.Stream()
-        self.s = B.Searcher(params, device=device, budget=budget, stream=self.stream)
+        self.s = B.Searcher(params, device=device,
+                            budget=library_budget(budget) if library_cap else 0,
+                            stream=self.stream)
         self.budget = budget
+        self.max_batch = max_batch
         self.batch = None
-        self.event = None
-        self.out = None
-        self.host = None
+        self.sz = B.BEST_DT.itemsize
+        self.out = B.DeviceOutputs(0, max_batch, self.s.device, mask=False, score=False)
+        self.host = torch.empty(max_batch * self.sz, dtype=torch.uint8, pin_memory=True)
+        self.event = torch.cuda.Event()
 
     def start(self, batch, now):
-        B, torch = self.B, self.torch
-        frames = [r.frame for r in batch]
-        pk = B.pack(frames, self.s.params)
-        n = len(frames)
-        self.out = B.DeviceOutputs(0, n, self.s.device, mask=False, score=False)
-        self.host = torch.empty(n * B.BEST_DT.itemsize, dtype=torch.uint8, pin_memory=True)
+        torch = self.torch
+        n = len(batch)
+        assert n <= self.max_batch
+        pk = self.B.pack([r.frame for r in batch], self.s.params)
         self.s.search_batch(pk, out=self.out, stream=self.stream)
         with torch.cuda.stream(self.stream):
-            self.host.copy_(self.out.best, non_blocking=True)
-            self.event = torch.cuda.Event()
+            self.host[:n * self.sz].copy_(self.out.best[:n * self.sz], non_blocking=True)
             self.event.record(self.stream)
         self.batch = batch
 
     def poll(self, now):
         if self.batch is None or not self.event.query():
             return None
-        recs = np.frombuffer(self.host.numpy().tobytes(), self.B.BEST_DT)
+        n = len(self.batch)
+        recs = np.frombuffer(self.host[:n * self.sz].numpy().tobytes(), self.B.BEST_DT)
         out = [(r, recs[i].copy()) for i, r in enumerate(self.batch)]
         self.batch = None
         return out
@@ -203,6 +221,9 @@ class ExactExecutor:
     @property
     def idle(self):
         return self.batch is None
+
+    def device_bytes(self) -> int:
+        return self.s.device_bytes()
 
     def close(self):
         self.s.close()
@@ -214,14 +235,17 @@ class SurrogateExecutor(ExactExecutor):
     it as a follow-up, which this executor then serves with the exact search
     (in the same launch sequence as the next batch's proposals)."""
 
-    def __init__(self, params: Params, weights: str | None, max_batch: int, budget: int = 1 << 34,
+    def __init__(self, params: Params, weights: str | None, max_batch: int, budget: int = 1 << 26,
                  k: int = 64, device: int = 0):
-        super().__init__(params, budget, device)
+        # the network's memory counts against the context, not the slot
+        super().__init__(params, budget, device, max_batch, library_cap=False)
         self.k = k
         self.net = self.B.Mlp(self.s, max_batch, max_k=k, seed=0)
         if weights:
             from paper_1909_07717_amd.surrogate import load_checkpoint
             self.net.set_params(load_checkpoint(weights)["params"])
+        self.prop = self.torch.empty(max_batch * self.sz, dtype=self.torch.uint8,
+                                     device=self.s.device)
         self.n_primary = 0
 
     def start(self, batch, now):
@@ -229,22 +253,21 @@ class SurrogateExecutor(ExactExecutor):
         prim = [r for r in batch if r.kind != "followup"]
         foll = [r for r in batch if r.kind == "followup"]
         ordered = prim + foll
-        n = len(ordered)
-        self.host = torch.empty(n * B.BEST_DT.itemsize, dtype=torch.uint8, pin_memory=True)
-        sz = B.BEST_DT.itemsize
+        sz, npr = self.sz, len(prim)
+        assert len(ordered) <= self.max_batch
         with torch.cuda.stream(self.stream):
             if prim:
-                best, _ = self.net.search_frames(B.pack([r.frame for r in prim], self.s.params),
-                                                 k=self.k, fallback=False, stream=self.stream)
-                self.host[:len(prim) * sz].copy_(best, non_blocking=True)
+                self.net.search_frames(B.pack([r.frame for r in prim], self.s.params), k=self.k,
+                                       fallback=False, best=self.prop[:npr * sz],
+                                       stream=self.stream)
+                self.host[:npr * sz].copy_(self.prop[:npr * sz], non_blocking=True)
             if foll:
                 pk = B.pack([r.frame for r in foll], self.s.params)
-                self.out = B.DeviceOutputs(0, len(foll), self.s.device, mask=False, score=False)
                 self.s.search_batch(pk, out=self.out, stream=self.stream)
-                self.host[len(prim) * sz:].copy_(self.out.best, non_blocking=True)
-            self.event = torch.cuda.Event()
+                self.host[npr * sz:len(ordered) * sz].copy_(self.out.best[:len(foll) * sz],
+                                                           non_blocking=True)
             self.event.record(self.stream)
-        self.n_primary = len(prim)
+        self.n_primary = npr
         self.batch = ordered
 
     def poll(self, now):
@@ -275,13 +298,15 @@ class Scheduler:
         self.admitted = set()
         self.followups = 0
         self.max_queue = 0
+        self.budget_cuts = 0      # batches closed by the budget with requests waiting
+        self.batches = []         # (slot, requests, admitted bytes) of every batch
 
     def _admit(self, si, now):
         ex = self.slots[si]
         batch, used = [], 0
         while self.queue and len(batch) < self.max_batch:
             r = self.queue[0]
-            b = request_bytes(r.frame)
+            b = r.nbytes if r.nbytes >= 0 else request_bytes(r.frame)
             if b > ex.budget:
                 # can never fit: fail it rather than block the queue
                 self.queue.popleft()
@@ -289,6 +314,7 @@ class Scheduler:
                 self.done.append(r)
                 continue
             if used + b > ex.budget:
+                self.budget_cuts += 1
                 break
             self.queue.popleft()
             assert r.rid not in self.admitted or r.kind == "followup"
@@ -298,6 +324,7 @@ class Scheduler:
             used += b
         if batch:
             self.inflight_bytes[si] = used
+            self.batches.append((si, len(batch), used))
             ex.start(batch, now)
 
     def run(self, requests, clock=None, sleep=None, realtime=True, horizon=None):
@@ -324,7 +351,8 @@ class Scheduler:
                 for r, out in res:
                     if out is None:
                         # no feasible proposal: back to the queue for the exact path
-                        f = Request(r.arrival, r.rid, r.match, r.frame, "followup")
+                        f = Request(r.arrival, r.rid, r.match, r.frame, "followup",
+                                    nbytes=r.nbytes)
                         self.followups += 1
                         self.queue.appendleft(f)
                         continue
@@ -356,23 +384,44 @@ def latency_stats(done):
             "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max())}
 
 
+def warm_batch(sim_params: Params, n: int, budget: int):
+    """Requests of the largest kind (5 cm whole field, 16 speeds, 8v8) that a
+    slot admits at once: serving them first grows every slot's memory to
+    what any later batch needs, so no allocation happens while serving."""
+    from paper_1909_07717_amd.framegen import random_frame
+    f = random_frame(np.random.default_rng(12345), 8, 8)
+    f.windows = [full_window(0.05)]
+    f.variants = variants_for(speeds_linear(16), flat=True, chip=False)
+    b = request_bytes(f, sim_params)
+    k = max(1, min(n, budget // b))
+    return [Request(0.0, -1 - i, 0, f, nbytes=b) for i in range(k)]
+
+
 def run_serving(kind: str = "exact", duration: float = 1.0, n_matches: int = 64, slots: int = 4,
                 max_batch: int = 64, weights: str | None = None, seed: int = 0,
-                budget: int = 1 << 34, params: Params | None = None):
+                budget: int = 1 << 26, params: Params | None = None):
     """Serve `duration` seconds of `n_matches` simulated matches on the GPU in
-    real time; returns (stats, done requests)."""
+    real time; returns (stats, done requests, scheduler).  `budget` is each
+    slot's device-memory budget for the requests it holds at once."""
     import torch
 
     p = params or Params(n_samples=128).as_f32()
-    reqs = request_schedule(MatchSim(n_matches, seed=seed), duration)
+    reqs = request_schedule(MatchSim(n_matches, seed=seed, params=p), duration)
     if kind == "exact":
-        ex = [ExactExecutor(p, budget) for _ in range(slots)]
+        ex = [ExactExecutor(p, budget, max_batch=max_batch) for _ in range(slots)]
     else:
         ex = [SurrogateExecutor(p, weights, max_batch, budget) for _ in range(slots)]
-    # warm every slot once (first launches compile nothing but allocate)
-    warm = Scheduler(ex, max_batch=max_batch)
-    warm.run([Request(0.0, -1 - i, 0, reqs[i].frame) for i in range(min(slots, len(reqs)))],
-             realtime=True)
+    # warm every slot with its largest admissible batch (device memory grows
+    # here, not while serving), the surrogate path's follow-up search included
+    for e in ex:
+        w = warm_batch(p, max_batch, budget)
+        if kind != "exact":
+            w = w + [Request(0.0, -1000 - i, 0, r.frame, "followup", nbytes=r.nbytes)
+                     for i, r in enumerate(w)]
+            w = w[:max_batch]
+        e.start(w, 0.0)
+        while e.poll(0.0) is None:
+            pass
     torch.cuda.synchronize()
     sch = Scheduler(ex, max_batch=max_batch)
     t0 = time.perf_counter()
@@ -382,8 +431,11 @@ def run_serving(kind: str = "exact", duration: float = 1.0, n_matches: int = 64,
     st.update({"kind": kind, "requests": len(reqs), "wall_s": wall, "duration_s": duration,
                "frames_per_s": len(done) / wall, "offered_per_s": len(reqs) / duration,
                "slots": slots, "max_batch": max_batch, "followups": sch.followups,
-               "max_queue": sch.max_queue,
+               "max_queue": sch.max_queue, "budget_bytes": budget,
+               "budget_cuts": sch.budget_cuts, "batches": len(sch.batches),
+               "max_batch_bytes": max((b for _, _, b in sch.batches), default=0),
+               "slot_device_bytes": [e.device_bytes() for e in ex],
                "evals": int(sum(r.frame.n_evals() for r in reqs))})
     for e in ex:
         e.close()
-    return st, done
+    return st, done, sch
