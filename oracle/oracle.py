@@ -15,19 +15,21 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+DEFAULT_LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB selects another build (e.g. one with sanitizers), loaded as is
+LIB = os.environ.get("ORACLE_LIB") or DEFAULT_LIB
 
 AMB_REACH, AMB_LAND, AMB_CROSS, AMB_MARGIN, AMB_ANGLE, AMB_RUN = 1, 2, 4, 8, 16, 32
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+    if force or not os.path.exists(DEFAULT_LIB) or os.path.getmtime(DEFAULT_LIB) < os.path.getmtime(SRC):
+        tmp = DEFAULT_LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC",
                                "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, DEFAULT_LIB)
+    return DEFAULT_LIB
 
 
 class OrcParams(C.Structure):
@@ -102,7 +104,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.environ.get("ORACLE_LIB") and (
+                not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build(force=True)
         L = C.CDLL(LIB)
         d, i32, i64 = C.c_double, C.c_int32, C.c_int64

@@ -63,8 +63,10 @@ def _run(cmd, verbose):
     return out
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    """Compile every source and link libdpps.so (always recompiles)."""
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None,
+          link_extra: list[str] | None = None) -> str:
+    """Compile every source and link libdpps.so, or `out` (always recompiles)."""
+    lib_path = out or LIB
     rev = [f'-DDPPS_KERNEL_REV="{kernel_rev()}"']
     with tempfile.TemporaryDirectory() as td:
         objs = []
@@ -73,10 +75,11 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
             _run([hipcc()] + COMMON + flags + rev + (extra or []) +
                  ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
             objs.append(obj)
-        tmp = LIB + ".tmp"
-        _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs, verbose)
-        os.replace(tmp, LIB)
-    return LIB
+        tmp = lib_path + ".tmp"
+        _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs +
+             (link_extra or []), verbose)
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

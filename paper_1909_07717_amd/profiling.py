@@ -145,12 +145,12 @@ def main():
 
         import torch
 
-        import bench
+        from paper_1909_07717_amd import rows_bench as R
         st = torch.cuda.Stream()
-        out = {"power": bench.power_bench(args.steps, st),
-               "shots": bench.shot_bench(4096, args.steps, 20, st),
-               "running": bench.run_bench(4096, args.steps, 20, st),
-               "rays": bench.ray_bench(512, args.steps, 20, st)}
+        out = {"power": R.power_bench(args.steps, st),
+               "shots": R.shot_bench(4096, args.steps, 20, st),
+               "running": R.run_bench(4096, args.steps, 20, st),
+               "rays": R.ray_bench(512, args.steps, 20, st)}
         print(json.dumps({k: v.get("workload", "") for k, v in out.items()}), flush=True)
     elif args.cmd == "latency":
         import json

@@ -14,6 +14,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1909_07717_amd.framegen import Params, config_small, random_frame
+from paper_1909_07717_amd.zones import front_zones
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -77,7 +78,7 @@ def test_running_points_front_zones(B):
     frames = []
     for _ in range(12):
         f = random_frame(rng, int(rng.integers(6, 9)), int(rng.integers(6, 9)), Params())
-        f.windows = B.front_zones(f.ball, p)
+        f.windows = front_zones(f.ball, p)
         frames.append(f)
     best, sc = _run(B, s, frames)
     zo = po = 0
@@ -109,12 +110,12 @@ def test_running_points_edge_cases_batch_and_errors(B):
     s = B.Searcher(p)
     alone = config_small(2)
     alone.opp = np.zeros((0, 4), np.float32)
-    alone.windows = B.front_zones(alone.ball, p)
+    alone.windows = front_zones(alone.ball, p)
     # a zone entirely inside the defense area: nothing to choose
     boxed = config_small(3)
     boxed.windows = [(np.float32(0.1), 111, 35, 8, 20)]
     near = config_small(4)
-    near.windows = B.front_zones(near.ball, p) + [(np.float32(0.2), 0, 0, 61, 46)]
+    near.windows = front_zones(near.ball, p) + [(np.float32(0.2), 0, 0, 61, 46)]
     frames = [alone, boxed, near]
     best, sc = _run(B, s, frames)
     zo = po = 0

@@ -4,8 +4,8 @@ valid window of the 0.1 m lattice, zones III/IV lie in front of I/II and on
 both sides of the long axis, and the zones follow the ball up the field."""
 import pytest
 
-from paper_1909_07717_amd import binding as B
 from paper_1909_07717_amd.framegen import Params
+from paper_1909_07717_amd.zones import front_zones
 
 
 def _x_range(z, p):
@@ -19,7 +19,7 @@ def _x_range(z, p):
 @pytest.mark.parametrize("by", [-4.5, 0.0, 3.2])
 def test_front_zones_are_valid_windows(bx, by):
     p = Params()
-    zones = B.front_zones((bx, by), p)
+    zones = front_zones((bx, by), p)
     assert len(zones) == 4
     nxa, nya = 121, 91
     for h, i0, j0, nx, ny in zones:
@@ -36,5 +36,5 @@ def test_front_zones_are_valid_windows(bx, by):
 
 def test_front_zones_follow_the_ball():
     p = Params()
-    starts = [_x_range(B.front_zones((bx, 0.0), p)[0], p)[0] for bx in (-4.0, -1.0, 1.0, 3.0)]
+    starts = [_x_range(front_zones((bx, 0.0), p)[0], p)[0] for bx in (-4.0, -1.0, 1.0, 3.0)]
     assert starts == sorted(starts) and starts[0] < starts[-1]
