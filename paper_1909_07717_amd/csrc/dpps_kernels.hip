@@ -280,27 +280,31 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
 
 // Inclusive prefix maximum over the 64 lanes of a wave (lane l gets the
 // maximum of lanes 0..l): four DPP row shifts give it within each row of 16
-// lanes (lanes without a source see -inf), then the row totals are carried
-// to the rows after them.
-template <int N>
-__device__ __forceinline__ float row_shr_max(float v)
+// lanes (lanes without a source see -inf), then two DPP row broadcasts carry
+// lane 15 into row 1 and row 3, and lane 31 into rows 2 and 3.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max(float v)
 {
-    const int u = __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v),
-                                              0x110 + N, 0xf, 0xf, false);
+    const int u = __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), CTRL,
+                                              ROW_MASK, 0xf, false);
     return fmaxf(v, __int_as_float(u));
 }
 
 __device__ __forceinline__ float wave_prefix_max(float v)
 {
-    v = row_shr_max<1>(v);
-    v = row_shr_max<2>(v);
-    v = row_shr_max<4>(v);
-    v = row_shr_max<8>(v);
-    const float c1 = readlane_f(v, 15);
-    const float c2 = fmaxf(c1, readlane_f(v, 31));
-    const float c3 = fmaxf(c2, readlane_f(v, 47));
-    const int l = lane_id();
-    return fmaxf(v, l >= 48 ? c3 : (l >= 32 ? c2 : (l >= 16 ? c1 : -INFINITY)));
+    v = dpp_max<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_max<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_max<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_max<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_max<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return dpp_max<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+}
+
+// Lane l gets lane l - 1's value, lane 0 gets -inf (DPP wave_shr:1).
+__device__ __forceinline__ float wave_shift_up(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v),
+                                                      0x138, 0xf, 0xf, false));
 }
 
 // Order this wave's accesses to its own LDS row.
@@ -328,9 +332,7 @@ __device__ __forceinline__ void store_running_max(const float (&vc)[KPL], float 
     run[0] = vc[0];
 #pragma unroll
     for (int q = 1; q < KPL; ++q) run[q] = fmaxf(run[q - 1], vc[q]);
-    const float incl = wave_prefix_max(run[KPL - 1]);
-    const float prev = __shfl_up(incl, 1, 64);
-    const float excl = l == 0 ? -INFINITY : prev;
+    const float excl = wave_shift_up(wave_prefix_max(run[KPL - 1]));
 #pragma unroll
     for (int q = 0; q < KPL; ++q) row[l * KPL + q] = fmaxf(excl, run[q]);
 }
@@ -339,19 +341,23 @@ template <int KPL>
 __device__ __forceinline__ void count_below(const float *rt, const float *ro, float v0, int &kt,
                                             int &ko)
 {
+    // a search over 2^n >= K entries, those past K read as the last one (the
+    // rows are non-decreasing, so the count only exceeds K when every entry
+    // is below v0, and is then clamped); no branches, both sides interleaved
     constexpr int K = KPL * 64;
-    constexpr int S0 = KPL >= 4 ? 256 : (KPL >= 2 ? 128 : 64);  // largest power of 2 <= K
+    constexpr int S0 = KPL >= 3 ? 128 : (KPL == 2 ? 64 : 32);  // half of 2^n
     int lt = 0, lo = 0;
 #pragma unroll
     for (int st = S0; st > 0; st >>= 1) {
-        const int it = lt + st - 1, io = lo + st - 1;
-        const float mt = rt[it < K ? it : K - 1];
-        const float mo = ro[io < K ? io : K - 1];
-        lt = (it < K && mt < v0) ? lt + st : lt;
-        lo = (io < K && mo < v0) ? lo + st : lo;
+        const float mt = rt[min(lt + st - 1, K - 1)];
+        const float mo = ro[min(lo + st - 1, K - 1)];
+        lt += mt < v0 ? st : 0;
+        lo += mo < v0 ? st : 0;
     }
-    kt = lt;
-    ko = lo;
+    const float mt = rt[min(lt, K - 1)];
+    const float mo = ro[min(lo, K - 1)];
+    kt = min(lt + (mt < v0 ? 1 : 0), K);
+    ko = min(lo + (mo < v0 ? 1 : 0), K);
 }
 
 // Kick speed at which the ball covers distance s in exactly time T (the
@@ -426,7 +432,16 @@ __device__ __forceinline__ double ball_time64(const VarConst &c, double s)
     double to = ph1 ? 0.0 : c.toff2;
     double x = s - so;
     double q = fmax(va * va - 2.0 * ac * x, 0.0);
-    return to + 2.0 * x / (va + sqrt(q));
+    // sqrt(q) and the division from the hardware estimates with two Newton
+    // steps each (relative error far below the float32 results need)
+    double y = __builtin_amdgcn_rsq(q);
+    y = y * fma(-0.5 * q, y * y, 1.5);
+    y = y * fma(-0.5 * q, y * y, 1.5);
+    const double den = va + (q > 0.0 ? q * y : 0.0);
+    double r = __builtin_amdgcn_rcp(den);
+    r = r * fma(-den, r, 2.0);
+    r = r * fma(-den, r, 2.0);
+    return fma(2.0 * x, r, to);
 }
 
 // Order-preserving map of a float's bits to an unsigned key (negative scores
@@ -614,13 +629,13 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
     sbip_crossings<KPL, POWER>(S, P, pr, pm, myv0, mytype, d, LA, my_kt, my_ko, d64,
                                (double)a.p_buffer, (double)a.p_vmin, (double)a.p_vmax, &v0);
     o_v0 = (float)v0;
-    // open goal angle (lanes = opponents)
-    const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
     // 4. finish: lanes = variants
     o_score = -INFINITY;
     o_feas = 0;
     o_tt = INFINITY;
     o_to = INFINITY;
+    bool feas = false;
+    double m = -INFINITY;
     if (l < n_var && (!POWER || v0 > 0.0)) {
         const VarConst c = POWER ? var_const(P, DPPS_FLAT, (float)v0) : S.vc[l];
         bool reach = d64 >= 1e-9 && d64 <= c.D && d64 >= c.sf_reach;
@@ -630,8 +645,15 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
             if (my_ko < K) to = ball_time64(c, (double)(my_ko + 1) * P.invK_d * d64);
         }
         bool tfin = tt < INFINITY;
-        double m = !tfin ? -INFINITY : (to < INFINITY ? to - tt : INFINITY);
-        bool feas = reach && tfin && m >= P.margin_d;
+        m = !tfin ? -INFINITY : (to < INFINITY ? to - tt : INFINITY);
+        feas = reach && tfin && m >= P.margin_d;
+        o_feas = feas;
+        o_tt = (float)tt;
+        o_to = (float)to;
+    }
+    // the open goal angle (lanes = opponents) enters only feasible scores
+    if (__ballot(feas)) {
+        const float ang = open_angle(S, P, cx, cy, n_op, n_tm);
         if (feas) {
             float gx = cx - P.goal_x;
             float dg = hsqrt(fmaf(gx, gx, cy * cy));
@@ -639,9 +661,6 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
             o_score = fmaf(P.w_ang_pi, ang, fmaf(P.w_dist, fmaf(-dg, P.inv_dist_norm, 1.0f),
                                                  P.w_margin * mc));
         }
-        o_feas = feas;
-        o_tt = (float)tt;
-        o_to = (float)to;
     }
 }
 
@@ -666,21 +685,26 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     float myv0 = 0.0f;
     int mytype = -1;
     int myvid = 0;  // the caller's index of lane l's variant
+    // Persistent workgroups take the tiles round-robin (no atomics) for all
+    // but the last one or two rounds, whose tiles they then pull from the
+    // work counter as they finish, so that the last tiles go to the
+    // workgroups that are free.
+    const int G = (int)gridDim.x;
+    const int n_static = a.persistent ? max(a.n_tiles / G - 1, 0) * G : 0;
     while (true) {
-        int t;
-        if (a.persistent) {
-            if (threadIdx.x == 0) s_tile = (int)atomicAdd(a.counter, 1u);
+        // the previous tile (its staged results and records) is finished
+        __syncthreads();
+        int t = (int)blockIdx.x + iter * G;
+        if (a.persistent && t >= n_static) {
+            if (threadIdx.x == 0) s_tile = n_static + (int)atomicAdd(a.counter, 1u);
             __syncthreads();
             t = s_tile;
-        } else {
-            t = blockIdx.x + iter * gridDim.x;
         }
-        ++iter;
         if (t >= a.n_tiles) break;
+        ++iter;
         const TileDev tile = a.tiles[t];
         const WinDev W = a.wins[tile.win];
         if (W.frame != cur_frame) {
-            __syncthreads();
             stage_frame(a.P, a.frames, a.robots, a.variants, W.frame, S);
             __syncthreads();
             cur_frame = W.frame;
@@ -688,8 +712,6 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             myv0 = l < nv ? S.v0[l] : 0.0f;
             mytype = l < nv ? S.type[l] : -1;
             myvid = l < nv ? S.vidx[l] : 0;
-        } else {
-            __syncthreads();
         }
         const int n_var = S.n_var;
         const int npts = min(TP, W.npts - tile.p0);
@@ -753,15 +775,20 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             O.wbest[w].pad = 0.0f;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            TileRec r = O.wbest[0];
-            for (int k = 1; k < nw; ++k)
-                if (O.wbest[k].key > r.key) r = O.wbest[k];
-            if (r.key == 0ull) {
-                r.t_team = INFINITY;
-                r.t_opp = INFINITY;
+        if (w == 0) {
+            // lanes < nw hold the waves' records; the largest key wins (keys
+            // of different waves differ unless both are 0)
+            const unsigned long long k = l < nw ? O.wbest[l].key : 0ull;
+            const unsigned long long tk = wave_max_u64(k);
+            const unsigned long long at = __ballot(k == tk && l < nw);
+            if (l == (int)__builtin_ctzll(at)) {
+                TileRec r = O.wbest[l];
+                if (r.key == 0ull) {
+                    r.t_team = INFINITY;
+                    r.t_opp = INFINITY;
+                }
+                a.tile_rec[t] = r;
             }
-            a.tile_rec[t] = r;
         }
         if (!reduced) {
             const int tot = n_var * npts;
