@@ -312,9 +312,12 @@ int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, vo
  * with the frame's variants; best pass per frame into d_best (device).  With
  * fallback != 0, frames where no proposed point is feasible, or whose best
  * re-scored pass scores below fallback_below (-INFINITY: infeasible frames
- * only), are searched exactly on the whole 5 cm lattice (synchronous) and
- * *n_fallback counts them.  The batch's own windows are not used.  A NaN
- * fallback_below is DPPS_E_INVALID. */
+ * only), are searched exactly on the whole 5 cm lattice; those frames are
+ * picked, and their tables built, on the device in stream order, so the
+ * call is asynchronous unless n_fallback (may be NULL) is given, in which
+ * case it returns once the stream has finished and *n_fallback counts them.
+ * The batch's own windows are not used.  A NaN fallback_below is
+ * DPPS_E_INVALID. */
 int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *d_best,
                           int fallback, float fallback_below, int32_t *n_fallback,
                           void *hip_stream);
@@ -324,7 +327,7 @@ int dpps_surrogate_search(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
  * requests allocates nothing.  n_frames must not exceed the network's
  * max_frames.  h_best (host, n_frames records, may be NULL): when given, the
  * best records are also written there and the call returns once the stream
- * has finished them (the fallback check reads them anyway). */
+ * has finished them. */
 int dpps_surrogate_search_frames(dpps_ctx *c, dpps_mlp *m, int32_t n_frames,
                                  const dpps_frame *frames, const dpps_robot *robots,
                                  const dpps_window *windows, const dpps_variant *variants,

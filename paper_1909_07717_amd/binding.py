@@ -721,12 +721,14 @@ class Mlp:
         return best, int(nfb.value)
 
     def search_frames(self, frames, k: int = 64, fallback: bool = True, best=None, stream=None,
-                      fallback_below: float = float("-inf"), host=None):
+                      fallback_below: float = float("-inf"), host=None, count: bool = True):
         """Surrogate search of host frames (a Packed request or framegen
         frames) through the context's own staging; same results as search()
         on a batch of the same frames.  With `host` (a numpy BEST_DT array of
         at least n_frames records) the records are also written there and
-        the call returns when they are final."""
+        the call returns when they are final.  With count=False (and no
+        `host`) the call does not wait for the stream and returns -1 as the
+        number of fallbacks."""
         import torch
         pk = frames if isinstance(frames, Packed) else pack(frames, self.s.params)
         nf = len(pk.frames)
@@ -738,8 +740,9 @@ class Mlp:
         _check(lib().dpps_surrogate_search_frames(
             self.s.h, self.h, nf, _ptr(pk.frames), _ptr(pk.robots), _ptr(pk.windows),
             _ptr(pk.variants), k, best.data_ptr(), int(fallback), float(fallback_below),
-            C.byref(nfb), host.ctypes.data if host is not None else None, _stream_ptr(stream)))
-        return best, int(nfb.value)
+            C.byref(nfb) if count else None, host.ctypes.data if host is not None else None,
+            _stream_ptr(stream)))
+        return best, int(nfb.value) if count else -1
 
 
 def pool_cells(fine, fine_nx: int, fine_ny: int, coarse_nx: int = 61, coarse_ny: int = 46,

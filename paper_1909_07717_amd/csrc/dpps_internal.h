@@ -70,6 +70,24 @@ struct FrameDev {
     int64_t ray_base;       // direction x variant search: first output element
 };
 
+// Fallback tables built on the device: frames whose best pass is not
+// feasible, or scores below `below`, get one window over the whole lattice
+// (nx x ny points at spacing h) in frames / wins; map[slot] is the frame,
+// *count the number of such frames.
+struct FallbackArgs {
+    const FrameDev *src;
+    const dpps_best *best;
+    int32_t n;
+    float below;
+    int32_t nx, ny;
+    float h;
+    int32_t tiles_per_frame;
+    FrameDev *frames;
+    WinDev *wins;
+    int32_t *map;
+    int32_t *count;
+};
+
 struct LaunchArgs {
     DevParams P;
     const FrameDev *frames;
@@ -92,6 +110,21 @@ struct LaunchArgs {
     float *t_team;
     float *t_opp;
     dpps_best *best;
+    // Tables built on the device (the exact fallback of the surrogate search):
+    // with tiles_per_frame > 0 the tiles are implicit (tile t covers window
+    // t / tiles_per_frame from point (t % tiles_per_frame) * tile_points),
+    // and with n_frames_dev the number of frames is read on the device
+    // (n_frames and n_tiles are then upper bounds); with best_map, frame f's
+    // best record goes to best[best_map[f]].
+    int32_t tiles_per_frame;
+    const int32_t *n_frames_dev;
+    const int32_t *best_map;
+    // with fb_on, the finalize kernel also appends each frame whose best pass
+    // needs the exact fallback to the fallback tables (slot by atomic count;
+    // fb.count must be 0 before the launch; fb.src is not used: the frame's
+    // own entry of `frames` is copied)
+    int32_t fb_on;
+    FallbackArgs fb;
 };
 
 // Best pass of one tile of the direction x variant search.

@@ -690,7 +690,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     // work counter as they finish, so that the last tiles go to the
     // workgroups that are free.
     const int G = (int)gridDim.x;
-    const int n_static = a.persistent ? max(a.n_tiles / G - 1, 0) * G : 0;
+    const int n_tiles = a.n_frames_dev ? *a.n_frames_dev * a.tiles_per_frame : a.n_tiles;
+    const int n_static = a.persistent ? max(n_tiles / G - 1, 0) * G : 0;
     while (true) {
         // the previous tile (its staged results and records) is finished
         __syncthreads();
@@ -700,9 +701,15 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             __syncthreads();
             t = s_tile;
         }
-        if (t >= a.n_tiles) break;
+        if (t >= n_tiles) break;
         ++iter;
-        const TileDev tile = a.tiles[t];
+        TileDev tile;
+        if (a.tiles_per_frame > 0) {
+            tile.win = t / a.tiles_per_frame;
+            tile.p0 = (t - tile.win * a.tiles_per_frame) * TP;
+        } else {
+            tile = a.tiles[t];
+        }
         const WinDev W = a.wins[tile.win];
         if (W.frame != cur_frame) {
             stage_frame(a.P, a.frames, a.robots, a.variants, W.frame, S);
@@ -811,6 +818,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
     if (f == 0 && tid == 0 && a.counter) *a.counter = 0u;
+    if (a.n_frames_dev && f >= *a.n_frames_dev) return;
     const FrameDev F = a.frames[f];
     TileRec r;
     r.key = 0ull;
@@ -882,8 +890,33 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
         b.t_opp = bestr.t_opp;
         b.t_ball = (float)ball_time64(c, sqrt(ex64 * ex64 + ey64 * ey64));
     }
-    a.best[f] = b;
+    a.best[a.best_map ? a.best_map[f] : f] = b;
+    if (a.fb_on && (!b.found || b.score < a.fb.below)) {
+        // this frame takes the exact fallback: one window over the whole lattice
+        const int slot = atomicAdd(a.fb.count, 1);
+        FrameDev G = F;
+        G.n_windows = 1;
+        G.win_off = slot;
+        G.tile_begin = slot * a.fb.tiles_per_frame;
+        G.tile_count = a.fb.tiles_per_frame;
+        a.fb.frames[slot] = G;
+        WinDev V;
+        V.h = a.fb.h;
+        V.i0 = 0;
+        V.j0 = 0;
+        V.nx = a.fb.nx;
+        V.ny = a.fb.ny;
+        V.halfNx = 0.5f * (float)(a.fb.nx - 1);
+        V.halfNy = 0.5f * (float)(a.fb.ny - 1);
+        V.frame = slot;
+        V.npts = a.fb.nx * a.fb.ny;
+        V.elem_base = 0;
+        V.out_base = 0;
+        a.fb.wins[slot] = V;
+        a.fb.map[slot] = f;
+    }
 }
+
 
 template <int KPL>
 static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream_t st,

@@ -62,7 +62,20 @@ struct dpps_mlp {
     TileRec *rrec;
     uint32_t *rcounter;
     int coarse_nx = 0, fine_nx = 0, fine_ny = 0;
+    // exact fallback built on the device: the frames whose proposals are all
+    // infeasible, their full-lattice windows, per-tile records, the frame
+    // map, the frame count and the work counter
+    FrameDev *ff;
+    WinDev *fw;
+    TileRec *frec;
+    int32_t *fmap;
+    int32_t *fcount;
+    uint32_t *fcounter;
+    int32_t *h_count = nullptr;  // pinned landing word of the fallback count
 };
+
+// Points per tile of the device-side exact fallback (its tiles are implicit).
+static constexpr int FB_TILE = 64;
 
 static size_t carve(size_t &off, size_t bytes)
 {
@@ -267,6 +280,13 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     size_t ort = carve(off, R * max_k * sizeof(TileDev));
     size_t orrec = carve(off, R * max_k * sizeof(TileRec));
     size_t octr = carve(off, 256);
+    const size_t fb_tpf = ((size_t)fnx * fny + FB_TILE - 1) / FB_TILE;
+    size_t off_ff = carve(off, R * sizeof(FrameDev));
+    size_t off_fw = carve(off, R * sizeof(WinDev));
+    size_t off_frec = carve(off, R * fb_tpf * sizeof(TileRec));
+    size_t off_fmap = carve(off, R * sizeof(int32_t));
+    size_t off_fcnt = carve(off, 256);
+    size_t off_fctr = carve(off, 256);
     if (c->p.hbm_budget_bytes && c->budget_used + off > c->p.hbm_budget_bytes) {
         delete m;
         return fail(DPPS_E_BUDGET, "network needs %zu device bytes", off);
@@ -303,9 +323,20 @@ int dpps_mlp_create(dpps_ctx *c, int32_t max_frames, int32_t max_k, uint64_t see
     m->rt = (TileDev *)(A + ort);
     m->rrec = (TileRec *)(A + orrec);
     m->rcounter = (uint32_t *)(A + octr);
+    m->ff = (FrameDev *)(A + off_ff);
+    m->fw = (WinDev *)(A + off_fw);
+    m->frec = (TileRec *)(A + off_frec);
+    m->fmap = (int32_t *)(A + off_fmap);
+    m->fcount = (int32_t *)(A + off_fcnt);
+    m->fcounter = (uint32_t *)(A + off_fctr);
     if (hipMemset(m->arena, 0, off) != hipSuccess) {
         dpps_mlp_destroy(m);
         return fail(DPPS_E_DEVICE, "hipMemset failed");
+    }
+    if (hipHostMalloc((void **)&m->h_count, 64, hipHostMallocDefault) != hipSuccess) {
+        m->h_count = nullptr;
+        dpps_mlp_destroy(m);
+        return fail(DPPS_E_NOMEM, "hipHostMalloc of the fallback count failed");
     }
     // He-uniform initialisation of the real weights (bound sqrt(6 / fan_in)),
     // zero biases; padding rows and columns stay zero
@@ -335,6 +366,7 @@ void dpps_mlp_destroy(dpps_mlp *m)
         (void)hipFree(m->arena);
         if (m->ctx) m->ctx->budget_used -= m->arena_bytes;
     }
+    if (m->h_count) (void)hipHostFree(m->h_count);
     delete m;
 }
 
@@ -499,7 +531,7 @@ int dpps_mlp_topk(dpps_mlp *m, int32_t n_frames, int32_t k, int32_t *d_cells, vo
 // Forward pass, top-k cells, re-score tables and the exact re-score of the
 // proposed windows (kernel launches only), best records into res.
 static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best *res,
-                   hipStream_t st)
+                   hipStream_t st, bool fallback = false, float fallback_below = -INFINITY)
 {
     const int nf = b->n_frames;
     int rc = forward(m, b, st, false);
@@ -514,6 +546,7 @@ static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best
     rt.frames = m->rf;
     rt.wins = m->rw;
     rt.tiles = m->rt;
+    rt.zero_word = m->fcount;  // the fallback list starts empty
     if (launch_topk(m->y, OUT_PAD, nf, OUT, k, m->cells, &rt, (void *)st))
         return fail(DPPS_E_DEVICE, "top-k launch failed");
     // exact re-score of the proposed windows: one 16-point tile per window
@@ -533,6 +566,20 @@ static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best
     a.counter = m->rcounter;
     a.tile_rec = m->rrec;
     a.best = res;
+    if (fallback) {
+        // frames without a feasible proposal (or below the threshold) are
+        // listed for the exact fallback by the re-score's finalize
+        a.fb_on = 1;
+        a.fb.below = fallback_below;
+        a.fb.nx = m->fine_nx;
+        a.fb.ny = m->fine_ny;
+        a.fb.h = (float)FINE_H;
+        a.fb.tiles_per_frame = (m->fine_nx * m->fine_ny + FB_TILE - 1) / FB_TILE;
+        a.fb.frames = m->ff;
+        a.fb.wins = m->fw;
+        a.fb.map = m->fmap;
+        a.fb.count = m->fcount;
+    }
     // few windows (small batches): eight waves share each window's 16
     // points, two points per wave, instead of the context's shape
     const int wv = (int64_t)a.n_tiles <= (int64_t)c->n_cu ? 8 : c->waves;
@@ -559,63 +606,47 @@ static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     const int nf = b->n_frames;
     if (n_fallback) *n_fallback = 0;
     if (nf == 0) return DPPS_OK;
-    int rc = propose(c, m, b, k, d_best, st);
+    int rc = propose(c, m, b, k, d_best, st, fallback != 0, fallback_below);
     if (rc) return rc;
     if (!fallback) return h_best ? read_best(c, h_best, d_best, nf, st) : DPPS_OK;
-    // frames whose proposals are all infeasible: exact search of the full
-    // fine lattice (the frame's own variants)
-    std::vector<dpps_best> own;
-    dpps_best *hb = h_best;
-    if (!hb) {
-        own.resize(nf);
-        hb = own.data();
+    // frames whose proposals are all infeasible (or score below the
+    // threshold), listed by the re-score's finalize: the exact search of the
+    // full fine lattice with the frame's own variants, its records placed on
+    // the device in stream order (no host round trip)
+    const int tpf = (m->fine_nx * m->fine_ny + FB_TILE - 1) / FB_TILE;
+    LaunchArgs a;
+    memset(&a, 0, sizeof a);
+    a.P = c->P;
+    a.P.out_flags = 0;
+    a.frames = m->ff;
+    a.robots = b->d_robots;
+    a.variants = b->d_variants;
+    a.wins = m->fw;
+    a.tiles = nullptr;
+    a.tiles_per_frame = tpf;
+    a.n_frames_dev = m->fcount;
+    a.best_map = m->fmap;
+    a.n_tiles = nf * tpf;
+    a.n_frames = nf;
+    a.tile_points = FB_TILE;
+    a.persistent = 1;
+    a.counter = m->fcounter;
+    a.tile_rec = m->frec;
+    a.best = d_best;
+    const int per_cu = search_occupancy(c->p.n_samples, c->waves);
+    const int64_t cap = (int64_t)c->n_cu * per_cu;
+    const int grid = (int)((int64_t)a.n_tiles < cap ? a.n_tiles : cap);
+    if (launch_search(a, c->waves, grid, (void *)st, nullptr, nullptr))
+        return fail(DPPS_E_DEVICE, "fallback search launch failed");
+    if (n_fallback)
+        HIP_OK(hipMemcpyAsync(m->h_count, m->fcount, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (h_best) {
+        rc = read_best(c, h_best, d_best, nf, st);
+        if (rc) return rc;
+    } else if (n_fallback) {
+        HIP_OK(hipStreamSynchronize(st));
     }
-    rc = read_best(c, hb, d_best, nf, st);
-    if (rc) return rc;
-    std::vector<int> redo;
-    for (int f = 0; f < nf; ++f)
-        if (!hb[f].found || hb[f].score < fallback_below) redo.push_back(f);
-    if (n_fallback) *n_fallback = (int32_t)redo.size();
-    if (redo.empty()) return DPPS_OK;
-    std::vector<dpps_frame> fr(redo.size());
-    std::vector<dpps_robot> rob;
-    std::vector<dpps_variant> var;
-    std::vector<dpps_window> win(redo.size());
-    for (size_t i = 0; i < redo.size(); ++i) {
-        const FrameDev &F = b->T.frames[redo[i]];
-        dpps_frame &G = fr[i];
-        memset(&G, 0, sizeof G);
-        G.n_team = F.n_team;
-        G.n_opp = F.n_opp;
-        G.passer = F.passer;
-        G.robot_off = (int32_t)rob.size();
-        G.n_windows = 1;
-        G.window_off = (int32_t)i;
-        G.n_variants = F.n_variants;
-        G.variant_off = (int32_t)var.size();
-        G.ball_x = F.ball_x;
-        G.ball_y = F.ball_y;
-        for (int r = 0; r < F.n_team + F.n_opp; ++r) rob.push_back(b->T.robots[F.robot_off + r]);
-        for (int v = 0; v < F.n_variants; ++v) var.push_back(b->T.variants[F.variant_off + v]);
-        win[i].h = (float)FINE_H;
-        win[i].i0 = 0;
-        win[i].j0 = 0;
-        win[i].nx = m->fine_nx;
-        win[i].ny = m->fine_ny;
-    }
-    // the context's own fallback batch: no allocation once it is large enough
-    dpps_batch *fb = &c->fallback;
-    rc = stage_batch(c, fb, (int32_t)redo.size(), fr.data(), rob.data(), win.data(), var.data(), st);
-    if (rc) return rc;
-    dpps_outputs o;
-    memset(&o, 0, sizeof o);
-    rc = run_batch(c, fb, &o, st, false);
-    if (rc) return rc;
-    for (size_t i = 0; i < redo.size(); ++i)
-        HIP_OK(hipMemcpyAsync(d_best + redo[i], fb->d_best + i, sizeof(dpps_best),
-                              hipMemcpyDeviceToDevice, st));
-    if (h_best) return read_best(c, h_best, d_best, nf, st);
-    HIP_OK(hipStreamSynchronize(st));
+    if (n_fallback) *n_fallback = *m->h_count;
     return DPPS_OK;
 }
 

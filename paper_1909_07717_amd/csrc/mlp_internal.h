@@ -53,6 +53,7 @@ struct RescoreTables {
     FrameDev *frames;
     WinDev *wins;
     TileDev *tiles;
+    int32_t *zero_word;     // cleared by the kernel (may be NULL)
 };
 // Top-k cells of each frame's map into out [n_frames][k]; with rt, also the
 // re-score tables of those cells.

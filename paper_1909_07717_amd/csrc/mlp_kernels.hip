@@ -787,6 +787,7 @@ __global__ void __launch_bounds__(TOPK_THREADS) topk_kernel(const float *__restr
         out[(size_t)f * k + t] = cell;
     }
     if (rt.frames) rescore_windows(rt, f, k, cell, scan_sh);
+    if (rt.zero_word && f == 0 && threadIdx.x == 0) *rt.zero_word = 0;
 }
 
 // host launchers -------------------------------------------------------------

@@ -14,9 +14,10 @@ staggered); requests carry the match's current robot states, a candidate grid
   the latency from the request's arrival to its result on the host.
 
 Executors: `ExactExecutor` (dpps_search_batch), `SurrogateExecutor` (network
-proposals re-scored exactly; a frame with no feasible proposal goes back to
-the queue as an exact follow-up request) and `MockExecutor` (CPU, injected
-delays) for the scheduler's own tests.
+proposals re-scored exactly, with the exact fallback on the device) and
+`MockExecutor` (CPU, injected delays) for the scheduler's own tests.  An
+executor may also hand a request back (result None) to be queued again as an
+exact follow-up.
 """
 from __future__ import annotations
 
@@ -230,10 +231,9 @@ class ExactExecutor:
 
 
 class SurrogateExecutor(ExactExecutor):
-    """Network proposals re-scored exactly (5 cm).  A primary request whose
-    proposals are all infeasible is returned as None, and the loop re-queues
-    it as a follow-up, which this executor then serves with the exact search
-    (in the same launch sequence as the next batch's proposals)."""
+    """Network proposals re-scored exactly (5 cm); a frame whose proposals
+    are all infeasible takes the exact search of its whole 5 cm lattice in
+    the same launch sequence (picked on the device, no host round trip)."""
 
     def __init__(self, params: Params, weights: str | None, max_batch: int, budget: int = 1 << 26,
                  k: int = 64, device: int = 0):
@@ -246,36 +246,18 @@ class SurrogateExecutor(ExactExecutor):
             self.net.set_params(load_checkpoint(weights)["params"])
         self.prop = self.torch.empty(max_batch * self.sz, dtype=self.torch.uint8,
                                      device=self.s.device)
-        self.n_primary = 0
 
     def start(self, batch, now):
         B, torch = self.B, self.torch
-        prim = [r for r in batch if r.kind != "followup"]
-        foll = [r for r in batch if r.kind == "followup"]
-        ordered = prim + foll
-        sz, npr = self.sz, len(prim)
-        assert len(ordered) <= self.max_batch
+        n, sz = len(batch), self.sz
+        assert n <= self.max_batch
         with torch.cuda.stream(self.stream):
-            if prim:
-                self.net.search_frames(B.pack([r.frame for r in prim], self.s.params), k=self.k,
-                                       fallback=False, best=self.prop[:npr * sz],
-                                       stream=self.stream)
-                self.host[:npr * sz].copy_(self.prop[:npr * sz], non_blocking=True)
-            if foll:
-                pk = B.pack([r.frame for r in foll], self.s.params)
-                self.s.search_batch(pk, out=self.out, stream=self.stream)
-                self.host[npr * sz:len(ordered) * sz].copy_(self.out.best[:len(foll) * sz],
-                                                           non_blocking=True)
+            self.net.search_frames(B.pack([r.frame for r in batch], self.s.params), k=self.k,
+                                   fallback=True, best=self.prop[:n * sz], stream=self.stream,
+                                   count=False)
+            self.host[:n * sz].copy_(self.prop[:n * sz], non_blocking=True)
             self.event.record(self.stream)
-        self.n_primary = npr
-        self.batch = ordered
-
-    def poll(self, now):
-        out = super().poll(now)
-        if out is None:
-            return None
-        return [(r, rec if (rec["found"] or i >= self.n_primary) else None)
-                for i, (r, rec) in enumerate(out)]
+        self.batch = batch
 
     def close(self):
         self.net.close()
@@ -412,14 +394,9 @@ def run_serving(kind: str = "exact", duration: float = 1.0, n_matches: int = 64,
     else:
         ex = [SurrogateExecutor(p, weights, max_batch, budget) for _ in range(slots)]
     # warm every slot with its largest admissible batch (device memory grows
-    # here, not while serving), the surrogate path's follow-up search included
+    # here, not while serving)
     for e in ex:
-        w = warm_batch(p, max_batch, budget)
-        if kind != "exact":
-            w = w + [Request(0.0, -1000 - i, 0, r.frame, "followup", nbytes=r.nbytes)
-                     for i, r in enumerate(w)]
-            w = w[:max_batch]
-        e.start(w, 0.0)
+        e.start(warm_batch(p, max_batch, budget), 0.0)
         while e.poll(0.0) is None:
             pass
     torch.cuda.synchronize()

@@ -307,6 +307,40 @@ def test_fallback_below_a_score_threshold(B):
     bt.close(); net.close(); s.close()
 
 
+def test_device_fallback_over_several_chunks_of_frames(B):
+    """300 frames (two chunks of the device's frame compaction), half of them
+    below the threshold: each fallback record equals the exact search of the
+    frame's whole 5 cm lattice, the others the raw proposals."""
+    s = B.Searcher(P)
+    frames = _frames(300, 900)
+    net = B.Mlp(s, 320, seed=4)
+    bt = s.batch(frames)
+    raw = B.best_records(net.search(bt, k=64, fallback=False)[0]).copy()
+    found = raw["found"] != 0
+    thr = float(np.median(raw["score"][found]))
+    got = B.best_records(net.search(bt, k=64, fallback=True, fallback_below=thr)[0])
+    fine = []
+    for f in frames:
+        g = f.copy()
+        g.windows = [full_window(0.05)]
+        fine.append(g)
+    _, ex = s.search_batch(fine, mask=False, score=False)
+    torch.cuda.synchronize()
+    ref = ex.best_host()
+    redo = ~found | (raw["score"] < thr)
+    assert 100 < int(redo.sum()) < 200
+    for i in range(len(frames)):
+        want = ref[i] if redo[i] else raw[i]
+        assert got[i].tobytes() == want.tobytes(), i
+    # asynchronous call (no fallback count): the same records
+    pk = B.pack(frames, P)
+    best = torch.empty(len(frames) * B.BEST_DT.itemsize, dtype=torch.uint8, device=s.device)
+    _, n = net.search_frames(pk, k=64, fallback=True, fallback_below=thr, best=best, count=False)
+    torch.cuda.synchronize()
+    assert n == -1 and B.best_records(best).tobytes() == got.tobytes()
+    bt.close(); net.close(); s.close()
+
+
 def test_training_resume_is_deterministic(B):
     s = B.Searcher(P)
     data = [_frames(64, 1000 + 64 * i) for i in range(6)]
