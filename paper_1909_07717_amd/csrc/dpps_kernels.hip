@@ -458,14 +458,29 @@ __device__ __forceinline__ float unordered_bits(uint32_t k)
     return __uint_as_float(k ^ ((k & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu));
 }
 
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xf,
+                                               false);
+    const unsigned long long y = ((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo;
+    return y > x ? y : x;
+}
+
+// Largest 64-bit key over the wave, on every lane: the DPP scan steps of
+// wave_prefix_max (lanes without a source see 0), then lane 63's total.
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long y = __shfl_xor(x, o, 64);
-        x = y > x ? y : x;
-    }
-    return x;
+    x = dpp_max_u64<0x111, 0xf>(x);
+    x = dpp_max_u64<0x112, 0xf>(x);
+    x = dpp_max_u64<0x114, 0xf>(x);
+    x = dpp_max_u64<0x118, 0xf>(x);
+    x = dpp_max_u64<0x142, 0xa>(x);
+    x = dpp_max_u64<0x143, 0xc>(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Open goal angle at c = (cx, cy) against the staged opponents; lanes are
@@ -950,15 +965,16 @@ __device__ __forceinline__ float row_newbcast(float v)
                                                       false));
 }
 
-// Open goal angle at up to four points at once: lane 16 g + o looks at
-// point g (its own cx, cy) and opponent o (at most 16 opponents).  The same
-// construction as open_angle within each group of 16 lanes; returns on every
-// lane the angle of its group's point.
-__device__ float open_angle4(const StageLDS &S, const DevParams &P, float cx, float cy, int n_op,
-                             int n_tm)
+// Open goal angle at up to 64 / GS points at once: lane GS g + o looks at
+// point g (its own cx, cy) and opponent o (GS = 16 for up to 16 opponents,
+// 8 for up to 8).  The same construction as open_angle within each group of
+// GS lanes; returns on every lane the angle of its group's point.
+template <int GS>
+__device__ float open_angle_groups(const StageLDS &S, const DevParams &P, float cx, float cy,
+                                   int n_op, int n_tm)
 {
     const int l = lane_id();
-    const int o = l & 15, base = l & 48;
+    const int o = l & (GS - 1), base = l & (64 - GS);
     const float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
     const float lo = atan2f(-P.half_goal_w - cy, dxg);
     const float hi = atan2f(P.half_goal_w - cy, dxg);
@@ -973,29 +989,80 @@ __device__ float open_angle4(const StageLDS &S, const DevParams &P, float cx, fl
     const float e = fminf(ang + al, hi);
     const bool has = valid && e > s;
     // each interval adds what the group's intervals sorted before it (by
-    // start, then index) have not covered; interval j of the group comes
-    // from lane j of the row by a DPP row broadcast (a start of +inf marks
-    // no interval)
+    // start, then index) have not covered; interval j of the group comes by
+    // a DPP row broadcast of lane j of the group's half of the 16-lane row
+    // (a start of +inf marks no interval)
     const float sh = has ? s : INFINITY;
+    const bool upper = GS == 8 && (l & 8) != 0;
     float M = -INFINITY;
-#define OA4_STEP(J)                                                      \
-    if (J < n_op) {                                                      \
-        const float sj = row_newbcast<J>(sh), ej = row_newbcast<J>(e);   \
-        const bool before = sj < sh || (sj == sh && J < o);              \
-        M = before ? fmaxf(M, ej) : M;                                   \
+#define OAG_STEP(J)                                                                   \
+    if (J < n_op && J < GS) {                                                         \
+        float sj = row_newbcast<J>(sh), ej = row_newbcast<J>(e);                      \
+        if (GS == 8) {                                                                \
+            const float su = row_newbcast<(J + 8) & 15>(sh);                          \
+            const float eu = row_newbcast<(J + 8) & 15>(e);                           \
+            sj = upper ? su : sj;                                                     \
+            ej = upper ? eu : ej;                                                     \
+        }                                                                             \
+        const bool before = sj < sh || (sj == sh && J < o);                           \
+        M = before ? fmaxf(M, ej) : M;                                                \
     }
-    OA4_STEP(0) OA4_STEP(1) OA4_STEP(2) OA4_STEP(3)
-    OA4_STEP(4) OA4_STEP(5) OA4_STEP(6) OA4_STEP(7)
-    OA4_STEP(8) OA4_STEP(9) OA4_STEP(10) OA4_STEP(11)
-    OA4_STEP(12) OA4_STEP(13) OA4_STEP(14) OA4_STEP(15)
-#undef OA4_STEP
+    OAG_STEP(0) OAG_STEP(1) OAG_STEP(2) OAG_STEP(3)
+    OAG_STEP(4) OAG_STEP(5) OAG_STEP(6) OAG_STEP(7)
+    OAG_STEP(8) OAG_STEP(9) OAG_STEP(10) OAG_STEP(11)
+    OAG_STEP(12) OAG_STEP(13) OAG_STEP(14) OAG_STEP(15)
+#undef OAG_STEP
     float c = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
     c += __shfl_xor(c, 1, 64);
     c += __shfl_xor(c, 2, 64);
     c += __shfl_xor(c, 4, 64);
-    c += __shfl_xor(c, 8, 64);
-    const bool gin = ((__ballot(inside) >> base) & 0xFFFFull) != 0ull;
+    if (GS == 16) c += __shfl_xor(c, 8, 64);
+    const unsigned long long gmask = GS == 16 ? 0xFFFFull : 0xFFull;
+    const bool gin = ((__ballot(inside) >> base) & gmask) != 0ull;
     return gin ? 0.0f : (hi - lo) - c;
+}
+
+// Open goal angles at the passing points of a direction's feasible variants
+// (lanes): a feasible lane whose passing sample differs from the previous
+// feasible lane's leads; the leaders' points go 64 / GS at a time through
+// open_angle_groups, and the other feasible lanes take their leader's angle.
+template <int GS>
+__device__ float leader_angles(const StageLDS &S, const DevParams &P, bool feas, int my_k,
+                               float px, float py, float bx, float by, int n_op, int n_tm)
+{
+    constexpr int NG = 64 / GS;
+    const int l = lane_id();
+    const unsigned long long fm = __ballot(feas);
+    const unsigned long long below = fm & ((1ull << l) - 1ull);
+    const int prevl = below ? 63 - __builtin_clzll(below) : 0;
+    const int kprev = __shfl(my_k, prevl, 64);
+    const bool lead = feas && (below == 0ull || kprev != my_k);
+    const unsigned long long lm = __ballot(lead);
+    float my_ang = 0.0f;
+    const int g = l / GS;
+    for (unsigned long long mm = lm; mm;) {
+        int lv[NG];
+        float cxg = bx, cyg = by;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            lv[q] = mm ? __builtin_ctzll(mm) : -1;
+            mm = mm ? mm & (mm - 1) : mm;
+            const float gx = lv[q] >= 0 ? readlane_f(px, lv[q]) : bx;
+            const float gy = lv[q] >= 0 ? readlane_f(py, lv[q]) : by;
+            cxg = g == q ? gx : cxg;
+            cyg = g == q ? gy : cyg;
+        }
+        const float a = open_angle_groups<GS>(S, P, cxg, cyg, n_op, n_tm);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const float aq = readlane_f(a, GS * q);
+            my_ang = (lv[q] >= 0 && l == lv[q]) ? aq : my_ang;
+        }
+    }
+    const unsigned long long upto = l == 63 ? lm : lm & ((2ull << l) - 1ull);
+    const int lead_l = upto ? 63 - __builtin_clzll(upto) : l;
+    const float la = __shfl(my_ang, lead_l, 64);
+    return feas ? la : 0.0f;
 }
 
 // Distance from the ball along (ux, uy) to the edge of the field (0 when the
@@ -1062,42 +1129,11 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
         px = bx + st * ux;
         py = by + st * uy;
     }
-    // open goal angle at each feasible passing point: a feasible lane whose
-    // passing sample differs from the previous feasible lane's leads; the
-    // leaders' points go four at a time through open_angle4, and the other
-    // feasible lanes take their leader's angle
-    const unsigned long long fm = __ballot(o.feas != 0);
-    const unsigned long long below = fm & ((1ull << l) - 1ull);
-    const int prevl = below ? 63 - __builtin_clzll(below) : 0;
-    const int kprev = __shfl(my_kt, prevl, 64);
-    const bool lead = o.feas && (below == 0ull || kprev != my_kt);
-    const unsigned long long lm = __ballot(lead);
-    const float pxf = (float)px, pyf = (float)py;
-    float my_ang = 0.0f;
-    for (unsigned long long mm = lm; mm;) {
-        int lv[4];
-        float gx4[4], gy4[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            lv[g] = mm ? __builtin_ctzll(mm) : -1;
-            mm = mm ? mm & (mm - 1) : mm;
-            gx4[g] = lv[g] >= 0 ? readlane_f(pxf, lv[g]) : (float)bx;
-            gy4[g] = lv[g] >= 0 ? readlane_f(pyf, lv[g]) : (float)by;
-        }
-        const int g = l >> 4;
-        const float cxg = g == 0 ? gx4[0] : (g == 1 ? gx4[1] : (g == 2 ? gx4[2] : gx4[3]));
-        const float cyg = g == 0 ? gy4[0] : (g == 1 ? gy4[1] : (g == 2 ? gy4[2] : gy4[3]));
-        const float a4 = open_angle4(S, P, cxg, cyg, n_op, n_tm);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float aq = readlane_f(a4, 16 * q);
-            my_ang = (lv[q] >= 0 && l == lv[q]) ? aq : my_ang;
-        }
-    }
-    const unsigned long long upto = l == 63 ? lm : lm & ((2ull << l) - 1ull);
-    const int lead_l = upto ? 63 - __builtin_clzll(upto) : l;
-    const float la = __shfl(my_ang, lead_l, 64);
-    my_ang = o.feas ? la : 0.0f;
+    // open goal angle at each feasible passing point
+    const float my_ang = n_op <= 8 ? leader_angles<8>(S, P, o.feas != 0, my_kt, (float)px, (float)py,
+                                                      (float)bx, (float)by, n_op, n_tm)
+                                   : leader_angles<16>(S, P, o.feas != 0, my_kt, (float)px,
+                                                       (float)py, (float)bx, (float)by, n_op, n_tm);
     if (o.feas) {
         const double gx = (double)P.goal_x - px, gy = -py;
         const float dg = (float)sqrt(gx * gx + gy * gy);
@@ -1154,10 +1190,14 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
         const int n_var = S.n_var;
         const int64_t base = a.frames[f].ray_base;
         const int nd = min(a.tile_dirs, a.n_dirs - tile.p0);
-        RayRec best;
-        best.key = 0ull;
-        best.t_team = best.t_opp = best.s_recv = INFINITY;
-        best.open_angle = best.refract = best.pad = 0.0f;
+        // the wave's best so far: its key in a uniform register, its record
+        // in the wave's LDS slot (written by the lane that holds it)
+        unsigned long long wbk = 0ull;
+        if (l == 0) {
+            WB[w].key = 0ull;
+            WB[w].t_team = WB[w].t_opp = WB[w].s_recv = INFINITY;
+            WB[w].open_angle = WB[w].refract = WB[w].pad = 0.0f;
+        }
         for (int slot = w; slot < nd; slot += nw) {
             const int d = tile.p0 + slot;
             const RayOut o = ray_direction<KPL>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0,
@@ -1171,37 +1211,28 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
                 if (a.t_opp) a.t_opp[e] = o.t_opp;
                 if (a.s_recv) a.s_recv[e] = o.s_recv;
             }
-            if (o.key > best.key) {
-                best.key = o.key;
-                best.t_team = o.t_team;
-                best.t_opp = o.t_opp;
-                best.s_recv = o.s_recv;
-                best.open_angle = o.open_angle;
-                best.refract = o.refract;
+            const unsigned long long dk = wave_max_u64(o.key);
+            if (dk > wbk) {
+                wbk = dk;
+                const int src = __builtin_ctzll(__ballot(o.key == dk));
+                if (l == src) {
+                    WB[w].key = dk;
+                    WB[w].t_team = o.t_team;
+                    WB[w].t_opp = o.t_opp;
+                    WB[w].s_recv = o.s_recv;
+                    WB[w].open_angle = o.open_angle;
+                    WB[w].refract = o.refract;
+                }
             }
         }
-        // the wave's best, then the tile's
-        const unsigned long long wk = wave_max_u64(best.key);
-        const unsigned long long who = __ballot(best.key == wk);
-        const int src = who ? __builtin_ctzll(who) : 0;
-        if (l == 0) WB[w].key = wk;
-        const float r0 = readlane_f(best.t_team, src), r1 = readlane_f(best.t_opp, src);
-        const float r2 = readlane_f(best.s_recv, src), r3 = readlane_f(best.open_angle, src);
-        const float r4 = readlane_f(best.refract, src);
-        if (l == 0) {
-            WB[w].t_team = r0;
-            WB[w].t_opp = r1;
-            WB[w].s_recv = r2;
-            WB[w].open_angle = r3;
-            WB[w].refract = r4;
-            WB[w].pad = 0.0f;
-        }
+        // the tile's best of the waves' records (keys of different waves
+        // differ unless both are 0)
         __syncthreads();
-        if (threadIdx.x == 0) {
-            RayRec r = WB[0];
-            for (int k = 1; k < nw; ++k)
-                if (WB[k].key > r.key) r = WB[k];
-            a.tile_rec[t] = r;
+        if (w == 0) {
+            const unsigned long long k = l < nw ? WB[l].key : 0ull;
+            const unsigned long long tk = wave_max_u64(k);
+            const unsigned long long at = __ballot(k == tk && l < nw);
+            if (l == (int)__builtin_ctzll(at)) a.tile_rec[t] = WB[l];
         }
     }
 }
