@@ -785,9 +785,15 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     int rc = build_tables(&c->p, n_frames, fr.data(), robots, &no_window, variants, c->tile_points,
                           b->T);
     if (rc) return rc;
-    // tiles of ray_tile_dirs directions of one frame; outputs frame by frame
-    // at least one direction per wave of a workgroup
-    const int td = c->ray_tile_dirs > c->waves ? c->ray_tile_dirs : c->waves;
+    // tiles of directions of one frame; outputs frame by frame.  A tile
+    // holds one direction per wave and up to ray_tile_dirs when there are
+    // enough directions to give every resident workgroup four such tiles (a
+    // single frame runs one direction per wave, for latency)
+    const int rw = c->ray_waves > 0 ? c->ray_waves : c->waves;
+    const int64_t ray_cap = (int64_t)c->n_cu * ray_occupancy(c->p.n_samples, rw);
+    const int64_t per_wg = (int64_t)n_frames * rp->n_dirs / (4 * ray_cap);
+    int td = (int)(per_wg < c->ray_tile_dirs ? per_wg : c->ray_tile_dirs) / rw * rw;
+    if (td < rw) td = rw;
     b->T.tiles.clear();
     int64_t base = 0;
     for (int32_t f = 0; f < n_frames; ++f) {
@@ -830,9 +836,8 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     a.t_opp = out->t_opp;
     a.s_recv = out->s_recv;
     a.best = out->best;
-    const int64_t cap = (int64_t)c->n_cu * ray_occupancy(c->p.n_samples, c->waves);
-    const int grid = (int)((int64_t)nt < cap ? (int64_t)nt : cap);
-    if (launch_ray(a, c->waves, grid, (void *)st)) return fail(DPPS_E_DEVICE, "ray launch failed");
+    const int grid = (int)((int64_t)nt < ray_cap ? (int64_t)nt : ray_cap);
+    if (launch_ray(a, rw, grid, (void *)st)) return fail(DPPS_E_DEVICE, "ray launch failed");
     return DPPS_OK;
 }
 

@@ -700,10 +700,10 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     float myv0 = 0.0f;
     int mytype = -1;
     int myvid = 0;  // the caller's index of lane l's variant
-    // Persistent workgroups take the tiles round-robin (no atomics) for all
-    // but the last one or two rounds, whose tiles they then pull from the
-    // work counter as they finish, so that the last tiles go to the
-    // workgroups that are free.
+    // Persistent workgroups take the tiles round-robin (no atomics; tiles of
+    // differing cost spread evenly) for all but the last one or two rounds,
+    // whose tiles they then pull from the work counter as they finish, so
+    // that the last tiles go to the workgroups that are free.
     const int G = (int)gridDim.x;
     const int n_tiles = a.n_frames_dev ? *a.n_frames_dev * a.tiles_per_frame : a.n_tiles;
     const int n_static = a.persistent ? max(n_tiles / G - 1, 0) * G : 0;
@@ -1168,15 +1168,26 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
     int cur_frame = -1;
     float myv0 = 0.0f;
     int mytype = -1, myvid = 0;
+    // a contiguous run of tiles per workgroup (consecutive tiles share a
+    // frame, so it is staged once per run) for all but the last one or two
+    // rounds' worth, then the work counter
+    const int G = (int)gridDim.x;
+    const int R = max(a.n_tiles / G - 1, 0);
+    const int n_static = R * G;
+    int iter = 0;
     while (true) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(a.counter, 1u);
-        __syncthreads();
-        const int t = s_tile;
+        __syncthreads();  // the previous tile is finished
+        int t = iter < R ? (int)blockIdx.x * R + iter : n_static;
+        if (t >= n_static) {
+            if (threadIdx.x == 0) s_tile = n_static + (int)atomicAdd(a.counter, 1u);
+            __syncthreads();
+            t = s_tile;
+        }
         if (t >= a.n_tiles) break;
+        ++iter;
         const TileDev tile = a.tiles[t];
         const int f = tile.win;
         if (f != cur_frame) {
-            __syncthreads();
             stage_frame(a.P, a.frames, a.robots, a.variants, f, S);
             __syncthreads();
             cur_frame = f;
@@ -1184,8 +1195,6 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
             myv0 = l < nv ? S.v0[l] : 0.0f;
             mytype = l < nv ? S.type[l] : -1;
             myvid = l < nv ? S.vidx[l] : 0;
-        } else {
-            __syncthreads();
         }
         const int n_var = S.n_var;
         const int64_t base = a.frames[f].ray_base;

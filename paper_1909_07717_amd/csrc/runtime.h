@@ -87,7 +87,8 @@ struct dpps_ctx {
     dpps_batch fallback;     // exact searches of surrogate frames without a feasible proposal
     dpps_batch rays;         // tables of dpps_ray_search
     DeviceArena ray_aux;     // its work counter and per-tile records
-    int ray_tile_dirs = 4;   // directions per tile of dpps_ray_search
+    int ray_tile_dirs = 32;  // directions per tile of dpps_ray_search
+    int ray_waves = 8;       // waves per workgroup of dpps_ray_search
     dpps_batch shots;        // tables of dpps_shot_decision
     int shot_tile = 16;      // window points per workgroup of the shot map
     int shot_waves = 4;      // waves per workgroup of the shot map
