@@ -236,9 +236,10 @@ int dpps_autotune(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, void *hip
 float dpps_last_kernel_ms(dpps_ctx *c);
 
 /* Kernel timing over many runs: dpps_timing_begin arms a ring of max_runs
- * event pairs; each later non-graph run records its search kernel into the
- * next pair (no host synchronisation); dpps_timing_end waits for them and
- * returns the summed kernel time and the number of runs recorded. */
+ * event pairs; each later non-graph run records its search kernel (for
+ * dpps_ray_search, its direction-sweep kernel) into the next pair (no host
+ * synchronisation); dpps_timing_end waits for them and returns the summed
+ * kernel time and the number of runs recorded. */
 int dpps_timing_begin(dpps_ctx *c, int32_t max_runs);
 int dpps_timing_end(dpps_ctx *c, float *total_ms, int32_t *n_runs);
 

@@ -837,7 +837,15 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     a.s_recv = out->s_recv;
     a.best = out->best;
     const int grid = (int)((int64_t)nt < ray_cap ? (int64_t)nt : ray_cap);
-    if (launch_ray(a, rw, grid, (void *)st)) return fail(DPPS_E_DEVICE, "ray launch failed");
+    // with a timing ring open (dpps_timing_begin), the ray kernel is timed
+    void *e0 = nullptr, *e1 = nullptr;
+    if (c->ring_used < (int)c->ring0.size()) {
+        e0 = (void *)c->ring0[c->ring_used];
+        e1 = (void *)c->ring1[c->ring_used];
+        ++c->ring_used;
+    }
+    if (launch_ray(a, rw, grid, (void *)st, e0, e1))
+        return fail(DPPS_E_DEVICE, "ray launch failed");
     return DPPS_OK;
 }
 

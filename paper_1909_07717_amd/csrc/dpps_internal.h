@@ -191,8 +191,10 @@ int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream,
 int launch_zero_words(uint32_t *p, int n, void *stream);
 // Resident workgroups per CU of the search kernel for this K and block size.
 int search_occupancy(int K, int waves_per_wg);
-// Direction x variant search (ray kernel then its finalize) on `stream`.
-int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream);
+// Direction x variant search (ray kernel then its finalize) on `stream`;
+// ev_start / ev_stop (hipEvent_t or NULL) bracket the ray kernel only.
+int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
+               void *ev_stop);
 int ray_occupancy(int K, int waves_per_wg);
 // Shooting decisions: the ball kernel, then (with a.map) the window kernel.
 int launch_shot(const ShotArgs &a, int waves_per_wg, void *stream);

@@ -1302,24 +1302,29 @@ __global__ void __launch_bounds__(256) ray_finalize_kernel(RayArgs a)
 }
 
 template <int KPL>
-static int launch_ray_kpl(const RayArgs &a, int waves_per_wg, int grid, hipStream_t st)
+static int launch_ray_kpl(const RayArgs &a, int waves_per_wg, int grid, hipStream_t st,
+                          hipEvent_t e0, hipEvent_t e1)
 {
+    if (e0) (void)hipEventRecord(e0, st);
     if (a.n_tiles > 0 && grid > 0)
         hipLaunchKernelGGL(ray_kernel<KPL>, dim3(grid), dim3(64 * waves_per_wg),
                            pm_bytes(KPL * 64, waves_per_wg), st, a);
+    if (e1) (void)hipEventRecord(e1, st);
     if (a.n_frames > 0)
         hipLaunchKernelGGL(ray_finalize_kernel, dim3(a.n_frames), dim3(256), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream)
+int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
+               void *ev_stop)
 {
     hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = (hipEvent_t)ev_start, e1 = (hipEvent_t)ev_stop;
     switch (a.P.K / 64) {
-    case 1: return launch_ray_kpl<1>(a, waves_per_wg, grid, st);
-    case 2: return launch_ray_kpl<2>(a, waves_per_wg, grid, st);
-    case 3: return launch_ray_kpl<3>(a, waves_per_wg, grid, st);
-    case 4: return launch_ray_kpl<4>(a, waves_per_wg, grid, st);
+    case 1: return launch_ray_kpl<1>(a, waves_per_wg, grid, st, e0, e1);
+    case 2: return launch_ray_kpl<2>(a, waves_per_wg, grid, st, e0, e1);
+    case 3: return launch_ray_kpl<3>(a, waves_per_wg, grid, st, e0, e1);
+    case 4: return launch_ray_kpl<4>(a, waves_per_wg, grid, st, e0, e1);
     default: return -2;
     }
 }

@@ -218,6 +218,7 @@ def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
         evals += e
         fl += x
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.timing_begin(steps)
     with torch.cuda.stream(st):
         e0.record(st)
         for _ in range(steps):
@@ -225,6 +226,8 @@ def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
         e1.record(st)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    kms, kn = s.timing_end()
+    kms /= max(kn, 1)
     # latency, one frame at a time
     one = s.ray_search(frames[:1], n_dirs, stream=st, mask=False, score=False, times=False,
                        recv=False)
@@ -245,9 +248,12 @@ def ray_bench(n_frames: int, steps: int, lat_frames: int, st):
             "evals_per_call": evals, "ms_per_call": round(ms, 4),
             "frames_per_s": round(n_frames / (ms * 1e-3), 1),
             "pass_evals_per_s": round(evals / (ms * 1e-3), 1),
-            "tflops": round(fl / (ms * 1e-3) / 1e12, 3),
-            "frac": round(FL.tflops(fl, ms) / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
-            "frac_of_nonpacked": round(FL.tflops(fl, ms) / FL.PEAK_FP32_NONPACKED_TFLOPS, 4),
+            # the roofline of the direction-sweep kernel alone (HIP events
+            # around it); ms_per_call also stages the frames from the host
+            "kernel_ms": round(kms, 4),
+            "tflops": round(fl / (kms * 1e-3) / 1e12, 3),
+            "frac": round(FL.tflops(fl, kms) / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
+            "frac_of_nonpacked": round(FL.tflops(fl, kms) / FL.PEAK_FP32_NONPACKED_TFLOPS, 4),
             "feasible_fraction": round(float(n_feas.sum()) / (n_frames * n_dirs * speeds), 4),
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                            "p99": round(float(np.percentile(lat, 99)), 4),
