@@ -103,23 +103,23 @@ DevParams derive(const dpps_params *p)
     double k3 = rho / ar, k4 = rho * rho / (2.0 * ar);
     double cD = k2 + k4, cTs = k1 + k3;
     P.f_cD = (float)cD;
-    P.f_cA = (float)(cD / (cTs * cTs));
-    P.f_cB = (float)(1.0 / k1 - 0.5 * as);
+    P.f_icA = (float)(cTs * cTs / cD);
+    P.f_icB = (float)(1.0 / (1.0 / k1 - 0.5 * as));
     double fal = k2 - rho * k1 - 0.5 * ar * k1 * k1, fbe = rho + ar * k1;
-    P.f_alpha4 = (float)(4.0 * fal);
-    P.f_beta = (float)fbe;
-    P.f_beta2 = (float)(fbe * fbe);
+    P.f_alpha = (float)fal;
+    P.f_hbeta = (float)(0.5 * fbe);
+    P.f_hbeta2 = (float)(0.25 * fbe * fbe);
     P.f_hfast = (float)(0.5 * as);
     P.f_pfast = 1.0f;
     // chip: flight time lam3 v0, carry lam1 v0^2, then roll from lam2 v0
     double ccD = lam1 + lam2 * lam2 / (2.0 * ar), ccTs = lam3 + lam2 / ar;
     P.c_cD = (float)ccD;
-    P.c_cA = (float)(ccD / (ccTs * ccTs));
-    P.c_cB = (float)(lam2 / lam3);
+    P.c_icA = (float)(ccTs * ccTs / ccD);
+    P.c_icB = (float)(lam3 / lam2);
     double cal = -0.5 * ar * lam3 * lam3, cbe = lam2 + ar * lam3;
-    P.c_alpha4 = (float)(4.0 * cal);
-    P.c_beta = (float)cbe;
-    P.c_beta2 = (float)(cbe * cbe);
+    P.c_alpha = (float)cal;
+    P.c_hbeta = (float)(0.5 * cbe);
+    P.c_hbeta2 = (float)(0.25 * cbe * cbe);
     P.c_hfast = 0.0f;
     P.c_pfast = (float)lam2;
     P.half_ar = (float)(0.5 * ar);
@@ -130,12 +130,12 @@ DevParams derive(const dpps_params *p)
     P.w_margin = p->w_margin;
     P.K = p->n_samples;
     P.out_flags = (int32_t)p->out_flags;
-    P.a_s_d = p->slide_decel;
-    P.a_r_d = p->roll_decel;
-    P.ratio_d = p->slide_ratio;
-    P.cos_d = cos((double)p->chip_angle);
-    P.sin_d = sin((double)p->chip_angle);
-    P.g_d = p->gravity;
+    P.bp.a_s = p->slide_decel;
+    P.bp.a_r = p->roll_decel;
+    P.bp.ratio = p->slide_ratio;
+    P.bp.cos_th = cos((double)p->chip_angle);
+    P.bp.sin_th = sin((double)p->chip_angle);
+    P.bp.g = p->gravity;
     P.margin_d = p->margin_s;
     P.invK_d = 1.0 / (double)p->n_samples;
     return P;

@@ -11,6 +11,13 @@ namespace dpps {
 // Constants derived once per context from dpps_params: reciprocals, the
 // robot model in time units scaled by the acceleration limit, and the
 // coefficients that invert the ball model for the critical kick speed.
+// The ball model's parameters in float64 (the per-variant ball constants
+// are derived from them): decelerations while sliding and rolling, the speed
+// ratio at the end of sliding, the chip angle's cosine and sine, gravity.
+struct BallParams64 {
+    double a_s, a_r, ratio, cos_th, sin_th, g;
+};
+
 struct DevParams {
     // geometry
     float field_len, field_wid;
@@ -22,17 +29,20 @@ struct DevParams {
     float invA2;       // 2 / amax: robot stage units (A T / 2) to seconds
     // ball model
     float a_s, a_r, ratio, cos_th, lam1_inv;  // lam1 = sin(2 th) / g  (carry = lam1 v0^2)
-    // flat inversion: stopped / rolling / sliding regimes
-    float f_cD, f_cA, f_cB, f_alpha4, f_beta, f_beta2, f_hfast, f_pfast;
-    // chip inversion: stopped / rolling / in-flight regimes
-    float c_cD, c_cA, c_cB, c_alpha4, c_beta, c_beta2, c_hfast, c_pfast;
+    // flat inversion: stopped / rolling / sliding regimes (icA = 1 / cA,
+    // icB = 1 / cB; alpha, hbeta = beta / 2, hbeta2 = hbeta^2: the slow
+    // root's terms with numerator and denominator halved)
+    float f_cD, f_icA, f_icB, f_alpha, f_hbeta, f_hbeta2, f_hfast, f_pfast;
+    // chip inversion: stopped / rolling / in-flight regimes (same layout)
+    float c_cD, c_icA, c_icB, c_alpha, c_hbeta, c_hbeta2, c_hfast, c_pfast;
     float half_ar;
     // scoring
     float margin_cap, w_ang_pi, w_dist, inv_dist_norm, w_margin;
     int32_t K;
     int32_t out_flags;
     // float64 copies used by the per-variant finish
-    double a_s_d, a_r_d, ratio_d, cos_d, sin_d, g_d, margin_d;
+    BallParams64 bp;
+    double margin_d;
     double invK_d;
 };
 

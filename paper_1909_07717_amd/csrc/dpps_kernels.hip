@@ -59,6 +59,7 @@ struct StageLDS {
     int32_t n_tm, n_op, n_var, has_flat, has_chip, frame;
     int32_t vel_ok;           // every robot's speed is at most vmax
     float bx, by;
+    BallParams64 bp;          // persistent kernels: written once at the start
 };
 
 struct OutLDS {
@@ -89,27 +90,27 @@ __device__ __forceinline__ int readlane_i(int x, int l) { return __builtin_amdgc
 // Ball constants of one variant (float64): phase split, speeds and
 // decelerations, offsets, stopping distance D and the minimum reachable
 // distance (the carry of a chip).
-__device__ VarConst var_const(const DevParams &P, int type, float v0f)
+__device__ VarConst var_const(const BallParams64 &B, int type, float v0f)
 {
     VarConst c;
     double v0 = (double)v0f;
     if (type == DPPS_CHIP) {
-        double vh = v0 * P.cos_d, vz = v0 * P.sin_d;
-        double tf = 2.0 * vz / P.g_d;
+        double vh = v0 * B.cos_th, vz = v0 * B.sin_th;
+        double tf = 2.0 * vz / B.g;
         double sf = vh * tf;
-        c.va1 = vh; c.a1 = P.a_r_d;             // unused: split < 0
-        c.va2 = vh; c.a2 = P.a_r_d; c.soff2 = sf; c.toff2 = tf;
+        c.va1 = vh; c.a1 = B.a_r;             // unused: split < 0
+        c.va2 = vh; c.a2 = B.a_r; c.soff2 = sf; c.toff2 = tf;
         c.split = -1.0;
-        c.D = sf + vh * vh / (2.0 * P.a_r_d);
+        c.D = sf + vh * vh / (2.0 * B.a_r);
         c.sf_reach = sf;
     } else {
-        double v1 = P.ratio_d * v0;
-        double t1 = (v0 - v1) / P.a_s_d;
-        double d1 = (v0 * v0 - v1 * v1) / (2.0 * P.a_s_d);
-        c.va1 = v0; c.a1 = P.a_s_d;
-        c.va2 = v1; c.a2 = P.a_r_d; c.soff2 = d1; c.toff2 = t1;
+        double v1 = B.ratio * v0;
+        double t1 = (v0 - v1) / B.a_s;
+        double d1 = (v0 * v0 - v1 * v1) / (2.0 * B.a_s);
+        c.va1 = v0; c.a1 = B.a_s;
+        c.va2 = v1; c.a2 = B.a_r; c.soff2 = d1; c.toff2 = t1;
         c.split = d1;
-        c.D = d1 + v1 * v1 / (2.0 * P.a_r_d);
+        c.D = d1 + v1 * v1 / (2.0 * B.a_r);
         c.sf_reach = 0.0;
     }
     return c;
@@ -117,9 +118,12 @@ __device__ VarConst var_const(const DevParams &P, int type, float v0f)
 
 // Stage the frame into LDS: interceptors (passer dropped), scaled by amax so
 // that the robot model runs in units where the acceleration limit is 1; the
-// per-variant ball constants in float64.  Called by all threads of a block.
-__device__ void stage_frame(const DevParams &P, const FrameDev *frames, const dpps_robot *robots,
-                            const dpps_variant *variants, int f, StageLDS &S)
+// per-variant ball constants in float64 (from B: persistent kernels pass
+// their LDS copy, so that the float64 parameters do not hold scalar
+// registers across the whole tile loop).  Called by all threads of a block.
+__device__ void stage_frame(const DevParams &P, const BallParams64 &B, const FrameDev *frames,
+                            const dpps_robot *robots, const dpps_variant *variants, int f,
+                            StageLDS &S)
 {
     const FrameDev F = frames[f];
     int tid = threadIdx.x;
@@ -147,7 +151,7 @@ __device__ void stage_frame(const DevParams &P, const FrameDev *frames, const dp
         S.v0[rank] = v.v0;
         S.type[rank] = v.type;
         S.vidx[rank] = tid;
-        S.vc[rank] = var_const(P, v.type, v.v0);
+        S.vc[rank] = var_const(B, v.type, v.v0);
     }
     if (tid == 0) {
         S.n_tm = F.n_team - 1;
@@ -201,10 +205,9 @@ __device__ __forceinline__ float robot_time_h(float4 r, float fq, float LA, cons
     const float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
     float u = fmaf(h, r.z, r.w) * inv;
     if (CLAMP) u = med3(u, -P.Vh, P.Vh);
-    const float st = u * u;
-    const float ss = u * fabsf(u);
+    const float ss = u * fabsf(u);  // its magnitude is u^2 (the add's abs modifier)
     const bool over = ss >= del;
-    const float Dp = st + (over ? -del : del);
+    const float Dp = fabsf(ss) + (over ? -del : del);
     const float sg = over ? u : -u;
     const float rh = Dp > P.V2 ? fmaf(Dp, P.inv2V, P.halfV) : hsqrt(Dp);
     return fmaf(sg, 0.70710678118654752f, rh);
@@ -366,44 +369,65 @@ __device__ __forceinline__ void count_below(const float *rt, const float *ro, fl
 // (quadratic in v0), or still in the fast phase (s >= cB T^2: sliding for a
 // flat kick, in the air for a chip).  Each root is written N / (Pp + sqrt M).
 // In the fast phase a flat kick slides (N = s + hfast T^2, Pp = T) and a
-// chip flies (N = s, Pp = pfast T).  T must be finite (a side with no robot
-// has no crossing; the caller skips it).  Every regime's terms are formed
-// first and then picked by plain selects, so that the lanes of a wave
-// (samples in different regimes) do not split into branches.
+// chip flies (N = s, Pp = pfast T).  The slow root 2Q / (beta T +
+// sqrt(4 alpha Q + beta^2 T^2)) is taken with numerator and denominator
+// halved (Q / (hbeta T + sqrt(alpha Q + hbeta^2 T^2)), hbeta = beta / 2:
+// power-of-two scalings, so the same value).  The terms that depend on the
+// sample only, s / cA, s / cB and the stopped M = cD s, come precomputed, so
+// that both sides share them.  T must be finite (a side with no robot has
+// no crossing; the caller skips it).  Every regime's terms are formed first
+// and then picked by plain selects, so that the lanes of a wave (samples in
+// different regimes) do not split into branches.
 template <bool CHIP>
-__device__ __forceinline__ float vcrit(float T, float s, float cD, float cA, float cB,
-                                       float alpha4, float beta, float beta2, float hfast,
+__device__ __forceinline__ float vcrit(float T, float s, float s_icA, float s_icB, float m_stop,
+                                       float alpha, float hbeta, float hbeta2, float hfast,
                                        float pfast, float half_ar)
 {
     const float T2 = T * T;
     const float Q = fmaf(half_ar, T2, s);
-    const bool stop = s <= cA * T2;
-    const bool fast = s >= cB * T2;
-    const float n_slow = Q + Q;
-    const float m_slow = fmaf(alpha4, Q, beta2 * T2);
-    const float m_stop = s * cD;
-    const float p_slow = beta * T;
+    const bool stop = s_icA <= T2;
+    const bool fast = s_icB >= T2;
+    // (clamped here, where it is formed: m_stop >= 0 and the fast M is 0)
+    const float m_slow = fmaxf(fmaf(alpha, Q, hbeta2 * T2), 0.0f);
+    const float p_slow = hbeta * T;
     float N, Pp;
     if (CHIP) {
-        N = (fast || stop) ? s : n_slow;
+        N = (fast || stop) ? s : Q;
         Pp = fast ? pfast * T : p_slow;
     } else {
-        N = fast ? fmaf(hfast, T2, s) : n_slow;
+        N = fast ? fmaf(hfast, T2, s) : Q;
         N = stop ? s : N;
         Pp = fast ? T : p_slow;
     }
     float M = fast ? 0.0f : m_slow;
     Pp = stop ? 0.0f : Pp;
     M = stop ? m_stop : M;
-    return N * hrcp(Pp + hsqrt(fmaxf(M, 0.0f)));
+    return N * hrcp(Pp + hsqrt(M));
 }
+
+// The side-independent terms of the inversion at the lane's samples for one
+// kick type.
+template <int KPL, bool CHIP>
+struct SampleTerms {
+    float icA[KPL], icB[KPL], mst[KPL];
+    __device__ __forceinline__ SampleTerms(const DevParams &P, const float (&sk)[KPL])
+    {
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+            icA[q] = sk[q] * (CHIP ? P.c_icA : P.f_icA);
+            icB[q] = sk[q] * (CHIP ? P.c_icB : P.f_icB);
+            mst[q] = sk[q] * (CHIP ? P.c_cD : P.f_cD);
+        }
+    }
+};
 
 // Critical speeds of one side at the lane's samples for one kick type (0 for
 // every sample when the side has no robot).
 template <int KPL, bool CHIP>
 __device__ __forceinline__ void side_vcrit(const DevParams &P, int n_side, const float (&T)[KPL],
-                                           const float (&sk)[KPL], const float (&vair)[KPL],
-                                           float (&v)[KPL])
+                                           const float (&sk)[KPL],
+                                           const SampleTerms<KPL, CHIP> &st,
+                                           const float (&vair)[KPL], float (&v)[KPL])
 {
     if (n_side == 0) {
 #pragma unroll
@@ -413,12 +437,12 @@ __device__ __forceinline__ void side_vcrit(const DevParams &P, int n_side, const
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         if (CHIP)
-            v[q] = fminf(vair[q], vcrit<true>(T[q], sk[q], P.c_cD, P.c_cA, P.c_cB, P.c_alpha4,
-                                              P.c_beta, P.c_beta2, P.c_hfast, P.c_pfast,
-                                              P.half_ar));
+            v[q] = fminf(vair[q], vcrit<true>(T[q], sk[q], st.icA[q], st.icB[q], st.mst[q],
+                                              P.c_alpha, P.c_hbeta, P.c_hbeta2, P.c_hfast,
+                                              P.c_pfast, P.half_ar));
         else
-            v[q] = vcrit<false>(T[q], sk[q], P.f_cD, P.f_cA, P.f_cB, P.f_alpha4, P.f_beta,
-                                P.f_beta2, P.f_hfast, P.f_pfast, P.half_ar);
+            v[q] = vcrit<false>(T[q], sk[q], st.icA[q], st.icB[q], st.mst[q], P.f_alpha,
+                                P.f_hbeta, P.f_hbeta2, P.f_hfast, P.f_pfast, P.half_ar);
     }
 }
 
@@ -534,9 +558,9 @@ __device__ __forceinline__ double pass_power(const DevParams &P, double d64, flo
 {
     if (!(t_recv < INFINITY)) return 0.0;
     const double t = (double)t_recv + buffer;
-    const double a = P.a_r_d;
+    const double a = P.bp.a_r;
     const double v1 = d64 >= 0.5 * a * t * t ? (d64 + 0.5 * a * t * t) / t : sqrt(2.0 * a * d64);
-    return fmin(fmax(v1 / P.ratio_d, vmin), vmax);
+    return fmin(fmax(v1 / P.bp.ratio, vmin), vmax);
 }
 
 // SBIP of every staged variant along one path of length d (metres; LA = d
@@ -596,8 +620,9 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
     wave_lds_sync();  // the previous path's searches are done with the rows
     if (flat_m) {
         float vt[KPL], vo[KPL];
-        side_vcrit<KPL, false>(P, n_tm, Tt, sk, sk, vt);
-        side_vcrit<KPL, false>(P, n_op, To, sk, sk, vo);
+        const SampleTerms<KPL, false> st(P, sk);
+        side_vcrit<KPL, false>(P, n_tm, Tt, sk, st, sk, vt);
+        side_vcrit<KPL, false>(P, n_op, To, sk, st, sk, vo);
         store_running_max<KPL>(vt, pf);
         store_running_max<KPL>(vo, pf + K);
     }
@@ -605,8 +630,9 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
         float vt[KPL], vo[KPL], vair[KPL];
 #pragma unroll
         for (int q = 0; q < KPL; ++q) vair[q] = hsqrt(sk[q] * P.lam1_inv);
-        side_vcrit<KPL, true>(P, n_tm, Tt, sk, vair, vt);
-        side_vcrit<KPL, true>(P, n_op, To, sk, vair, vo);
+        const SampleTerms<KPL, true> st(P, sk);
+        side_vcrit<KPL, true>(P, n_tm, Tt, sk, st, vair, vt);
+        side_vcrit<KPL, true>(P, n_op, To, sk, st, vair, vo);
         store_running_max<KPL>(vt, pc);
         store_running_max<KPL>(vo, pc + K);
     }
@@ -652,7 +678,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
     bool feas = false;
     double m = -INFINITY;
     if (l < n_var && (!POWER || v0 > 0.0)) {
-        const VarConst c = POWER ? var_const(P, DPPS_FLAT, (float)v0) : S.vc[l];
+        const VarConst c = POWER ? var_const(P.bp, DPPS_FLAT, (float)v0) : S.vc[l];
         bool reach = d64 >= 1e-9 && d64 <= c.D && d64 >= c.sf_reach;
         double tt = INFINITY, to = INFINITY;
         if (reach) {
@@ -707,6 +733,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     const int G = (int)gridDim.x;
     const int n_tiles = a.n_frames_dev ? *a.n_frames_dev * a.tiles_per_frame : a.n_tiles;
     const int n_static = a.persistent ? max(n_tiles / G - 1, 0) * G : 0;
+    if (threadIdx.x == 0) S.bp = P.bp;  // read after the loop's first barrier
     while (true) {
         // the previous tile (its staged results and records) is finished
         __syncthreads();
@@ -727,7 +754,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         }
         const WinDev W = a.wins[tile.win];
         if (W.frame != cur_frame) {
-            stage_frame(a.P, a.frames, a.robots, a.variants, W.frame, S);
+            stage_frame(a.P, S.bp, a.frames, a.robots, a.variants, W.frame, S);
             __syncthreads();
             cur_frame = W.frame;
             const int nv = S.n_var;
@@ -888,7 +915,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
         // the per-point power search passes one flat kick at the point's power
         const int ptype = a.power ? DPPS_FLAT : var.type;
         const float pv0 = a.power ? bestr.v0 : var.v0;
-        const VarConst c = var_const(a.P, ptype, pv0);
+        const VarConst c = var_const(a.P.bp, ptype, pv0);
         double ex64 = (double)W.h * (double)mi - (double)F.ball_x;
         double ey64 = (double)W.h * (double)mj - (double)F.ball_y;
         b.found = 1;
@@ -1175,6 +1202,7 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
     const int R = max(a.n_tiles / G - 1, 0);
     const int n_static = R * G;
     int iter = 0;
+    if (threadIdx.x == 0) S.bp = P.bp;  // read after the loop's first barrier
     while (true) {
         __syncthreads();  // the previous tile is finished
         int t = iter < R ? (int)blockIdx.x * R + iter : n_static;
@@ -1188,7 +1216,7 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
         const TileDev tile = a.tiles[t];
         const int f = tile.win;
         if (f != cur_frame) {
-            stage_frame(a.P, a.frames, a.robots, a.variants, f, S);
+            stage_frame(a.P, S.bp, a.frames, a.robots, a.variants, f, S);
             __syncthreads();
             cur_frame = f;
             const int nv = S.n_var;
@@ -1482,9 +1510,9 @@ __global__ void __launch_bounds__(512) shot_kernel(ShotArgs a)
     const TileDev tile = MAP ? a.tiles[t] : TileDev{0, 0};
     const WinDev W = MAP ? a.wins[tile.win] : WinDev{};
     const int f = MAP ? W.frame : t;
-    stage_frame(P, a.frames, a.robots, a.variants, f, S);
+    stage_frame(P, P.bp, a.frames, a.robots, a.variants, f, S);
     __syncthreads();
-    const VarConst vc = var_const(P, DPPS_FLAT, a.v_shot);
+    const VarConst vc = var_const(P.bp, DPPS_FLAT, a.v_shot);
     if (!MAP) {
         const dpps_shot r = shot_origin<KPL>(S, P, PR[0], (double)S.bx, (double)S.by, vc,
                                              a.min_angle, a.margin);
@@ -1542,10 +1570,9 @@ __device__ __forceinline__ float robot_time_pt(const DevParams &P, float4 r, flo
     const float del = fmaxf(fmaf(r2, inv, -P.RA), 0.0f);
     float u = fmaf(dx, r.z, dy * r.w) * (0.70710678118654752f * inv);
     u = med3(u, -P.Vh, P.Vh);
-    const float st = u * u;
-    const float ss = u * fabsf(u);
+    const float ss = u * fabsf(u);  // its magnitude is u^2 (the add's abs modifier)
     const bool over = ss >= del;
-    const float Dp = st + (over ? -del : del);
+    const float Dp = fabsf(ss) + (over ? -del : del);
     const float sg = over ? u : -u;
     const float rh = Dp > P.V2 ? fmaf(Dp, P.inv2V, P.halfV) : hsqrt(Dp);
     return fmaf(sg, 0.70710678118654752f, rh) * P.invA2;
@@ -1613,7 +1640,7 @@ __global__ void __launch_bounds__(256) run_kernel(RunArgs a)
     __shared__ unsigned long long red[4];
     const DevParams &P = a.P;
     const WinDev W = a.wins[blockIdx.x];
-    stage_frame(P, a.frames, a.robots, a.variants, W.frame, S);
+    stage_frame(P, P.bp, a.frames, a.robots, a.variants, W.frame, S);
     __syncthreads();
     const int n_tm = S.n_tm, n_op = S.n_op;
     unsigned long long best = 0ull;
