@@ -285,29 +285,31 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
 // maximum of lanes 0..l): four DPP row shifts give it within each row of 16
 // lanes (lanes without a source see -inf), then two DPP row broadcasts carry
 // lane 15 into row 1 and row 3, and lane 31 into rows 2 and 3.
+// Running maxima of critical speeds are taken on the bit patterns: the
+// speeds are non-negative floats or +inf, which order as their bits read as
+// signed integers, and an integer max needs no NaN quieting, so each DPP lane
+// shift fuses into its max (identity INT_MIN, the bits of -0.0).
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_max(float v)
+__device__ __forceinline__ int dpp_imax(int v)
 {
-    const int u = __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), CTRL,
-                                              ROW_MASK, 0xf, false);
-    return fmaxf(v, __int_as_float(u));
+    const int u = __builtin_amdgcn_update_dpp(INT_MIN, v, CTRL, ROW_MASK, 0xf, false);
+    return max(v, u);
 }
 
-__device__ __forceinline__ float wave_prefix_max(float v)
+__device__ __forceinline__ int wave_prefix_imax(int v)
 {
-    v = dpp_max<0x111, 0xf>(v);  // row_shr:1
-    v = dpp_max<0x112, 0xf>(v);  // row_shr:2
-    v = dpp_max<0x114, 0xf>(v);  // row_shr:4
-    v = dpp_max<0x118, 0xf>(v);  // row_shr:8
-    v = dpp_max<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    return dpp_max<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    v = dpp_imax<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_imax<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_imax<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_imax<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_imax<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return dpp_imax<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
 }
 
-// Lane l gets lane l - 1's value, lane 0 gets -inf (DPP wave_shr:1).
-__device__ __forceinline__ float wave_shift_up(float v)
+// Lane l gets lane l - 1's value, lane 0 gets INT_MIN (DPP wave_shr:1).
+__device__ __forceinline__ int wave_shift_up_i(int v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v),
-                                                      0x138, 0xf, 0xf, false));
+    return __builtin_amdgcn_update_dpp(INT_MIN, v, 0x138, 0xf, 0xf, false);
 }
 
 // Order this wave's accesses to its own LDS row.
@@ -331,13 +333,13 @@ template <int KPL>
 __device__ __forceinline__ void store_running_max(const float (&vc)[KPL], float *row)
 {
     const int l = lane_id();
-    float run[KPL];
-    run[0] = vc[0];
+    int run[KPL];
+    run[0] = __float_as_int(vc[0]);
 #pragma unroll
-    for (int q = 1; q < KPL; ++q) run[q] = fmaxf(run[q - 1], vc[q]);
-    const float excl = wave_shift_up(wave_prefix_max(run[KPL - 1]));
+    for (int q = 1; q < KPL; ++q) run[q] = max(run[q - 1], __float_as_int(vc[q]));
+    const int excl = wave_shift_up_i(wave_prefix_imax(run[KPL - 1]));
 #pragma unroll
-    for (int q = 0; q < KPL; ++q) row[l * KPL + q] = fmaxf(excl, run[q]);
+    for (int q = 0; q < KPL; ++q) row[l * KPL + q] = __int_as_float(max(excl, run[q]));
 }
 
 template <int KPL>
@@ -346,21 +348,27 @@ __device__ __forceinline__ void count_below(const float *rt, const float *ro, fl
 {
     // a search over 2^n >= K entries, those past K read as the last one (the
     // rows are non-decreasing, so the count only exceeds K when every entry
-    // is below v0, and is then clamped); no branches, both sides interleaved
+    // is below v0, and is then clamped); no branches, both sides interleaved.
+    // The search moves row pointers (the step's offset goes into the LDS
+    // read's immediate); when K is a power of two no read can pass the end.
     constexpr int K = KPL * 64;
     constexpr int S0 = KPL >= 3 ? 128 : (KPL == 2 ? 64 : 32);  // half of 2^n
-    int lt = 0, lo = 0;
+    constexpr bool POW2 = (K & (K - 1)) == 0;
+    const float *pt = rt, *po = ro;
+    const float *const et = rt + (K - 1), *const eo = ro + (K - 1);
 #pragma unroll
     for (int st = S0; st > 0; st >>= 1) {
-        const float mt = rt[min(lt + st - 1, K - 1)];
-        const float mo = ro[min(lo + st - 1, K - 1)];
-        lt += mt < v0 ? st : 0;
-        lo += mo < v0 ? st : 0;
+        const float mt = POW2 ? pt[st - 1] : *min(pt + (st - 1), et);
+        const float mo = POW2 ? po[st - 1] : *min(po + (st - 1), eo);
+        pt += mt < v0 ? st : 0;
+        po += mo < v0 ? st : 0;
     }
-    const float mt = rt[min(lt, K - 1)];
-    const float mo = ro[min(lo, K - 1)];
-    kt = min(lt + (mt < v0 ? 1 : 0), K);
-    ko = min(lo + (mo < v0 ? 1 : 0), K);
+    const float mt = POW2 ? *pt : *min(pt, et);
+    const float mo = POW2 ? *po : *min(po, eo);
+    const int lt = (int)(pt - rt) + (mt < v0 ? 1 : 0);
+    const int lo = (int)(po - ro) + (mo < v0 ? 1 : 0);
+    kt = POW2 ? lt : min(lt, K);
+    ko = POW2 ? lo : min(lo, K);
 }
 
 // Kick speed at which the ball covers distance s in exactly time T (the
@@ -444,6 +452,17 @@ __device__ __forceinline__ void side_vcrit(const DevParams &P, int n_side, const
             v[q] = vcrit<false>(T[q], sk[q], st.icA[q], st.icB[q], st.mst[q], P.f_alpha,
                                 P.f_hbeta, P.f_hbeta2, P.f_hfast, P.f_pfast, P.half_ar);
     }
+}
+
+// Square root of a non-negative float64 from the hardware reciprocal square
+// root estimate with two Newton steps (0 for 0): within a few units in the
+// last place, in about half the instructions of the correctly rounded sqrt.
+__device__ __forceinline__ double sqrt64(double q)
+{
+    double y = __builtin_amdgcn_rsq(q);
+    y = y * fma(-0.5 * q, y * y, 1.5);
+    y = y * fma(-0.5 * q, y * y, 1.5);
+    return q > 0.0 ? q * y : 0.0;
 }
 
 // Ball time (float64) to distance s for staged variant c.
@@ -664,7 +683,7 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
     const float d = hsqrt(fmaf(ex, ex, ey * ey));
     const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
     const double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
-    const double d64 = sqrt(ex64 * ex64 + ey64 * ey64);
+    const double d64 = sqrt64(ex64 * ex64 + ey64 * ey64);
     int my_kt, my_ko;
     double v0 = 0.0;
     sbip_crossings<KPL, POWER>(S, P, pr, pm, myv0, mytype, d, LA, my_kt, my_ko, d64,
