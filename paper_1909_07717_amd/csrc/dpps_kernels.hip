@@ -62,6 +62,14 @@ struct StageLDS {
     BallParams64 bp;          // persistent kernels: written once at the start
 };
 
+// A wave's path-frame block: MAX_ROB entries, then MAX_ROB bound keys.
+#define PR_ENTRIES (MAX_ROB + MAX_ROB / 4)
+__device__ __forceinline__ uint32_t *bound_keys(float4 *pr) { return (uint32_t *)(pr + MAX_ROB); }
+__device__ __forceinline__ const uint32_t *bound_keys(const float4 *pr)
+{
+    return (const uint32_t *)(pr + MAX_ROB);
+}
+
 struct OutLDS {
     float score[MAX_VAR * MAX_TILE];
     uint8_t mask[MAX_VAR * MAX_TILE];
@@ -177,6 +185,46 @@ __device__ void stage_frame(const DevParams &P, const BallParams64 &B, const Fra
     }
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wave (lane l gets the
+// maximum of lanes 0..l): four DPP row shifts give it within each row of 16
+// lanes (lanes without a source see the identity), then two DPP row
+// broadcasts carry lane 15 into row 1 and row 3, and lane 31 into rows 2
+// and 3.  The maxima of critical speeds and arrival times are taken on the
+// bit patterns: those are non-negative floats or +inf, which order as their
+// bits read as signed integers, and an integer max needs no NaN quieting, so
+// each DPP lane shift fuses into its max (identity INT_MIN, the bits of
+// -0.0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_imax(int v)
+{
+    const int u = __builtin_amdgcn_update_dpp(INT_MIN, v, CTRL, ROW_MASK, 0xf, false);
+    return max(v, u);
+}
+
+__device__ __forceinline__ int wave_prefix_imax(int v)
+{
+    v = dpp_imax<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_imax<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_imax<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_imax<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_imax<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    return dpp_imax<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+}
+
+// Lane l gets lane l - 1's value, lane 0 gets INT_MIN (DPP wave_shr:1).
+__device__ __forceinline__ int wave_shift_up_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(INT_MIN, v, 0x138, 0xf, 0xf, false);
+}
+
+// Order this wave's accesses to its own LDS row.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Arrival time of one robot at one sample.  Lengths are scaled by amax (a
 // distance d becomes A d) and speeds by 1/sqrt(2); with that scaling the
 // time-optimal straight-line motion that ends at rest takes
@@ -235,16 +283,48 @@ __device__ __forceinline__ void robot_stage(const float4 *pr, const DevParams &P
     }
 }
 
+// Robots [j0, j0 + n) of a side, sorted by ascending lower bound on their
+// arrival times: after the first two, the side's latest arrival over all the
+// wave's samples so far is taken, and the robots whose bound is not below it
+// (a suffix of the sorted order) are left out: they cannot lower any
+// sample's minimum, so the minima are those of all the side's robots.
+// Arrival times are non-negative or +inf, bounds non-negative: both compare
+// as their bits.
+template <int KPL, bool CLAMP>
+__device__ __forceinline__ void robot_stage_bounded(const float4 *pr, const DevParams &P, int j0,
+                                                    int n, uint32_t side_bit,
+                                                    const float (&fs)[KPL], float LA,
+                                                    float (&T)[KPL])
+{
+    const int first = min(n, 2);
+    robot_stage<KPL, CLAMP>(pr, P, j0, first, fs, LA, T);
+    if (n > first) {
+        int m = __float_as_int(T[0]);
+#pragma unroll
+        for (int q = 1; q < KPL; ++q) m = max(m, __float_as_int(T[q]));
+        m = __builtin_amdgcn_readlane(wave_prefix_imax(m), 63);
+        const int l = lane_id();
+        const uint32_t k = l < MAX_ROB ? bound_keys(pr)[l] : 0xFFFFFFFFu;
+        const bool below = k != 0xFFFFFFFFu && (k & 0x80000000u) == side_bit &&
+                           (int)(k & 0x7FFFFFFFu & ~(uint32_t)(MAX_ROB - 1)) < m;
+        const int need = max((int)__builtin_popcountll(__ballot(below)), first);
+        robot_stage<KPL, CLAMP>(pr, P, j0 + first, need - first, fs, LA, T);
+    }
+}
+
 // Path frame of a ball path along the unit direction e = (ux, uy) for the
 // staged robots (lanes = robots), in float64 and then rounded once: for robot
 // j with offset a = ball - x_j and normal n = (-e_y, e_x): t = -a.e and
 // q = a.n (scaled by amax), w = velocity / sqrt(2), and pr[j] =
 // (t, q^2, w.e, q w.n).
+template <bool SORT>
 __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParams &P, float4 *pr,
-                                               int n_rob, double ux, double uy, double bx,
-                                               double by)
+                                               int n_rob, int n_tm, double LA, double ux,
+                                               double uy, double bx, double by)
 {
     const int l = lane_id();
+    float4 fr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t key = 0xFFFFFFFFu;
     if (l < n_rob) {
         const float4 r = S.rob[l];
         const double A = (double)P.A;
@@ -253,12 +333,43 @@ __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParam
         const double q = (ay * ux - ax * uy) * A;
         const double we = ((double)r.z * ux + (double)r.w * uy) * 0.70710678118654752;
         const double wn = ((double)r.w * ux - (double)r.z * uy) * 0.70710678118654752;
-        pr[l] = make_float4((float)t, (float)(q * q + 1e-30), (float)we, (float)(q * wn));
+        fr = make_float4((float)t, (float)(q * q + 1e-30), (float)we, (float)(q * wn));
+        if (SORT) {
+            // The robot's distance to the path segment [0, LA] bounds its
+            // arrival time at every sample from below, whatever its velocity:
+            // with delta = max(dist - RA, 0) in the robot stage's units, the
+            // time is at least sqrt(delta / 2) for delta <= vmax^2 / 2 (the
+            // best approach speed, sqrt(delta), is reachable) and else
+            // delta / (2 vmax) + vmax / 4 (approach at the speed limit and
+            // cruise).  Less 2^-12 for the rounding of both computations,
+            // then truncated to make room for the lane in the low bits.
+            const double tc = t < 0.0 ? -t : (t > LA ? t - LA : 0.0);
+            const float dseg = hsqrt((float)(q * q + tc * tc));
+            const float del = fmaxf(dseg - P.RA, 0.0f);
+            const float lb = del <= 0.5f * P.V2 ? hsqrt(0.5f * del)
+                                                : fmaf(del, P.inv2V, 0.5f * P.halfV);
+            key = (__float_as_uint(lb * (1.0f - 1.0f / 4096.0f)) & ~(uint32_t)(MAX_ROB - 1)) |
+                  (uint32_t)l | (l >= n_tm ? 0x80000000u : 0u);
+        }
+    }
+    if (SORT) {
+        // Rank by key: each side's robots by ascending bound (the side bit
+        // puts the team's first), written to the rows in that order.  The
+        // keys stay in the row's key block, by robot, for the bound test.
+        uint32_t *const pk = bound_keys(pr);
+        if (l < MAX_ROB) pk[l] = key;
+        wave_lds_sync();
+        int rank = 0;
+        for (int j = 0; j < n_rob; j += 4) {
+            const uint4 k4 = *(const uint4 *)(pk + j);
+            rank += (k4.x < key) + (k4.y < key) + (k4.z < key) + (k4.w < key);
+        }
+        if (l < n_rob) pr[rank] = fr;
+    } else if (l < n_rob) {
+        pr[l] = fr;
     }
     // the row is written and read by this wave only
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
 }
 
 // The same for the path from the ball to candidate point c: e = (c - ball) /
@@ -267,8 +378,8 @@ __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParam
 // (relative error far below the float32 rounding that follows).  Returns
 // |c - ball| A.
 __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &P, float4 *pr,
-                                            int n_rob, double cx64, double cy64, double bx,
-                                            double by)
+                                            int n_rob, int n_tm, double cx64, double cy64,
+                                            double bx, double by)
 {
     const double ex = cx64 - bx, ey = cy64 - by;
     const double L2 = ex * ex + ey * ey;
@@ -277,47 +388,8 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
     const bool pos = L2 > 0.0;
     const double L = pos ? L2 * iL : 0.0;
     const double ux = pos ? ex * iL : 1.0, uy = pos ? ey * iL : 0.0;
-    path_frame_dir(S, P, pr, n_rob, ux, uy, bx, by);
+    path_frame_dir<true>(S, P, pr, n_rob, n_tm, L * (double)P.A, ux, uy, bx, by);
     return (float)(L * (double)P.A);
-}
-
-// Inclusive prefix maximum over the 64 lanes of a wave (lane l gets the
-// maximum of lanes 0..l): four DPP row shifts give it within each row of 16
-// lanes (lanes without a source see -inf), then two DPP row broadcasts carry
-// lane 15 into row 1 and row 3, and lane 31 into rows 2 and 3.
-// Running maxima of critical speeds are taken on the bit patterns: the
-// speeds are non-negative floats or +inf, which order as their bits read as
-// signed integers, and an integer max needs no NaN quieting, so each DPP lane
-// shift fuses into its max (identity INT_MIN, the bits of -0.0).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int dpp_imax(int v)
-{
-    const int u = __builtin_amdgcn_update_dpp(INT_MIN, v, CTRL, ROW_MASK, 0xf, false);
-    return max(v, u);
-}
-
-__device__ __forceinline__ int wave_prefix_imax(int v)
-{
-    v = dpp_imax<0x111, 0xf>(v);  // row_shr:1
-    v = dpp_imax<0x112, 0xf>(v);  // row_shr:2
-    v = dpp_imax<0x114, 0xf>(v);  // row_shr:4
-    v = dpp_imax<0x118, 0xf>(v);  // row_shr:8
-    v = dpp_imax<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-    return dpp_imax<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-}
-
-// Lane l gets lane l - 1's value, lane 0 gets INT_MIN (DPP wave_shr:1).
-__device__ __forceinline__ int wave_shift_up_i(int v)
-{
-    return __builtin_amdgcn_update_dpp(INT_MIN, v, 0x138, 0xf, 0xf, false);
-}
-
-// Order this wave's accesses to its own LDS row.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // First crossings by running maxima.  The first crossing of a variant on
@@ -613,11 +685,11 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
     }
     // 1. robot stage, in the path frame
     if (uni(S.vel_ok)) {
-        robot_stage<KPL, false>(pr, P, 0, n_tm, fs, LA, Tt);
-        robot_stage<KPL, false>(pr, P, n_tm, n_op, fs, LA, To);
+        robot_stage_bounded<KPL, false>(pr, P, 0, n_tm, 0u, fs, LA, Tt);
+        robot_stage_bounded<KPL, false>(pr, P, n_tm, n_op, 0x80000000u, fs, LA, To);
     } else {
-        robot_stage<KPL, true>(pr, P, 0, n_tm, fs, LA, Tt);
-        robot_stage<KPL, true>(pr, P, n_tm, n_op, fs, LA, To);
+        robot_stage_bounded<KPL, true>(pr, P, 0, n_tm, 0u, fs, LA, Tt);
+        robot_stage_bounded<KPL, true>(pr, P, n_tm, n_op, 0x80000000u, fs, LA, To);
     }
     // 2-3. critical kick speeds per sample, then the first crossing of each
     // lane's variant (a side with no robot never intercepts: critical speed 0)
@@ -681,7 +753,8 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
     const float bx = unif(S.bx), by = unif(S.by);
     const float ex = cx - bx, ey = cy - by;
     const float d = hsqrt(fmaf(ex, ex, ey * ey));
-    const float LA = unif(path_frame(S, P, pr, n_tm + n_op, cx64, cy64, (double)bx, (double)by));
+    const float LA =
+        unif(path_frame(S, P, pr, n_tm + n_op, n_tm, cx64, cy64, (double)bx, (double)by));
     const double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
     const double d64 = sqrt64(ex64 * ex64 + ey64 * ey64);
     int my_kt, my_ko;
@@ -731,7 +804,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
     __shared__ OutLDS O;
-    __shared__ float4 PR[MAX_WAVES][MAX_ROB];  // each wave's path frame of its point
+    __shared__ float4 PR[MAX_WAVES][PR_ENTRIES];  // each wave's path frame of its point
     extern __shared__ float PMX[];              // each wave's running maxima: 4 rows of K
     __shared__ int s_tile;
     const DevParams &P = a.P;
@@ -1144,7 +1217,7 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
     const double xd = 2.0 * (double)d / (double)n_dirs;  // theta_d / pi
     const double ux = cospi(xd), uy = sinpi(xd);
     const double L = ray_length(P, bx, by, ux, uy);
-    path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, bx, by);
+    path_frame_dir<true>(S, P, pr, n_tm + n_op, n_tm, L * (double)P.A, ux, uy, bx, by);
     int my_kt, my_ko;
     sbip_crossings<KPL, false>(S, P, pr, pm, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
                         my_ko);
@@ -1203,7 +1276,7 @@ template <int KPL>
 __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
 {
     __shared__ StageLDS S;
-    __shared__ float4 PR[MAX_WAVES][MAX_ROB];
+    __shared__ float4 PR[MAX_WAVES][PR_ENTRIES];
     extern __shared__ float PMX[];
     __shared__ RayRec WB[MAX_WAVES];
     __shared__ int s_tile;
@@ -1485,7 +1558,7 @@ __device__ dpps_shot shot_origin(const StageLDS &S, const DevParams &P, float4 *
     const float aim = gap > 0.0f ? fmaf(0.5f, gap, g0) : atan2f(-fy, (float)dxg);
     const double ux = (double)cosf(aim), uy = (double)sinf(aim);
     const double L = dxg / ux;
-    path_frame_dir(S, P, pr, n_tm + n_op, ux, uy, cx, cy);
+    path_frame_dir<false>(S, P, pr, n_tm + n_op, n_tm, 0.0, ux, uy, cx, cy);
     const float Lf = (float)L, LA = (float)(L * (double)P.A);
     float fs[KPL], T[KPL];
 #pragma unroll
@@ -1521,7 +1594,7 @@ template <int KPL, bool MAP>
 __global__ void __launch_bounds__(512) shot_kernel(ShotArgs a)
 {
     __shared__ StageLDS S;
-    __shared__ float4 PR[MAX_WAVES][MAX_ROB];
+    __shared__ float4 PR[MAX_WAVES][PR_ENTRIES];
     const DevParams &P = a.P;
     const int w = threadIdx.x >> 6;
     const int l = lane_id();
