@@ -290,25 +290,47 @@ __device__ __forceinline__ void robot_stage(const float4 *pr, const DevParams &P
 // sample's minimum, so the minima are those of all the side's robots.
 // Arrival times are non-negative or +inf, bounds non-negative: both compare
 // as their bits.
+// The robots of the side among [j0, j0 + n) whose bound is below the
+// latest of the arrival minima T over the wave's samples (a prefix of the
+// sorted order; at least `done`).
+template <int KPL>
+__device__ __forceinline__ int robots_needed(const float4 *pr, int n, int done,
+                                             uint32_t side_bit, const float (&T)[KPL])
+{
+    int m = __float_as_int(T[0]);
+#pragma unroll
+    for (int q = 1; q < KPL; ++q) m = max(m, __float_as_int(T[q]));
+    m = __builtin_amdgcn_readlane(wave_prefix_imax(m), 63);
+    const int l = lane_id();
+    const uint32_t k = l < MAX_ROB ? bound_keys(pr)[l] : 0xFFFFFFFFu;
+    const bool below = k != 0xFFFFFFFFu && (k & 0x80000000u) == side_bit &&
+                       (int)(k & 0x7FFFFFFFu & ~(uint32_t)(MAX_ROB - 1)) < m;
+    return min(max((int)__builtin_popcountll(__ballot(below)), done), n);
+}
+
+// Robots [j0, j0 + n) of a side, sorted by ascending lower bound on their
+// arrival times: after the first two, and again after the next two, the
+// side's latest arrival over all the wave's samples so far is taken, and the
+// robots whose bound is not below it (a suffix of the sorted order) are left
+// out: they cannot lower any sample's minimum, so the minima are those of
+// all the side's robots.  Arrival times are non-negative or +inf, bounds
+// non-negative: both compare as their bits.
 template <int KPL, bool CLAMP>
 __device__ __forceinline__ void robot_stage_bounded(const float4 *pr, const DevParams &P, int j0,
                                                     int n, uint32_t side_bit,
                                                     const float (&fs)[KPL], float LA,
                                                     float (&T)[KPL])
 {
-    const int first = min(n, 2);
-    robot_stage<KPL, CLAMP>(pr, P, j0, first, fs, LA, T);
-    if (n > first) {
-        int m = __float_as_int(T[0]);
-#pragma unroll
-        for (int q = 1; q < KPL; ++q) m = max(m, __float_as_int(T[q]));
-        m = __builtin_amdgcn_readlane(wave_prefix_imax(m), 63);
-        const int l = lane_id();
-        const uint32_t k = l < MAX_ROB ? bound_keys(pr)[l] : 0xFFFFFFFFu;
-        const bool below = k != 0xFFFFFFFFu && (k & 0x80000000u) == side_bit &&
-                           (int)(k & 0x7FFFFFFFu & ~(uint32_t)(MAX_ROB - 1)) < m;
-        const int need = max((int)__builtin_popcountll(__ballot(below)), first);
-        robot_stage<KPL, CLAMP>(pr, P, j0 + first, need - first, fs, LA, T);
+    int done = min(n, 2);
+    robot_stage<KPL, CLAMP>(pr, P, j0, done, fs, LA, T);
+    if (n > done) {
+        int need = robots_needed<KPL>(pr, n, done, side_bit, T);
+        if (need > done + 2) {
+            robot_stage<KPL, CLAMP>(pr, P, j0 + done, 2, fs, LA, T);
+            done += 2;
+            need = robots_needed<KPL>(pr, need, done, side_bit, T);
+        }
+        robot_stage<KPL, CLAMP>(pr, P, j0 + done, need - done, fs, LA, T);
     }
 }
 
