@@ -102,7 +102,7 @@ DevParams derive(const dpps_params *p)
     double k1 = (1.0 - rho) / as, k2 = (1.0 - rho * rho) / (2.0 * as);
     double k3 = rho / ar, k4 = rho * rho / (2.0 * ar);
     double cD = k2 + k4, cTs = k1 + k3;
-    P.f_cD = (float)cD;
+    P.f_icD = (float)(1.0 / cD);
     P.f_icA = (float)(cTs * cTs / cD);
     P.f_icB = (float)(1.0 / (1.0 / k1 - 0.5 * as));
     double fal = k2 - rho * k1 - 0.5 * ar * k1 * k1, fbe = rho + ar * k1;
@@ -113,7 +113,7 @@ DevParams derive(const dpps_params *p)
     P.f_pfast = 1.0f;
     // chip: flight time lam3 v0, carry lam1 v0^2, then roll from lam2 v0
     double ccD = lam1 + lam2 * lam2 / (2.0 * ar), ccTs = lam3 + lam2 / ar;
-    P.c_cD = (float)ccD;
+    P.c_icD = (float)(1.0 / ccD);
     P.c_icA = (float)(ccTs * ccTs / ccD);
     P.c_icB = (float)(lam3 / lam2);
     double cal = -0.5 * ar * lam3 * lam3, cbe = lam2 + ar * lam3;

@@ -29,12 +29,12 @@ struct DevParams {
     float invA2;       // 2 / amax: robot stage units (A T / 2) to seconds
     // ball model
     float a_s, a_r, ratio, cos_th, lam1_inv;  // lam1 = sin(2 th) / g  (carry = lam1 v0^2)
-    // flat inversion: stopped / rolling / sliding regimes (icA = 1 / cA,
-    // icB = 1 / cB; alpha, hbeta = beta / 2, hbeta2 = hbeta^2: the slow
-    // root's terms with numerator and denominator halved)
-    float f_cD, f_icA, f_icB, f_alpha, f_hbeta, f_hbeta2, f_hfast, f_pfast;
+    // flat inversion: stopped / rolling / sliding regimes (icD = 1 / cD,
+    // icA = 1 / cA, icB = 1 / cB; alpha, hbeta = beta / 2, hbeta2 = hbeta^2:
+    // the slow root's terms with numerator and denominator halved)
+    float f_icD, f_icA, f_icB, f_alpha, f_hbeta, f_hbeta2, f_hfast, f_pfast;
     // chip inversion: stopped / rolling / in-flight regimes (same layout)
-    float c_cD, c_icA, c_icB, c_alpha, c_hbeta, c_hbeta2, c_hfast, c_pfast;
+    float c_icD, c_icA, c_icB, c_alpha, c_hbeta, c_hbeta2, c_hfast, c_pfast;
     float half_ar;
     // scoring
     float margin_cap, w_ang_pi, w_dist, inv_dist_norm, w_margin;

@@ -469,19 +469,21 @@ __device__ __forceinline__ void count_below(const float *rt, const float *ro, fl
 // ball's distance at a fixed time grows with the kick speed).  Regimes at
 // time T: stopped (s <= cA T^2), decelerating at the slower rate
 // (quadratic in v0), or still in the fast phase (s >= cB T^2: sliding for a
-// flat kick, in the air for a chip).  Each root is written N / (Pp + sqrt M).
-// In the fast phase a flat kick slides (N = s + hfast T^2, Pp = T) and a
-// chip flies (N = s, Pp = pfast T).  The slow root 2Q / (beta T +
+// flat kick, in the air for a chip).  Stopped, the ball has covered its
+// whole range cD v0^2, so v0 = sqrt(s / cD), which depends on the sample
+// only.  In the fast phase a flat kick slides, v0 = (s + hfast T^2) / T, and
+// a chip flies, v0 = s / (pfast T).  The slow root 2Q / (beta T +
 // sqrt(4 alpha Q + beta^2 T^2)) is taken with numerator and denominator
 // halved (Q / (hbeta T + sqrt(alpha Q + hbeta^2 T^2)), hbeta = beta / 2:
 // power-of-two scalings, so the same value).  The terms that depend on the
-// sample only, s / cA, s / cB and the stopped M = cD s, come precomputed, so
+// sample only, s / cA, s / cB and the stopped root, come precomputed, so
 // that both sides share them.  T must be finite (a side with no robot has
 // no crossing; the caller skips it).  Every regime's terms are formed first
-// and then picked by plain selects, so that the lanes of a wave (samples in
-// different regimes) do not split into branches.
+// and then picked by plain selects (the fast and slow roots share one
+// division), so that the lanes of a wave (samples in different regimes) do
+// not split into branches.
 template <bool CHIP>
-__device__ __forceinline__ float vcrit(float T, float s, float s_icA, float s_icB, float m_stop,
+__device__ __forceinline__ float vcrit(float T, float s, float s_icA, float s_icB, float v_stop,
                                        float alpha, float hbeta, float hbeta2, float hfast,
                                        float pfast, float half_ar)
 {
@@ -489,36 +491,25 @@ __device__ __forceinline__ float vcrit(float T, float s, float s_icA, float s_ic
     const float Q = fmaf(half_ar, T2, s);
     const bool stop = s_icA <= T2;
     const bool fast = s_icB >= T2;
-    // (clamped here, where it is formed: m_stop >= 0 and the fast M is 0)
     const float m_slow = fmaxf(fmaf(alpha, Q, hbeta2 * T2), 0.0f);
-    const float p_slow = hbeta * T;
-    float N, Pp;
-    if (CHIP) {
-        N = (fast || stop) ? s : Q;
-        Pp = fast ? pfast * T : p_slow;
-    } else {
-        N = fast ? fmaf(hfast, T2, s) : Q;
-        N = stop ? s : N;
-        Pp = fast ? T : p_slow;
-    }
-    float M = fast ? 0.0f : m_slow;
-    Pp = stop ? 0.0f : Pp;
-    M = stop ? m_stop : M;
-    return N * hrcp(Pp + hsqrt(M));
+    const float d_slow = fmaf(hbeta, T, hsqrt(m_slow));
+    const float N = fast ? (CHIP ? s : fmaf(hfast, T2, s)) : Q;
+    const float D = fast ? (CHIP ? pfast * T : T) : d_slow;
+    return stop ? v_stop : N * hrcp(D);
 }
 
 // The side-independent terms of the inversion at the lane's samples for one
 // kick type.
 template <int KPL, bool CHIP>
 struct SampleTerms {
-    float icA[KPL], icB[KPL], mst[KPL];
+    float icA[KPL], icB[KPL], vst[KPL];
     __device__ __forceinline__ SampleTerms(const DevParams &P, const float (&sk)[KPL])
     {
 #pragma unroll
         for (int q = 0; q < KPL; ++q) {
             icA[q] = sk[q] * (CHIP ? P.c_icA : P.f_icA);
             icB[q] = sk[q] * (CHIP ? P.c_icB : P.f_icB);
-            mst[q] = sk[q] * (CHIP ? P.c_cD : P.f_cD);
+            vst[q] = hsqrt(sk[q] * (CHIP ? P.c_icD : P.f_icD));
         }
     }
 };
@@ -539,11 +530,11 @@ __device__ __forceinline__ void side_vcrit(const DevParams &P, int n_side, const
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         if (CHIP)
-            v[q] = fminf(vair[q], vcrit<true>(T[q], sk[q], st.icA[q], st.icB[q], st.mst[q],
+            v[q] = fminf(vair[q], vcrit<true>(T[q], sk[q], st.icA[q], st.icB[q], st.vst[q],
                                               P.c_alpha, P.c_hbeta, P.c_hbeta2, P.c_hfast,
                                               P.c_pfast, P.half_ar));
         else
-            v[q] = vcrit<false>(T[q], sk[q], st.icA[q], st.icB[q], st.mst[q], P.f_alpha,
+            v[q] = vcrit<false>(T[q], sk[q], st.icA[q], st.icB[q], st.vst[q], P.f_alpha,
                                 P.f_hbeta, P.f_hbeta2, P.f_hfast, P.f_pfast, P.half_ar);
     }
 }
