@@ -425,6 +425,8 @@ int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t s
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (!c->persistent) grid = a.n_tiles;
+    // one frame on a persistent grid: one best record per workgroup
+    if (c->persistent && b->n_frames == 1) a.wg_records = grid;
     void *e0 = timed ? (void *)c->ev0 : nullptr, *e1 = timed ? (void *)c->ev1 : nullptr;
     if (timed && c->ring_used < (int)c->ring0.size()) {
         e0 = (void *)c->ring0[c->ring_used];

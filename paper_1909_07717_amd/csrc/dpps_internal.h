@@ -129,6 +129,10 @@ struct LaunchArgs {
     int32_t tiles_per_frame;
     const int32_t *n_frames_dev;
     const int32_t *best_map;
+    // > 0 (one frame, persistent grid of wg_records workgroups): each
+    // workgroup keeps its best over all its tiles and writes that one record
+    // to tile_rec[blockIdx.x]; the finalize kernel reduces those records
+    int32_t wg_records;
     // with fb_on, the finalize kernel also appends each frame whose best pass
     // needs the exact fallback to the fallback tables (slot by atomic count;
     // fb.count must be 0 before the launch; fb.src is not used: the frame's

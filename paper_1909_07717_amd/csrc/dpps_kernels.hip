@@ -74,6 +74,7 @@ struct OutLDS {
     float score[MAX_VAR * MAX_TILE];
     uint8_t mask[MAX_VAR * MAX_TILE];
     TileRec wbest[MAX_WAVES];
+    TileRec wgbest;           // the workgroup's best over its tiles (one-frame launches)
 };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -838,7 +839,14 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
     const int G = (int)gridDim.x;
     const int n_tiles = a.n_frames_dev ? *a.n_frames_dev * a.tiles_per_frame : a.n_tiles;
     const int n_static = a.persistent ? max(n_tiles / G - 1, 0) * G : 0;
-    if (threadIdx.x == 0) S.bp = P.bp;  // read after the loop's first barrier
+    if (threadIdx.x == 0) {  // read after the loop's first barrier
+        S.bp = P.bp;
+        O.wgbest.key = 0ull;
+        O.wgbest.t_team = INFINITY;
+        O.wgbest.t_opp = INFINITY;
+        O.wgbest.v0 = 0.0f;
+        O.wgbest.pad = 0.0f;
+    }
     while (true) {
         // the previous tile (its staged results and records) is finished
         __syncthreads();
@@ -941,7 +949,10 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                     r.t_team = INFINITY;
                     r.t_opp = INFINITY;
                 }
-                a.tile_rec[t] = r;
+                if (!a.wg_records)
+                    a.tile_rec[t] = r;
+                else if (r.key > O.wgbest.key)
+                    O.wgbest = r;
             }
         }
         if (!reduced) {
@@ -954,19 +965,26 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             }
         }
     }
+    // (wave 0 made the last update of the workgroup's best before the barrier
+    // that ended the loop)
+    if (a.wg_records && threadIdx.x == 0) a.tile_rec[blockIdx.x] = O.wgbest;
 }
 
 // One workgroup per frame: reduce the frame's tile records to its best pass;
 // block 0 also rearms the persistent work counter for the next launch.
 __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
 {
-    __shared__ TileRec red[256];
+    __shared__ TileRec red[256 / 64];
     __shared__ int s_wi;
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
     if (f == 0 && tid == 0 && a.counter) *a.counter = 0u;
     if (a.n_frames_dev && f >= *a.n_frames_dev) return;
     const FrameDev F = a.frames[f];
+    // the frame's tile records, or one record per workgroup of a one-frame
+    // launch
+    const int rc = a.wg_records ? a.wg_records : F.tile_count;
+    const int rb = a.wg_records ? 0 : F.tile_begin;
     TileRec r;
     r.key = 0ull;
     r.v0 = 0.0f;
@@ -974,26 +992,27 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
     r.t_team = INFINITY;
     r.t_opp = INFINITY;
     // four records in flight per thread (the keys are unique: order-free)
-    for (int k0 = tid; k0 < F.tile_count; k0 += 4 * blockDim.x) {
+    for (int k0 = tid; k0 < rc; k0 += 4 * blockDim.x) {
         TileRec x[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + q * blockDim.x;
             x[q].key = 0ull;
-            if (k < F.tile_count) x[q] = a.tile_rec[F.tile_begin + k];
+            if (k < rc) x[q] = a.tile_rec[rb + k];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (x[q].key > r.key) r = x[q];
     }
-    red[tid] = r;
+    // each wave's largest key by DPP, the waves' winners through LDS
+    const unsigned long long wk = wave_max_u64(r.key);
+    const unsigned long long who = __ballot(r.key == wk);
+    if ((tid & 63) == (int)__builtin_ctzll(who)) red[tid >> 6] = r;
     if (tid == 0) s_wi = 0;
     __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s && red[tid + s].key > red[tid].key) red[tid] = red[tid + s];
-        __syncthreads();
-    }
-    const TileRec bestr = red[0];
+    TileRec bestr = red[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+        if (red[q].key > bestr.key) bestr = red[q];
     // the window of the best element: the last window whose element base is
     // not above it (bases increase with the window), searched in parallel
     const uint32_t lin = 0xFFFFFFFFu - (uint32_t)bestr.key;
