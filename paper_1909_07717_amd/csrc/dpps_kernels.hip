@@ -358,19 +358,40 @@ __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParam
         const double wn = ((double)r.w * ux - (double)r.z * uy) * 0.70710678118654752;
         fr = make_float4((float)t, (float)(q * q + 1e-30), (float)we, (float)(q * wn));
         if (SORT) {
-            // The robot's distance to the path segment [0, LA] bounds its
-            // arrival time at every sample from below, whatever its velocity:
-            // with delta = max(dist - RA, 0) in the robot stage's units, the
-            // time is at least sqrt(delta / 2) for delta <= vmax^2 / 2 (the
-            // best approach speed, sqrt(delta), is reachable) and else
-            // delta / (2 vmax) + vmax / 4 (approach at the speed limit and
-            // cruise).  Less 2^-12 for the rounding of both computations,
-            // then truncated to make room for the lane in the low bits.
+            // A lower bound on the robot's arrival time (robot stage units)
+            // at every sample of the segment [0, LA] along e.  With delta =
+            // max(dist - RA, 0) for its distance to the segment, and u' the
+            // speed toward a sample (clamped to +-vmax/sqrt 2 as the stage
+            // clamps it), the time -u'/sqrt 2 + R(u'^2 + delta) falls as u'
+            // grows up to sqrt(delta) and grows with delta, so with U the
+            // largest u' toward any sample: U < sqrt(delta) bounds it by
+            // -U/sqrt 2 + R(U^2 + delta); otherwise, whatever the velocity,
+            // by sqrt(delta / 2) for delta <= vmax^2 / 2 and else
+            // delta / (2 vmax) + vmax / 4.  U: the scaled velocity w' = (w.e,
+            // w.n) against the directions (h, q) to the samples, h in [-t,
+            // LA - t]: |w'| when w' lies among them, else the larger end.
+            // Less 2^-12 for the rounding of both computations, then
+            // truncated to make room for the lane in the low bits.
             const double tc = t < 0.0 ? -t : (t > LA ? t - LA : 0.0);
             const float dseg = hsqrt((float)(q * q + tc * tc));
             const float del = fmaxf(dseg - P.RA, 0.0f);
-            const float lb = del <= 0.5f * P.V2 ? hsqrt(0.5f * del)
-                                                : fmaf(del, P.inv2V, 0.5f * P.halfV);
+            const float qf = (float)q, h0 = (float)(-t), h1 = (float)(LA - t);
+            const float wef = (float)we, wnf = (float)wn;
+            const float sq = qf < 0.0f ? -1.0f : 1.0f;
+            const bool among = (h1 * wnf - qf * wef) * sq >= 0.0f &&
+                               (wef * qf - wnf * h0) * sq >= 0.0f;
+            const float u0 = fmaf(h0, wef, qf * wnf) * rsq(fmaxf(fmaf(h0, h0, qf * qf), 1e-30f));
+            const float u1 = fmaf(h1, wef, qf * wnf) * rsq(fmaxf(fmaf(h1, h1, qf * qf), 1e-30f));
+            const float U = med3(among ? hsqrt(fmaf(wef, wef, wnf * wnf)) : fmaxf(u0, u1),
+                                 -P.Vh, P.Vh);
+            float lb;
+            if (U * fabsf(U) < del) {
+                const float D = fmaf(U, U, del);
+                lb = fmaf(-0.70710678118654752f, U,
+                          D > P.V2 ? fmaf(D, P.inv2V, P.halfV) : hsqrt(D));
+            } else {
+                lb = del <= 0.5f * P.V2 ? hsqrt(0.5f * del) : fmaf(del, P.inv2V, 0.5f * P.halfV);
+            }
             key = (__float_as_uint(lb * (1.0f - 1.0f / 4096.0f)) & ~(uint32_t)(MAX_ROB - 1)) |
                   (uint32_t)l | (l >= n_tm ? 0x80000000u : 0u);
         }
