@@ -339,13 +339,13 @@ __device__ __forceinline__ void robot_stage_bounded(const float4 *pr, const DevP
 // staged robots (lanes = robots), in float64 and then rounded once: for robot
 // j with offset a = ball - x_j and normal n = (-e_y, e_x): t = -a.e and
 // q = a.n (scaled by amax), w = velocity / sqrt(2), and pr[j] =
-// (t, q^2, w.e, q w.n).
+// (t, q^2, w.e, q w.n).  The lane frames robot l (lanes with l >= n_rob
+// idle); every lane of the wave takes part (the row syncs are wave-wide).
 template <bool SORT>
 __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParams &P, float4 *pr,
                                                int n_rob, int n_tm, double LA, double ux,
-                                               double uy, double bx, double by)
+                                               double uy, double bx, double by, int l)
 {
-    const int l = lane_id();
     float4 fr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     uint32_t key = 0xFFFFFFFFu;
     if (l < n_rob) {
@@ -423,7 +423,7 @@ __device__ __forceinline__ void path_frame_dir(const StageLDS &S, const DevParam
 // |c - ball| A.
 __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &P, float4 *pr,
                                             int n_rob, int n_tm, double cx64, double cy64,
-                                            double bx, double by)
+                                            double bx, double by, int l)
 {
     const double ex = cx64 - bx, ey = cy64 - by;
     const double L2 = ex * ex + ey * ey;
@@ -432,7 +432,7 @@ __device__ __forceinline__ float path_frame(const StageLDS &S, const DevParams &
     const bool pos = L2 > 0.0;
     const double L = pos ? L2 * iL : 0.0;
     const double ux = pos ? ex * iL : 1.0, uy = pos ? ey * iL : 0.0;
-    path_frame_dir<true>(S, P, pr, n_rob, n_tm, L * (double)P.A, ux, uy, bx, by);
+    path_frame_dir<true>(S, P, pr, n_rob, n_tm, L * (double)P.A, ux, uy, bx, by, l);
     return (float)(L * (double)P.A);
 }
 
@@ -771,16 +771,17 @@ __device__ __forceinline__ void sbip_crossings(const StageLDS &S, const DevParam
     }
 }
 
-// Evaluate candidate point (cx, cy) for every staged variant.  myv0 / mytype
-// hold lane v's variant (lanes >= n_var: type -1).  On return lane v
-// (< n_var) holds that variant's results.  With POWER the point has one flat
-// variant at its own passing power (returned in o_v0), computed from the
-// launch's buffer and kick range.
+// Evaluate candidate point (cx, cy) for every staged variant, its path
+// frame already in pr (LA: |c - ball| A).  myv0 / mytype hold lane v's
+// variant (lanes >= n_var: type -1).  On return lane v (< n_var) holds that
+// variant's results.  With POWER the point has one flat variant at its own
+// passing power (returned in o_v0), computed from the launch's buffer and
+// kick range.
 template <int KPL, bool POWER>
-__device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, float *pm,
+__device__ void eval_point(const StageLDS &S, const DevParams &P, const float4 *pr, float *pm,
                            float myv0, int mytype, float cx, float cy, double cx64,
-                           double cy64, float &o_score, int &o_feas, float &o_tt, float &o_to,
-                           float &o_v0, const LaunchArgs &a)
+                           double cy64, float LA, float &o_score, int &o_feas, float &o_tt,
+                           float &o_to, float &o_v0, const LaunchArgs &a)
 {
     const int l = lane_id();
     const int K = KPL * 64;
@@ -788,8 +789,6 @@ __device__ void eval_point(const StageLDS &S, const DevParams &P, float4 *pr, fl
     const float bx = unif(S.bx), by = unif(S.by);
     const float ex = cx - bx, ey = cy - by;
     const float d = hsqrt(fmaf(ex, ex, ey * ey));
-    const float LA =
-        unif(path_frame(S, P, pr, n_tm + n_op, n_tm, cx64, cy64, (double)bx, (double)by));
     const double ex64 = cx64 - (double)bx, ey64 = cy64 - (double)by;
     const double d64 = sqrt64(ex64 * ex64 + ey64 * ey64);
     int my_kt, my_ko;
@@ -839,7 +838,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
     __shared__ OutLDS O;
-    __shared__ float4 PR[MAX_WAVES][PR_ENTRIES];  // each wave's path frame of its point
+    __shared__ float4 PR[MAX_WAVES][2][PR_ENTRIES];  // each wave's path frames of two points
     extern __shared__ float PMX[];              // each wave's running maxima: 4 rows of K
     __shared__ int s_tile;
     const DevParams &P = a.P;
@@ -900,7 +899,26 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         const int npts = min(TP, W.npts - tile.p0);
         unsigned long long bkey = 0ull;
         float btt = INFINITY, bto = INFINITY, bv0 = 0.0f;
-        for (int slot = w; slot < npts; slot += nw) {
+        // the wave's points in pairs, slots s0 and s0 + nw: one pass of the
+        // path-frame stage frames both (lanes 0-31 the first point's robots,
+        // lanes 32-63 the second's; a lone last point is framed twice)
+        for (int s0 = w; s0 < npts; s0 += 2 * nw) {
+            const int n_pair = s0 + nw < npts ? 2 : 1;
+            const int s1 = n_pair == 2 ? s0 + nw : s0;
+            float LA0, LA1;
+            {
+                const int p = tile.p0 + (l < 32 ? s0 : s1);
+                const int j = p / W.nx, i = p - j * W.nx;
+                const float mi = (float)(W.i0 + i) - W.halfNx;
+                const float mj = (float)(W.j0 + j) - W.halfNy;
+                const float LAl = path_frame(S, P, PR[w][l >> 5], S.n_tm + S.n_op, S.n_tm,
+                                             (double)W.h * (double)mi, (double)W.h * (double)mj,
+                                             (double)unif(S.bx), (double)unif(S.by), l & 31);
+                LA0 = readlane_f(LAl, 0);
+                LA1 = readlane_f(LAl, 32);
+            }
+            for (int g = 0; g < n_pair; ++g) {
+            const int slot = g ? s1 : s0;
             const int p = tile.p0 + slot;
             const int j = p / W.nx, i = p - j * W.nx;
             const float mi = (float)(W.i0 + i) - W.halfNx;
@@ -909,9 +927,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
             float sc, tt, to, pv0;
             int fe;
-            eval_point<KPL, POWER>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0, mytype, cx,
-                                   cy, cx64, cy64, sc, fe,
-                                   tt, to, pv0, a);
+            eval_point<KPL, POWER>(S, P, PR[w][g], PMX + w * PM_ROWS * KPL * 64, myv0, mytype, cx,
+                                   cy, cx64, cy64, g ? LA1 : LA0, sc, fe, tt, to, pv0, a);
             if (POWER && l == 0 && a.v0_out) a.v0_out[W.out_base + p] = pv0;
             unsigned long long key = 0ull;
             if (fe) {
@@ -942,6 +959,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                 O.mask[myvid * MAX_TILE + slot] = (uint8_t)fe;
                 if (a.t_team) a.t_team[W.out_base + (int64_t)myvid * W.npts + p] = tt;
                 if (a.t_opp) a.t_opp[W.out_base + (int64_t)myvid * W.npts + p] = to;
+            }
             }
         }
         // the wave's best pass (and its times), then the tile's
@@ -1270,7 +1288,7 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
     const double xd = 2.0 * (double)d / (double)n_dirs;  // theta_d / pi
     const double ux = cospi(xd), uy = sinpi(xd);
     const double L = ray_length(P, bx, by, ux, uy);
-    path_frame_dir<true>(S, P, pr, n_tm + n_op, n_tm, L * (double)P.A, ux, uy, bx, by);
+    path_frame_dir<true>(S, P, pr, n_tm + n_op, n_tm, L * (double)P.A, ux, uy, bx, by, l);
     int my_kt, my_ko;
     sbip_crossings<KPL, false>(S, P, pr, pm, myv0, mytype, (float)L, (float)(L * (double)P.A), my_kt,
                         my_ko);
@@ -1611,7 +1629,7 @@ __device__ dpps_shot shot_origin(const StageLDS &S, const DevParams &P, float4 *
     const float aim = gap > 0.0f ? fmaf(0.5f, gap, g0) : atan2f(-fy, (float)dxg);
     const double ux = (double)cosf(aim), uy = (double)sinf(aim);
     const double L = dxg / ux;
-    path_frame_dir<false>(S, P, pr, n_tm + n_op, n_tm, 0.0, ux, uy, cx, cy);
+    path_frame_dir<false>(S, P, pr, n_tm + n_op, n_tm, 0.0, ux, uy, cx, cy, l);
     const float Lf = (float)L, LA = (float)(L * (double)P.A);
     float fs[KPL], T[KPL];
 #pragma unroll
