@@ -421,7 +421,8 @@ int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t s
         a.p_vmax = power->v_max;
         a.v0_out = v0_out;
     }
-    int per_cu = c->wg_per_cu > 0 ? c->wg_per_cu : search_occupancy(c->p.n_samples, c->waves);
+    int per_cu = c->wg_per_cu > 0 ? c->wg_per_cu
+                                  : search_occupancy(c->p.n_samples, c->waves, c->tile_points);
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (!c->persistent) grid = a.n_tiles;
@@ -646,7 +647,7 @@ int dpps_get_launch(const dpps_ctx *c, int32_t *tile_points, int32_t *waves_per_
     if (wg_per_cu)
         *wg_per_cu = !c->persistent ? -1
                      : c->wg_per_cu > 0 ? c->wg_per_cu
-                                        : search_occupancy(c->p.n_samples, c->waves);
+                                        : search_occupancy(c->p.n_samples, c->waves, c->tile_points);
     return DPPS_OK;
 }
 

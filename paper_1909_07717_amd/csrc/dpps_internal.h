@@ -204,7 +204,7 @@ int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream,
 // Zero n 32-bit words of device memory on `stream` (a kernel, no memset).
 int launch_zero_words(uint32_t *p, int n, void *stream);
 // Resident workgroups per CU of the search kernel for this K and block size.
-int search_occupancy(int K, int waves_per_wg);
+int search_occupancy(int K, int waves_per_wg, int tile_points);
 // Direction x variant search (ray kernel then its finalize) on `stream`;
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the ray kernel only.
 int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,

@@ -64,6 +64,16 @@ struct StageLDS {
 
 // A wave's path-frame block: MAX_ROB entries, then MAX_ROB bound keys.
 #define PR_ENTRIES (MAX_ROB + MAX_ROB / 4)
+
+// Dynamic LDS of the search kernel, sized by the launch: each wave's
+// running-maximum rows and its two path-frame blocks, then the tile's staged
+// score and mask maps (MAX_VAR rows of tile_points).
+static size_t search_lds_bytes(int K, int waves, int tile_points)
+{
+    const size_t maps = (size_t)MAX_VAR * tile_points * (sizeof(float) + 1);
+    return pm_bytes(K, waves) + (size_t)waves * 2 * PR_ENTRIES * sizeof(float4) +
+           ((maps + 15) & ~(size_t)15);
+}
 __device__ __forceinline__ uint32_t *bound_keys(float4 *pr) { return (uint32_t *)(pr + MAX_ROB); }
 __device__ __forceinline__ const uint32_t *bound_keys(const float4 *pr)
 {
@@ -71,8 +81,6 @@ __device__ __forceinline__ const uint32_t *bound_keys(const float4 *pr)
 }
 
 struct OutLDS {
-    float score[MAX_VAR * MAX_TILE];
-    uint8_t mask[MAX_VAR * MAX_TILE];
     TileRec wbest[MAX_WAVES];
     TileRec wgbest;           // the workgroup's best over its tiles (one-frame launches)
 };
@@ -838,14 +846,18 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
 {
     __shared__ StageLDS S;
     __shared__ OutLDS O;
-    __shared__ float4 PR[MAX_WAVES][2][PR_ENTRIES];  // each wave's path frames of two points
-    extern __shared__ float PMX[];              // each wave's running maxima: 4 rows of K
+    // dynamic: each wave's running maxima (4 rows of K), its path frames of
+    // two points, the tile's staged score and mask maps
+    extern __shared__ float PMX[];
     __shared__ int s_tile;
     const DevParams &P = a.P;
     const int nw = blockDim.x >> 6;
     const int w = threadIdx.x >> 6;
     const int l = lane_id();
     const int TP = a.tile_points;
+    float4 *const PR = (float4 *)(PMX + nw * PM_ROWS * KPL * 64);
+    float *const OS = (float *)(PR + nw * 2 * PR_ENTRIES);
+    uint8_t *const OM = (uint8_t *)(OS + MAX_VAR * TP);
     const bool reduced = (P.out_flags & DPPS_OUT_REDUCED) != 0;
     int iter = 0;
     int cur_frame = -1;
@@ -911,7 +923,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                 const int j = p / W.nx, i = p - j * W.nx;
                 const float mi = (float)(W.i0 + i) - W.halfNx;
                 const float mj = (float)(W.j0 + j) - W.halfNy;
-                const float LAl = path_frame(S, P, PR[w][l >> 5], S.n_tm + S.n_op, S.n_tm,
+                const float LAl = path_frame(S, P, PR + (w * 2 + (l >> 5)) * PR_ENTRIES,
+                                             S.n_tm + S.n_op, S.n_tm,
                                              (double)W.h * (double)mi, (double)W.h * (double)mj,
                                              (double)unif(S.bx), (double)unif(S.by), l & 31);
                 LA0 = readlane_f(LAl, 0);
@@ -927,7 +940,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const double cx64 = (double)W.h * (double)mi, cy64 = (double)W.h * (double)mj;
             float sc, tt, to, pv0;
             int fe;
-            eval_point<KPL, POWER>(S, P, PR[w][g], PMX + w * PM_ROWS * KPL * 64, myv0, mytype, cx,
+            eval_point<KPL, POWER>(S, P, PR + (w * 2 + g) * PR_ENTRIES, PMX + w * PM_ROWS * KPL * 64,
+                                   myv0, mytype, cx,
                                    cy, cx64, cy64, g ? LA1 : LA0, sc, fe, tt, to, pv0, a);
             if (POWER && l == 0 && a.v0_out) a.v0_out[W.out_base + p] = pv0;
             unsigned long long key = 0ull;
@@ -955,8 +969,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
                     }
                 }
             } else if (l < n_var) {
-                O.score[myvid * MAX_TILE + slot] = sc;
-                O.mask[myvid * MAX_TILE + slot] = (uint8_t)fe;
+                OS[myvid * TP + slot] = sc;
+                OM[myvid * TP + slot] = (uint8_t)fe;
                 if (a.t_team) a.t_team[W.out_base + (int64_t)myvid * W.npts + p] = tt;
                 if (a.t_opp) a.t_opp[W.out_base + (int64_t)myvid * W.npts + p] = to;
             }
@@ -999,8 +1013,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             for (int e = threadIdx.x; e < tot; e += blockDim.x) {
                 const int v = e / npts, slot = e - v * npts;
                 const int64_t o = W.out_base + (int64_t)v * W.npts + tile.p0 + slot;
-                if (a.score) a.score[o] = O.score[v * MAX_TILE + slot];
-                if (a.mask) a.mask[o] = O.mask[v * MAX_TILE + slot];
+                if (a.score) a.score[o] = OS[v * TP + slot];
+                if (a.mask) a.mask[o] = OM[v * TP + slot];
             }
         }
     }
@@ -1129,12 +1143,13 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
 {
     if (e0) (void)hipEventRecord(e0, st);
     if (a.n_tiles > 0 && grid > 0) {
+        const size_t lds = search_lds_bytes(KPL * 64, waves_per_wg, a.tile_points);
         if (a.power)
             hipLaunchKernelGGL((search_kernel<KPL, true>), dim3(grid), dim3(64 * waves_per_wg),
-                               pm_bytes(KPL * 64, waves_per_wg), st, a);
+                               lds, st, a);
         else
             hipLaunchKernelGGL((search_kernel<KPL, false>), dim3(grid), dim3(64 * waves_per_wg),
-                               pm_bytes(KPL * 64, waves_per_wg), st, a);
+                               lds, st, a);
     }
     if (e1) (void)hipEventRecord(e1, st);
     if (a.n_frames > 0)
@@ -1881,16 +1896,17 @@ int launch_search(const LaunchArgs &a, int waves_per_wg, int grid, void *stream,
     }
 }
 
-int search_occupancy(int K, int waves_per_wg)
+int search_occupancy(int K, int waves_per_wg, int tile_points)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     const int bs = 64 * waves_per_wg;
+    const size_t lds = search_lds_bytes(K, waves_per_wg, tile_points);
     switch (K / 64) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1, false>, bs, pm_bytes(1 * 64, waves_per_wg)); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2, false>, bs, pm_bytes(2 * 64, waves_per_wg)); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3, false>, bs, pm_bytes(3 * 64, waves_per_wg)); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4, false>, bs, pm_bytes(4 * 64, waves_per_wg)); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<1, false>, bs, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<2, false>, bs, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<3, false>, bs, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, search_kernel<4, false>, bs, lds); break;
     default: break;
     }
     return e == hipSuccess && n > 0 ? n : 1;

@@ -583,7 +583,7 @@ static int propose(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dpps_best
     // few windows (small batches): eight waves share each window's 16
     // points, two points per wave, instead of the context's shape
     const int wv = (int64_t)a.n_tiles <= (int64_t)c->n_cu ? 8 : c->waves;
-    int per_cu = search_occupancy(c->p.n_samples, wv);
+    int per_cu = search_occupancy(c->p.n_samples, wv, a.tile_points);
     int64_t cap = (int64_t)c->n_cu * per_cu;
     int grid = (int)(a.n_tiles < cap ? a.n_tiles : cap);
     if (launch_search(a, wv, grid, (void *)st, nullptr, nullptr))
@@ -633,7 +633,7 @@ static int surrogate_core(dpps_ctx *c, dpps_mlp *m, dpps_batch *b, int32_t k, dp
     a.counter = m->fcounter;
     a.tile_rec = m->frec;
     a.best = d_best;
-    const int per_cu = search_occupancy(c->p.n_samples, c->waves);
+    const int per_cu = search_occupancy(c->p.n_samples, c->waves, a.tile_points);
     const int64_t cap = (int64_t)c->n_cu * per_cu;
     const int grid = (int)((int64_t)a.n_tiles < cap ? a.n_tiles : cap);
     if (launch_search(a, c->waves, grid, (void *)st, nullptr, nullptr))
