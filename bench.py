@@ -42,9 +42,10 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+def measured_counters():
+    """The committed counter summary of the full-frame search (HBM bytes per
+    launch, hardware-counted FP32 flops, VALU issue), if it was taken on the
+    current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "search_kernel_full_frame_traffic.json")
     if not os.path.exists(path):
         return None
@@ -52,7 +53,14 @@ def measured_traffic():
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    rec = measured_counters()
+    return None if rec is None else rec.get("hbm_bytes_per_launch")
 
 
 def host_cpu():
@@ -427,6 +435,16 @@ def main() -> int:
                 "flops_per_launch": fl,
                 "nonpacked_peak": FL.PEAK_FP32_NONPACKED_TFLOPS,
                 "frac_of_nonpacked": round(achieved / FL.PEAK_FP32_NONPACKED_TFLOPS, 4)}
+    # beside the modelled work: the hardware FP32 flop counter (FMA = 2,
+    # add / mul / transcendental = 1) and the VALU issue fraction of the
+    # committed counter profile, when it was taken on this kernel source
+    ctr = measured_counters()
+    if ctr is not None and ctr.get("fp32_flops_counted_per_launch"):
+        counted = ctr["fp32_flops_counted_per_launch"] / (kern_avg_ms * 1e-3) / 1e12
+        roofline.update({"counted_fp32_flops_per_launch": ctr["fp32_flops_counted_per_launch"],
+                         "counted_tflops": round(counted, 3),
+                         "counted_frac": round(counted / FL.PEAK_FP32_VECTOR_TFLOPS, 4),
+                         "valu_issue": ctr.get("valu_issue")})
     cpu = None if args.no_cpu else cpu_baseline(frame, p, args.cpu_seconds)
     if cpu is not None:
         progress("cpu baseline done")
