@@ -330,16 +330,22 @@ __device__ __forceinline__ void robot_stage_bounded(const float4 *pr, const DevP
                                                     const float (&fs)[KPL], float LA,
                                                     float (&T)[KPL])
 {
-    int done = min(n, 2);
-    robot_stage<KPL, CLAMP>(pr, P, j0, done, fs, LA, T);
-    if (n > done) {
-        int need = robots_needed<KPL>(pr, n, done, side_bit, T);
-        if (need > done + 2) {
-            robot_stage<KPL, CLAMP>(pr, P, j0 + done, 2, fs, LA, T);
-            done += 2;
-            need = robots_needed<KPL>(pr, need, done, side_bit, T);
-        }
-        robot_stage<KPL, CLAMP>(pr, P, j0 + done, need - done, fs, LA, T);
+    // one copy of the pair body (the kernel's code stays small enough for
+    // the instruction cache): the tests run after the pairs at 0 and 2
+    int need = n;
+    int j = 0;
+    for (; j + 1 < need; j += 2) {
+        const float4 ra = pr[j0 + j], rb = pr[j0 + j + 1];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q)
+            T[q] = fminf(T[q], fminf(robot_time_h<CLAMP>(ra, fs[q], LA, P),
+                                     robot_time_h<CLAMP>(rb, fs[q], LA, P)));
+        if (j < 4 && need > j + 2) need = robots_needed<KPL>(pr, need, j + 2, side_bit, T);
+    }
+    if (j < need) {
+        const float4 r = pr[j0 + j];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_h<CLAMP>(r, fs[q], LA, P));
     }
 }
 
