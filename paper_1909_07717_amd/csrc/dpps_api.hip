@@ -536,6 +536,7 @@ void dpps_destroy(dpps_ctx *c)
     batch_free_device(&c->shots);
     batch_free_device(&c->runs);
     if (c->ray_aux.ptr) (void)hipFree(c->ray_aux.ptr);
+    if (c->ray_dirs.ptr) (void)hipFree(c->ray_dirs.ptr);
     noalloc_release(c);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->pinned_best) (void)hipHostFree(c->pinned_best);
@@ -818,6 +819,16 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     // a fresh allocation starts with the work counter at zero; afterwards the
     // finalize kernel rearms it at the end of every launch
     if (c->ray_aux.ptr != old) HIP_OK(hipMemset(c->ray_aux.ptr, 0, 256));
+    // the direction table, recomputed when the direction count changes (and
+    // waited for, so that calls on other streams read it complete)
+    if (c->ray_dirs_n != rp->n_dirs) {
+        rc = arena_reserve(c, c->ray_dirs, 4096 * sizeof(double2));
+        if (rc) return rc;
+        if (launch_ray_dirs((double2 *)c->ray_dirs.ptr, rp->n_dirs, (void *)st))
+            return fail(DPPS_E_DEVICE, "direction table launch failed");
+        HIP_OK(hipStreamSynchronize(st));
+        c->ray_dirs_n = rp->n_dirs;
+    }
     RayArgs a;
     memset(&a, 0, sizeof a);
     a.P = c->P;
@@ -825,6 +836,7 @@ int dpps_ray_search(dpps_ctx *c, int32_t n_frames, const dpps_frame *frames,
     a.robots = b->d_robots;
     a.variants = b->d_variants;
     a.tiles = b->d_tiles;
+    a.dirs = (const double2 *)c->ray_dirs.ptr;
     a.n_tiles = (int32_t)nt;
     a.n_frames = n_frames;
     a.tile_dirs = td;

@@ -153,6 +153,7 @@ struct RayArgs {
     const dpps_robot *robots;
     const dpps_variant *variants;
     const TileDev *tiles;   // win = frame, p0 = first direction of the tile
+    const double2 *dirs;    // (cos, sin) of each kick direction (launch_ray_dirs)
     int32_t n_tiles;
     int32_t n_frames;
     int32_t tile_dirs;
@@ -207,6 +208,8 @@ int launch_zero_words(uint32_t *p, int n, void *stream);
 int search_occupancy(int K, int waves_per_wg, int tile_points);
 // Direction x variant search (ray kernel then its finalize) on `stream`;
 // ev_start / ev_stop (hipEvent_t or NULL) bracket the ray kernel only.
+// (cos, sin) of theta_d = 2 pi d / n for d < n into dirs (n <= 4096).
+int launch_ray_dirs(double2 *dirs, int n, void *stream);
 int launch_ray(const RayArgs &a, int waves_per_wg, int grid, void *stream, void *ev_start,
                void *ev_stop);
 int ray_occupancy(int K, int waves_per_wg);

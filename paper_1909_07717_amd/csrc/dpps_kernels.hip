@@ -1297,17 +1297,34 @@ struct RayOut {
 };
 
 // Every staged variant (lanes) for direction d of the staged frame.
+// Unit vector of each kick direction, theta_d = 2 pi d / n from +x
+// (computed once per direction count, read by every ray).
+__global__ void __launch_bounds__(256) ray_dirs_kernel(double2 *dirs, int n)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const double xd = 2.0 * (double)d / (double)n;  // theta_d / pi
+    dirs[d] = make_double2(cospi(xd), sinpi(xd));
+}
+
+int launch_ray_dirs(double2 *dirs, int n, void *stream)
+{
+    hipLaunchKernelGGL(ray_dirs_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       dirs, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int KPL>
 __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *pr, float *pm,
-                                float myv0, int mytype, int myvid, int d, int n_dirs,
+                                float myv0, int mytype, int myvid, int d, const double2 *dirs,
                                 float w_time, float w_refract)
 {
     const int l = lane_id();
     const int K = KPL * 64;
     const int n_tm = uni(S.n_tm), n_op = uni(S.n_op), n_var = uni(S.n_var);
     const double bx = (double)unif(S.bx), by = (double)unif(S.by);
-    const double xd = 2.0 * (double)d / (double)n_dirs;  // theta_d / pi
-    const double ux = cospi(xd), uy = sinpi(xd);
+    const double2 u = dirs[d];
+    const double ux = u.x, uy = u.y;
     const double L = ray_length(P, bx, by, ux, uy);
     path_frame_dir<true>(S, P, pr, n_tm + n_op, n_tm, L * (double)P.A, ux, uy, bx, by, l);
     int my_kt, my_ko;
@@ -1422,8 +1439,8 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
         for (int slot = w; slot < nd; slot += nw) {
             const int d = tile.p0 + slot;
             const RayOut o = ray_direction<KPL>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0,
-                                                mytype, myvid, d,
-                                                a.n_dirs, a.w_time, a.w_refract);
+                                                mytype, myvid, d, a.dirs, a.w_time,
+                                                a.w_refract);
             if (l < n_var) {
                 const int64_t e = base + (int64_t)d * n_var + myvid;
                 if (a.mask) a.mask[e] = (uint8_t)o.feas;

@@ -87,6 +87,8 @@ struct dpps_ctx {
     dpps_batch fallback;     // exact searches of surrogate frames without a feasible proposal
     dpps_batch rays;         // tables of dpps_ray_search
     DeviceArena ray_aux;     // its work counter and per-tile records
+    DeviceArena ray_dirs;    // unit vectors of the kick directions (4096 at most)
+    int ray_dirs_n = 0;      // the direction count they were computed for
     int ray_tile_dirs = 32;  // directions per tile of dpps_ray_search
     int ray_waves = 8;       // waves per workgroup of dpps_ray_search
     dpps_batch shots;        // tables of dpps_shot_decision
