@@ -178,3 +178,24 @@ def test_ray_invalid_arguments_and_determinism(B):
         assert np.array_equal(a[key], b[key], equal_nan=True)
     assert a["best"].tobytes() == b["best"].tobytes()
     s.close()
+
+
+def test_ray_direction_count_changes_between_calls(B):
+    """The context keeps the kick directions' unit vectors for the last
+    direction count: calls with other counts, back and forth, equal a fresh
+    context's results bit for bit (the 128-direction call is also checked
+    against the oracle)."""
+    p = Params(n_samples=64).as_f32()
+    s = B.Searcher(p)
+    f = _frame(500, 6, 6, 8, True)
+    for i, n_dirs in enumerate((128, 37, 128, 1, 37)):
+        g = _gpu(B, s, [f], n_dirs)[0]
+        fresh = B.Searcher(p)
+        h = _gpu(B, fresh, [f], n_dirs)[0]
+        fresh.close()
+        for key in ("mask", "score", "t_team", "t_opp", "s_recv"):
+            assert np.array_equal(g[key], h[key], equal_nan=True), (n_dirs, key)
+        assert g["best"].tobytes() == h["best"].tobytes(), n_dirs
+        if i == 0:
+            _compare(p, f, g, n_dirs)
+    s.close()
