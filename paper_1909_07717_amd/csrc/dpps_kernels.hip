@@ -1389,6 +1389,7 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
     extern __shared__ float PMX[];
     __shared__ RayRec WB[MAX_WAVES];
     __shared__ int s_tile;
+    __shared__ int s_dir;  // next unclaimed direction slot of the tile
     const DevParams &P = a.P;
     const int nw = blockDim.x >> 6;
     const int w = threadIdx.x >> 6;
@@ -1403,7 +1404,10 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
     const int R = max(a.n_tiles / G - 1, 0);
     const int n_static = R * G;
     int iter = 0;
-    if (threadIdx.x == 0) S.bp = P.bp;  // read after the loop's first barrier
+    if (threadIdx.x == 0) {  // read after the loop's first barrier
+        S.bp = P.bp;
+        s_dir = nw;
+    }
     while (true) {
         __syncthreads();  // the previous tile is finished
         int t = iter < R ? (int)blockIdx.x * R + iter : n_static;
@@ -1436,7 +1440,9 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
             WB[w].t_team = WB[w].t_opp = WB[w].s_recv = INFINITY;
             WB[w].open_angle = WB[w].refract = WB[w].pad = 0.0f;
         }
-        for (int slot = w; slot < nd; slot += nw) {
+        // each wave takes slot w, then claims the tile's next free slot as it
+        // finishes one (directions differ in cost: the waves end together)
+        for (int slot = w; slot < nd;) {
             const int d = tile.p0 + slot;
             const RayOut o = ray_direction<KPL>(S, P, PR[w], PMX + w * PM_ROWS * KPL * 64, myv0,
                                                 mytype, myvid, d, a.dirs, a.w_time,
@@ -1462,10 +1468,15 @@ __global__ void __launch_bounds__(512, 4) ray_kernel(RayArgs a)
                     WB[w].refract = o.refract;
                 }
             }
+            int nx = 0;
+            if (l == 0) nx = atomicAdd(&s_dir, 1);
+            slot = uni(nx);
         }
         // the tile's best of the waves' records (keys of different waves
-        // differ unless both are 0)
+        // differ unless both are 0); the slot counter is rearmed for the
+        // next tile, whose first barrier orders it before any claim
         __syncthreads();
+        if (threadIdx.x == 0) s_dir = nw;
         if (w == 0) {
             const unsigned long long k = l < nw ? WB[l].key : 0ull;
             const unsigned long long tk = wave_max_u64(k);
