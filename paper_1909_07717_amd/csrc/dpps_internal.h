@@ -57,7 +57,10 @@ struct WinDev {
     int64_t out_base;       // absolute output element of this window's first (reduced) element
 };
 
-// A tile: up to tile_points consecutive points of one window.
+// A tile of the passing-point search: p0 / tile_points = k, and the tile
+// holds points k, k + T, k + 2T, ... (up to tile_points of them) of a window
+// cut into T tiles.  A tile of the shot map: points p0 .. p0 + tile_points -
+// 1; of the direction sweep: directions p0 .. p0 + tile_dirs - 1.
 struct TileDev {
     int32_t win;
     int32_t p0;
@@ -121,8 +124,8 @@ struct LaunchArgs {
     float *t_opp;
     dpps_best *best;
     // Tables built on the device (the exact fallback of the surrogate search):
-    // with tiles_per_frame > 0 the tiles are implicit (tile t covers window
-    // t / tiles_per_frame from point (t % tiles_per_frame) * tile_points),
+    // with tiles_per_frame > 0 the tiles are implicit (tile t is tile
+    // t % tiles_per_frame of window t / tiles_per_frame),
     // and with n_frames_dev the number of frames is read on the device
     // (n_frames and n_tiles are then upper bounds); with best_map, frame f's
     // best record goes to best[best_map[f]].

@@ -914,7 +914,13 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             myvid = l < nv ? S.vidx[l] : 0;
         }
         const int n_var = S.n_var;
-        const int npts = min(TP, W.npts - tile.p0);
+        // tile k of a window cut into T tiles holds the window's points k,
+        // k + T, k + 2T, ...: every tile samples the whole window, so tiles
+        // cost alike (neighbouring points cost alike, distant ones do not)
+        // and the last round of tiles ends together
+        const int tk = tile.p0 / TP;
+        const int Tw = max((W.npts + TP - 1) / TP, 1);
+        const int npts = tk < Tw ? min(TP, (W.npts - tk + Tw - 1) / Tw) : 0;
         unsigned long long bkey = 0ull;
         float btt = INFINITY, bto = INFINITY, bv0 = 0.0f;
         // the wave's points in pairs, slots s0 and s0 + nw: one pass of the
@@ -925,7 +931,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int s1 = n_pair == 2 ? s0 + nw : s0;
             float LA0, LA1;
             {
-                const int p = tile.p0 + (l < 32 ? s0 : s1);
+                const int p = tk + (l < 32 ? s0 : s1) * Tw;
                 const int j = p / W.nx, i = p - j * W.nx;
                 const float mi = (float)(W.i0 + i) - W.halfNx;
                 const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -938,7 +944,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             }
             for (int g = 0; g < n_pair; ++g) {
             const int slot = g ? s1 : s0;
-            const int p = tile.p0 + slot;
+            const int p = tk + slot * Tw;
             const int j = p / W.nx, i = p - j * W.nx;
             const float mi = (float)(W.i0 + i) - W.halfNx;
             const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -1018,7 +1024,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int tot = n_var * npts;
             for (int e = threadIdx.x; e < tot; e += blockDim.x) {
                 const int v = e / npts, slot = e - v * npts;
-                const int64_t o = W.out_base + (int64_t)v * W.npts + tile.p0 + slot;
+                const int64_t o = W.out_base + (int64_t)v * W.npts + tk + slot * Tw;
                 if (a.score) a.score[o] = OS[v * TP + slot];
                 if (a.mask) a.mask[o] = OM[v * TP + slot];
             }
