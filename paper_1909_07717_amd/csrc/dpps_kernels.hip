@@ -1178,23 +1178,103 @@ static int launch_kpl(const LaunchArgs &a, int waves_per_wg, int grid, hipStream
 template <int N>
 __device__ __forceinline__ float row_newbcast(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xf, 0xf,
-                                                      false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, true));
+}
+
+// Lane l ^ m within each group of 4 lanes (m = 1, 2, 3; DPP quad_perm; every
+// source lane exists, so no old value is needed).
+template <int M>
+__device__ __forceinline__ float quad_xor(float v)
+{
+    constexpr int ctrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : 0x1B;
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xf, 0xf, true));
+}
+
+// Lane l ^ 7 within each group of 8 lanes (DPP row_half_mirror).
+__device__ __forceinline__ float half_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, true));
+}
+
+// Lane l ^ 15 within each row of 16 lanes (DPP row_mirror).
+__device__ __forceinline__ float row_mirror(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xf, 0xf, true));
+}
+
+// Sum over each group of GS (8 or 16) lanes, on every lane of the group:
+// pairs, then quads, then halves (each partner holds the same partial sum,
+// so every lane gets the same bits).
+template <int GS>
+__device__ __forceinline__ float group_sum(float c)
+{
+    c += quad_xor<1>(c);
+    c += quad_xor<2>(c);
+    c += half_mirror(c);
+    if (GS == 16) c += row_mirror(c);
+    return c;
+}
+
+// Covered length of the union of the intervals [s, e] held by the lanes of
+// each group of GS lanes (GS = 8, or 16 for up to n <= 16 intervals; lane o of
+// a group holds interval o, has marks a real interval, no end exceeds hi), on
+// every lane of the group: each interval adds what the group's intervals
+// sorted before it (by start, then index) have not covered.  M, the largest
+// end among those, is formed with a median against hi, which needs no NaN
+// quieting.
+template <int GS>
+__device__ __forceinline__ float group_cover(float s, float e, bool has, float hi, int o, int n)
+{
+    const float sh = has ? s : INFINITY;  // a start of +inf marks no interval
+    float M = -INFINITY;
+    if (GS == 8) {
+        // interval of lane o ^ m of the group for m = 1..7 by DPP lane swaps
+        // (l ^ m = l ^ 7 ^ (m ^ 7) for m >= 4); that lane sorts before this
+        // one on equal starts when o has the highest bit of m set
+        const float hs = half_mirror(sh), he = half_mirror(e);
+        const bool hb1 = (o & 1) != 0, hb2 = (o & 2) != 0, hb4 = (o & 4) != 0;
+#define GC_UNION(SJ, EJ, HB)                                             \
+    {                                                                    \
+        const float sj = (SJ), ej = (EJ);                                \
+        const bool before = (sj < sh) || ((sj == sh) && (HB));           \
+        M = before ? __builtin_amdgcn_fmed3f(M, ej, hi) : M;             \
+    }
+        GC_UNION(quad_xor<1>(sh), quad_xor<1>(e), hb1)
+        GC_UNION(quad_xor<2>(sh), quad_xor<2>(e), hb2)
+        GC_UNION(quad_xor<3>(sh), quad_xor<3>(e), hb2)
+        GC_UNION(quad_xor<3>(hs), quad_xor<3>(he), hb4)
+        GC_UNION(quad_xor<2>(hs), quad_xor<2>(he), hb4)
+        GC_UNION(quad_xor<1>(hs), quad_xor<1>(he), hb4)
+        GC_UNION(hs, he, hb4)
+#undef GC_UNION
+    } else {
+        // interval j of the group by a row broadcast of lane j
+#define GC_STEP(J)                                                                    \
+    if (J < n) {                                                                      \
+        const float sj = row_newbcast<J>(sh), ej = row_newbcast<J>(e);                \
+        const bool before = (sj < sh) || ((sj == sh) && (J < o));                     \
+        M = before ? __builtin_amdgcn_fmed3f(M, ej, hi) : M;                          \
+    }
+        GC_STEP(0) GC_STEP(1) GC_STEP(2) GC_STEP(3)
+        GC_STEP(4) GC_STEP(5) GC_STEP(6) GC_STEP(7)
+        GC_STEP(8) GC_STEP(9) GC_STEP(10) GC_STEP(11)
+        GC_STEP(12) GC_STEP(13) GC_STEP(14) GC_STEP(15)
+#undef GC_STEP
+    }
+    return group_sum<GS>(has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f);
 }
 
 // Open goal angle at up to 64 / GS points at once: lane GS g + o looks at
-// point g (its own cx, cy) and opponent o (GS = 16 for up to 16 opponents,
-// 8 for up to 8).  The same construction as open_angle within each group of
-// GS lanes; returns on every lane the angle of its group's point.
+// point g (its own cx, cy, and the point's goal-post angles lo, hi) and
+// opponent o (GS = 16 for up to 16 opponents, 8 for up to 8).  The same
+// construction as open_angle within each group of GS lanes; returns on every
+// lane the angle of its group's point.
 template <int GS>
 __device__ float open_angle_groups(const StageLDS &S, const DevParams &P, float cx, float cy,
-                                   int n_op, int n_tm)
+                                   float lo, float hi, int n_op, int n_tm)
 {
     const int l = lane_id();
     const int o = l & (GS - 1), base = l & (64 - GS);
-    const float dxg = fmaxf(P.goal_x - cx, P.goal_eps);
-    const float lo = atan2f(-P.half_goal_w - cy, dxg);
-    const float hi = atan2f(P.half_goal_w - cy, dxg);
     const float4 r = S.rob[n_tm + (o < n_op ? o : 0)];
     const float ox = r.x - cx, oy = r.y - cy;
     const bool valid = o < n_op && r.x < P.goal_x;
@@ -1205,35 +1285,7 @@ __device__ float open_angle_groups(const StageLDS &S, const DevParams &P, float 
     const float s = fmaxf(ang - al, lo);
     const float e = fminf(ang + al, hi);
     const bool has = valid && e > s;
-    // each interval adds what the group's intervals sorted before it (by
-    // start, then index) have not covered; interval j of the group comes by
-    // a DPP row broadcast of lane j of the group's half of the 16-lane row
-    // (a start of +inf marks no interval)
-    const float sh = has ? s : INFINITY;
-    const bool upper = GS == 8 && (l & 8) != 0;
-    float M = -INFINITY;
-#define OAG_STEP(J)                                                                   \
-    if (J < n_op && J < GS) {                                                         \
-        float sj = row_newbcast<J>(sh), ej = row_newbcast<J>(e);                      \
-        if (GS == 8) {                                                                \
-            const float su = row_newbcast<(J + 8) & 15>(sh);                          \
-            const float eu = row_newbcast<(J + 8) & 15>(e);                           \
-            sj = upper ? su : sj;                                                     \
-            ej = upper ? eu : ej;                                                     \
-        }                                                                             \
-        const bool before = sj < sh || (sj == sh && J < o);                           \
-        M = before ? fmaxf(M, ej) : M;                                                \
-    }
-    OAG_STEP(0) OAG_STEP(1) OAG_STEP(2) OAG_STEP(3)
-    OAG_STEP(4) OAG_STEP(5) OAG_STEP(6) OAG_STEP(7)
-    OAG_STEP(8) OAG_STEP(9) OAG_STEP(10) OAG_STEP(11)
-    OAG_STEP(12) OAG_STEP(13) OAG_STEP(14) OAG_STEP(15)
-#undef OAG_STEP
-    float c = has ? fmaxf(e - fmaxf(s, M), 0.0f) : 0.0f;
-    c += __shfl_xor(c, 1, 64);
-    c += __shfl_xor(c, 2, 64);
-    c += __shfl_xor(c, 4, 64);
-    if (GS == 16) c += __shfl_xor(c, 8, 64);
+    const float c = group_cover<GS>(s, e, has, hi, o, n_op);
     const unsigned long long gmask = GS == 16 ? 0xFFFFull : 0xFFull;
     const bool gin = ((__ballot(inside) >> base) & gmask) != 0ull;
     return gin ? 0.0f : (hi - lo) - c;
@@ -1241,11 +1293,14 @@ __device__ float open_angle_groups(const StageLDS &S, const DevParams &P, float 
 
 // Open goal angles at the passing points of a direction's feasible variants
 // (lanes): a feasible lane whose passing sample differs from the previous
-// feasible lane's leads; the leaders' points go 64 / GS at a time through
-// open_angle_groups, and the other feasible lanes take their leader's angle.
+// feasible lane's leads.  The leaders write their points and goal-post
+// angles, in lane order, to the wave's LDS block scr (64 float4; free once
+// the crossings are known), their points go 64 / GS at a time through
+// open_angle_groups, each angle goes back to its leader's entry, and every
+// feasible lane reads its leader's.
 template <int GS>
-__device__ float leader_angles(const StageLDS &S, const DevParams &P, bool feas, int my_k,
-                               float px, float py, float bx, float by, int n_op, int n_tm)
+__device__ float leader_angles(const StageLDS &S, const DevParams &P, float *scr, bool feas,
+                               int my_k, float px, float py, int n_op, int n_tm)
 {
     constexpr int NG = 64 / GS;
     const int l = lane_id();
@@ -1255,31 +1310,26 @@ __device__ float leader_angles(const StageLDS &S, const DevParams &P, bool feas,
     const int kprev = __shfl(my_k, prevl, 64);
     const bool lead = feas && (below == 0ull || kprev != my_k);
     const unsigned long long lm = __ballot(lead);
-    float my_ang = 0.0f;
-    const int g = l / GS;
-    for (unsigned long long mm = lm; mm;) {
-        int lv[NG];
-        float cxg = bx, cyg = by;
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-            lv[q] = mm ? __builtin_ctzll(mm) : -1;
-            mm = mm ? mm & (mm - 1) : mm;
-            const float gx = lv[q] >= 0 ? readlane_f(px, lv[q]) : bx;
-            const float gy = lv[q] >= 0 ? readlane_f(py, lv[q]) : by;
-            cxg = g == q ? gx : cxg;
-            cyg = g == q ? gy : cyg;
-        }
-        const float a = open_angle_groups<GS>(S, P, cxg, cyg, n_op, n_tm);
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-            const float aq = readlane_f(a, GS * q);
-            my_ang = (lv[q] >= 0 && l == lv[q]) ? aq : my_ang;
-        }
+    const int n_lead = __popcll(lm);
+    float4 *const pts = (float4 *)scr;
+    wave_lds_sync();  // the crossing searches are done with the block
+    if (lead) {
+        const float dxg = fmaxf(P.goal_x - px, P.goal_eps);
+        pts[__popcll(lm & ((1ull << l) - 1ull))] =
+            make_float4(px, py, atan2f(-P.half_goal_w - py, dxg), atan2f(P.half_goal_w - py, dxg));
     }
+    wave_lds_sync();
+    for (int c0 = 0; c0 < n_lead; c0 += NG) {
+        const int idx = c0 + l / GS;
+        const float4 q = pts[min(idx, n_lead - 1)];
+        const float a = open_angle_groups<GS>(S, P, q.x, q.y, q.z, q.w, n_op, n_tm);
+        if ((l & (GS - 1)) == 0 && idx < n_lead) scr[4 * idx + 2] = a;
+    }
+    wave_lds_sync();
+    // a feasible lane's leader is the last leader at or below it
     const unsigned long long upto = l == 63 ? lm : lm & ((2ull << l) - 1ull);
-    const int lead_l = upto ? 63 - __builtin_clzll(upto) : l;
-    const float la = __shfl(my_ang, lead_l, 64);
-    return feas ? la : 0.0f;
+    const float la = feas ? scr[4 * (__popcll(upto) - 1) + 2] : 0.0f;
+    return la;
 }
 
 // Distance from the ball along (ux, uy) to the edge of the field (0 when the
@@ -1364,10 +1414,10 @@ __device__ RayOut ray_direction(const StageLDS &S, const DevParams &P, float4 *p
         py = by + st * uy;
     }
     // open goal angle at each feasible passing point
-    const float my_ang = n_op <= 8 ? leader_angles<8>(S, P, o.feas != 0, my_kt, (float)px, (float)py,
-                                                      (float)bx, (float)by, n_op, n_tm)
-                                   : leader_angles<16>(S, P, o.feas != 0, my_kt, (float)px,
-                                                       (float)py, (float)bx, (float)by, n_op, n_tm);
+    const float my_ang = n_op <= 8 ? leader_angles<8>(S, P, pm, o.feas != 0, my_kt, (float)px,
+                                                      (float)py, n_op, n_tm)
+                                   : leader_angles<16>(S, P, pm, o.feas != 0, my_kt, (float)px,
+                                                       (float)py, n_op, n_tm);
     if (o.feas) {
         const double gx = (double)P.goal_x - px, gy = -py;
         const float dg = (float)sqrt(gx * gx + gy * gy);
