@@ -58,8 +58,8 @@ struct WinDev {
 };
 
 // A tile of the passing-point search: p0 / tile_points = k, and the tile
-// holds points k, k + T, k + 2T, ... (up to tile_points of them) of a window
-// cut into T tiles.  A tile of the shot map: points p0 .. p0 + tile_points -
+// holds chunks k, k + T, k + 2T, ... of 4 consecutive points (up to
+// tile_points points) of a window cut into T tiles.  A tile of the shot map: points p0 .. p0 + tile_points -
 // 1; of the direction sweep: directions p0 .. p0 + tile_dirs - 1.
 struct TileDev {
     int32_t win;

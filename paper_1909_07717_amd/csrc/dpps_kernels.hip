@@ -914,13 +914,21 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             myvid = l < nv ? S.vidx[l] : 0;
         }
         const int n_var = S.n_var;
-        // tile k of a window cut into T tiles holds the window's points k,
-        // k + T, k + 2T, ...: every tile samples the whole window, so tiles
-        // cost alike (neighbouring points cost alike, distant ones do not)
-        // and the last round of tiles ends together
+        // the window's points in chunks of CH; tile k of a window cut into T
+        // tiles holds chunks k, k + T, k + 2T, ...: every tile samples the
+        // whole window, so tiles cost alike (neighbouring points cost alike,
+        // distant ones do not) and the last round of tiles ends together,
+        // while each chunk's outputs are still written as one 16-byte piece
+        // per variant.  Slot s of the tile is point (k + (s / CH) T) CH +
+        // s % CH; only the window's last chunk can be short, and it is the
+        // last chunk of its tile.
+        constexpr int CH = 4;
         const int tk = tile.p0 / TP;
-        const int Tw = max((W.npts + TP - 1) / TP, 1);
-        const int npts = tk < Tw ? min(TP, (W.npts - tk + Tw - 1) / Tw) : 0;
+        const int NC = (W.npts + CH - 1) / CH, cpt = TP / CH;
+        const int Tw = max((NC + cpt - 1) / cpt, 1);  // = ceil(npts / TP)
+        const int nch = tk < Tw ? min(cpt, (NC - tk + Tw - 1) / Tw) : 0;
+        const int npts =
+            nch > 0 ? (nch - 1) * CH + min(CH, W.npts - (tk + (nch - 1) * Tw) * CH) : 0;
         unsigned long long bkey = 0ull;
         float btt = INFINITY, bto = INFINITY, bv0 = 0.0f;
         // the wave's points in pairs, slots s0 and s0 + nw: one pass of the
@@ -931,7 +939,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int s1 = n_pair == 2 ? s0 + nw : s0;
             float LA0, LA1;
             {
-                const int p = tk + (l < 32 ? s0 : s1) * Tw;
+                const int sl = l < 32 ? s0 : s1;
+                const int p = (tk + (sl / CH) * Tw) * CH + (sl & (CH - 1));
                 const int j = p / W.nx, i = p - j * W.nx;
                 const float mi = (float)(W.i0 + i) - W.halfNx;
                 const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -944,7 +953,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             }
             for (int g = 0; g < n_pair; ++g) {
             const int slot = g ? s1 : s0;
-            const int p = tk + slot * Tw;
+            const int p = (tk + (slot / CH) * Tw) * CH + (slot & (CH - 1));
             const int j = p / W.nx, i = p - j * W.nx;
             const float mi = (float)(W.i0 + i) - W.halfNx;
             const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -1024,7 +1033,8 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int tot = n_var * npts;
             for (int e = threadIdx.x; e < tot; e += blockDim.x) {
                 const int v = e / npts, slot = e - v * npts;
-                const int64_t o = W.out_base + (int64_t)v * W.npts + tk + slot * Tw;
+                const int64_t o = W.out_base + (int64_t)v * W.npts + (tk + (slot / CH) * Tw) * CH +
+                                  (slot & (CH - 1));
                 if (a.score) a.score[o] = OS[v * TP + slot];
                 if (a.mask) a.mask[o] = OM[v * TP + slot];
             }
