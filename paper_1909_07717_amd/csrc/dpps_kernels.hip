@@ -1225,6 +1225,27 @@ __device__ __forceinline__ float group_sum(float c)
     return c;
 }
 
+// Least / greatest value over the wave (DPP within each row of 16 lanes,
+// then the four rows), on every lane.
+__device__ __forceinline__ float wave_min_dpp(float x)
+{
+    x = fminf(x, quad_xor<1>(x));
+    x = fminf(x, quad_xor<2>(x));
+    x = fminf(x, half_mirror(x));
+    x = fminf(x, row_mirror(x));
+    return fminf(fminf(readlane_f(x, 0), readlane_f(x, 16)),
+                 fminf(readlane_f(x, 32), readlane_f(x, 48)));
+}
+__device__ __forceinline__ float wave_max_dpp(float x)
+{
+    x = fmaxf(x, quad_xor<1>(x));
+    x = fmaxf(x, quad_xor<2>(x));
+    x = fmaxf(x, half_mirror(x));
+    x = fmaxf(x, row_mirror(x));
+    return fmaxf(fmaxf(readlane_f(x, 0), readlane_f(x, 16)),
+                 fmaxf(readlane_f(x, 32), readlane_f(x, 48)));
+}
+
 // Covered length of the union of the intervals [s, e] held by the lanes of
 // each group of GS lanes (GS = 8, or 16 for up to n <= 16 intervals; lane o of
 // a group holds interval o, has marks a real interval, no end exceeds hi), on
@@ -1667,11 +1688,55 @@ __device__ __forceinline__ float ball_time32(const VarConst &c, float s)
     return fmaf(2.0f * x, hrcp(va + hsqrt(q)), to);
 }
 
-__device__ __forceinline__ float wave_min_f(float x)
+// Earliest arrival (A T / 2), at each of the lane's samples, of the
+// opponents [n_tm, n_tm + n_op) of a shot's path frame, sorted by ascending
+// lower bound on their arrival over the path -- for the shot's least slack
+// only.  After the first two opponents, and again after the next two, the
+// slack so far is taken: the least, over the samples the ball reaches
+// (sk <= D), of the arrival less the ball's time tb there; tbm is the latest
+// of those ball times.  An opponent whose bound less tbm is not below that
+// slack cannot lower it at any sample (its arrival is at least the bound, the
+// ball's time at most tbm, and both roundings are monotone; the bound is
+// shaved by 2^-16 and tbm raised by 2^-18 to cover the two forms'
+// roundings), nor can the opponents after it in the sorted order: they are
+// left out.  The minima can then differ at some samples; the least slack
+// cannot.
+template <int KPL>
+__device__ __forceinline__ void shot_opponents(const float4 *pr, const DevParams &P, int n_tm,
+                                               int n_op, const float (&fs)[KPL],
+                                               const float (&sk)[KPL], const float (&tb)[KPL],
+                                               float D, float LA, float tbm, float (&T)[KPL])
 {
+    const float tbh = tbm * (1.0f + 1.0f / 262144.0f);
+    int need = n_op;
+    int j = 0;
+    for (; j + 1 < need; j += 2) {
+        const float4 ra = pr[n_tm + j], rb = pr[n_tm + j + 1];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, 64));
-    return x;
+        for (int q = 0; q < KPL; ++q)
+            T[q] = fminf(T[q], fminf(robot_time_h<true>(ra, fs[q], LA, P),
+                                     robot_time_h<true>(rb, fs[q], LA, P)));
+        if (j < 4 && need > j + 2) {
+            float m = INFINITY;
+#pragma unroll
+            for (int q = 0; q < KPL; ++q) {
+                const float d = T[q] * P.invA2 - tb[q];
+                m = sk[q] <= D ? fminf(m, d) : m;
+            }
+            m = wave_min_dpp(m);
+            const int l = lane_id();
+            const uint32_t k = l < MAX_ROB ? bound_keys(pr)[l] : 0xFFFFFFFFu;
+            const float kv = __uint_as_float(k & 0x7FFFFFFFu & ~(uint32_t)(MAX_ROB - 1));
+            const bool opp = k != 0xFFFFFFFFu && (k & 0x80000000u) != 0u;
+            const bool out = fmaf(kv * (1.0f - 1.0f / 65536.0f), P.invA2, -tbh) >= m;
+            need = min(max((int)__builtin_popcountll(__ballot(opp && !out)), j + 2), need);
+        }
+    }
+    if (j < need) {
+        const float4 r = pr[n_tm + j];
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) T[q] = fminf(T[q], robot_time_h<true>(r, fs[q], LA, P));
+    }
 }
 
 // Open gaps of the goal mouth seen from (cx, cy); lanes are opponents, lane 62
@@ -1744,24 +1809,27 @@ __device__ dpps_shot shot_origin(const StageLDS &S, const DevParams &P, float4 *
     const float aim = gap > 0.0f ? fmaf(0.5f, gap, g0) : atan2f(-fy, (float)dxg);
     const double ux = (double)cosf(aim), uy = (double)sinf(aim);
     const double L = dxg / ux;
-    path_frame_dir<false>(S, P, pr, n_tm + n_op, n_tm, 0.0, ux, uy, cx, cy, l);
+    path_frame_dir<true>(S, P, pr, n_tm + n_op, n_tm, L * (double)P.A, ux, uy, cx, cy, l);
     const float Lf = (float)L, LA = (float)(L * (double)P.A);
-    float fs[KPL], T[KPL];
+    const float D = (float)vc.D;
+    float fs[KPL], sk[KPL], tb[KPL], T[KPL];
+    float tbm = -INFINITY;
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
         fs[q] = (float)(q * 64 + l + 1) * (1.0f / (float)K);
+        sk[q] = fs[q] * Lf;
+        tb[q] = ball_time32(vc, sk[q]);
         T[q] = INFINITY;
+        tbm = sk[q] <= D ? fmaxf(tbm, tb[q]) : tbm;
     }
-    robot_stage<KPL, true>(pr, P, n_tm, n_op, fs, LA, T);
-    const float D = (float)vc.D;
+    shot_opponents<KPL>(pr, P, n_tm, n_op, fs, sk, tb, D, LA, wave_max_dpp(tbm), T);
     float m = INFINITY;
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
-        const float sk = fs[q] * Lf;
-        const float d = T[q] * P.invA2 - ball_time32(vc, sk);
-        m = sk <= D ? fminf(m, d) : m;
+        const float d = T[q] * P.invA2 - tb[q];
+        m = sk[q] <= D ? fminf(m, d) : m;
     }
-    m = wave_min_f(m);
+    m = wave_min_dpp(m);
     dpps_shot r;
     r.reachable = L <= vc.D;
     r.aim = aim;
