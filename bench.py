@@ -412,7 +412,7 @@ def main() -> int:
         lf = min(args.latency_frames, 2000)
         rays = ray_bench(args.ray_frames, 5, lf, st)
         progress("direction sweep done")
-        power = power_bench(20, st)
+        power = power_bench(20, st, launch=shape)  # the full frame's lattice and K
         progress("passing power done")
         shots = shot_bench(4096, 20, lf, st)
         progress("shots done")

@@ -132,6 +132,8 @@ def main():
     m.add_argument("--steps", type=int, default=20)
     w = sub.add_parser("rows")
     w.add_argument("--steps", type=int, default=5)
+    w.add_argument("--power-launch", type=int, nargs=3, default=None,
+                   metavar=("TILE", "WAVES", "WG_PER_CU"))
     q = sub.add_parser("latency")
     q.add_argument("--frames", type=int, default=300)
     q.add_argument("--warmup", type=int, default=50)
@@ -147,7 +149,7 @@ def main():
 
         from paper_1909_07717_amd import rows_bench as R
         st = torch.cuda.Stream()
-        out = {"power": R.power_bench(args.steps, st),
+        out = {"power": R.power_bench(args.steps, st, launch=args.power_launch),
                "shots": R.shot_bench(4096, args.steps, 20, st),
                "running": R.run_bench(4096, args.steps, 20, st),
                "rays": R.ray_bench(512, args.steps, 20, st)}

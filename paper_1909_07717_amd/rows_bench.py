@@ -9,11 +9,13 @@ import time
 from paper_1909_07717_amd.zones import front_zones
 
 
-def power_bench(steps: int, st):
+def power_bench(steps: int, st, launch=None):
     """Per-point passing power (Sec. 4.1, Eq. 1-2): the full frame's 8v8 robots
     and 5 cm lattice (43 621 points), one flat pass per point at the point's
     own power (receiver + 0.3 s, kick range 1-6.5 m/s), K = 256; inputs staged
-    from the host on every call."""
+    from the host on every call.  launch: (tile points, waves, workgroups per
+    CU) for the search, e.g. the full frame's tuned shape (same lattice and
+    K); None keeps the context's default."""
     import torch
 
     from paper_1909_07717_amd import binding as Bn
@@ -22,6 +24,9 @@ def power_bench(steps: int, st):
     p = Params(n_samples=256).as_f32()
     f = config_full(100)
     s = Bn.Searcher(p, device=0)
+    if launch is not None:
+        s.set_launch(*launch)
+    shape = s.get_launch()
     with torch.cuda.stream(st):
         out, v0 = s.search_power([f], stream=st)
     torch.cuda.synchronize()
@@ -40,7 +45,9 @@ def power_bench(steps: int, st):
                         "own power (Eq. 1-2), K = 256", "points": 43621,
             "ms_per_frame": round(ms, 4), "points_per_s": round(43621 / (ms * 1e-3), 1),
             "feasible_points": feas, "v0_min": round(float(vv.min()), 4),
-            "v0_max": round(float(vv.max()), 4)}
+            "v0_max": round(float(vv.max()), 4),
+            "launch": {"tile_points": shape[0], "waves_per_wg": shape[1],
+                       "wg_per_cu": shape[2]}}
 
 
 def shot_bench(n_frames: int, steps: int, lat_frames: int, st):
