@@ -405,6 +405,9 @@ int run_batch(dpps_ctx *c, dpps_batch *b, const dpps_outputs *out, hipStream_t s
     a.n_tiles = (int32_t)b->T.tiles.size();
     a.n_frames = b->n_frames;
     a.tile_points = c->tile_points;
+    // the search kernel cuts a tile into chunks of 4 points
+    if (a.tile_points < 4 || a.tile_points % 4)
+        return fail(DPPS_E_INVALID, "tile_points %d is not a multiple of 4", a.tile_points);
     a.persistent = c->persistent;
     a.counter = b->d_counter;
     a.tile_rec = b->d_tile_rec;
