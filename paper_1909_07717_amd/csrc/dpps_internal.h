@@ -112,7 +112,8 @@ struct LaunchArgs {
     int32_t n_frames;
     int32_t tile_points;
     int32_t persistent;
-    uint32_t *counter;      // persistent work counter; the finalize kernel resets it
+    uint32_t *counter;      // 8 persistent work counters (one per class of workgroup
+                            // index mod 8); the finalize kernel resets them
     TileRec *tile_rec;      // one per tile
     // per-point passing power (Eq. 1-2) instead of the frames' variants
     int32_t power;

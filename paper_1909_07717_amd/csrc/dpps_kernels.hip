@@ -890,7 +890,15 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         __syncthreads();
         int t = (int)blockIdx.x + iter * G;
         if (a.persistent && t >= n_static) {
-            if (threadIdx.x == 0) s_tile = n_static + (int)atomicAdd(a.counter, 1u);
+            // a persistent grid's workgroup b sits on XCD b % 8, and so do
+            // its static tiles when the grid is a multiple of 8; its dynamic
+            // tiles keep that class too, from one counter per class, so
+            // that the tiles an XCD runs together write neighbouring chunks
+            // (below) and its L2 merges their lines.  C classes: every class
+            // has a workgroup (a grid under 8 workgroups uses G classes).
+            const int C = min(G, 8);
+            const int x = (int)blockIdx.x % C;
+            if (threadIdx.x == 0) s_tile = n_static + C * (int)atomicAdd(a.counter + x, 1u) + x;
             __syncthreads();
             t = s_tile;
         }
@@ -915,20 +923,23 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
         }
         const int n_var = S.n_var;
         // the window's points in chunks of CH; tile k of a window cut into T
-        // tiles holds chunks k, k + T, k + 2T, ...: every tile samples the
+        // tiles holds chunks pk, pk + T, pk + 2T, ...: every tile samples the
         // whole window, so tiles cost alike (neighbouring points cost alike,
         // distant ones do not) and the last round of tiles ends together,
         // while each chunk's outputs are still written as one 16-byte piece
-        // per variant.  Slot s of the tile is point (k + (s / CH) T) CH +
-        // s % CH; only the window's last chunk can be short, and it is the
-        // last chunk of its tile.
+        // per variant.  pk ranks the tiles by (k % 8, k / 8), so the tiles of
+        // one class mod 8 (one XCD's, when the window's tiles start the
+        // launch's tile list) hold neighbouring chunks.  Slot s of the tile
+        // is point (pk + (s / CH) T) CH + s % CH; only the window's last
+        // chunk can be short, and it is the last chunk of its tile.
         constexpr int CH = 4;
         const int tk = tile.p0 / TP;
         const int NC = (W.npts + CH - 1) / CH, cpt = TP / CH;
         const int Tw = max((NC + cpt - 1) / cpt, 1);  // = ceil(npts / TP)
-        const int nch = tk < Tw ? min(cpt, (NC - tk + Tw - 1) / Tw) : 0;
+        const int pk = (tk & 7) * (Tw >> 3) + min(tk & 7, Tw & 7) + (tk >> 3);
+        const int nch = tk < Tw ? min(cpt, (NC - pk + Tw - 1) / Tw) : 0;
         const int npts =
-            nch > 0 ? (nch - 1) * CH + min(CH, W.npts - (tk + (nch - 1) * Tw) * CH) : 0;
+            nch > 0 ? (nch - 1) * CH + min(CH, W.npts - (pk + (nch - 1) * Tw) * CH) : 0;
         unsigned long long bkey = 0ull;
         float btt = INFINITY, bto = INFINITY, bv0 = 0.0f;
         // the wave's points in pairs, slots s0 and s0 + nw: one pass of the
@@ -940,7 +951,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             float LA0, LA1;
             {
                 const int sl = l < 32 ? s0 : s1;
-                const int p = (tk + (sl / CH) * Tw) * CH + (sl & (CH - 1));
+                const int p = (pk + (sl / CH) * Tw) * CH + (sl & (CH - 1));
                 const int j = p / W.nx, i = p - j * W.nx;
                 const float mi = (float)(W.i0 + i) - W.halfNx;
                 const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -953,7 +964,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             }
             for (int g = 0; g < n_pair; ++g) {
             const int slot = g ? s1 : s0;
-            const int p = (tk + (slot / CH) * Tw) * CH + (slot & (CH - 1));
+            const int p = (pk + (slot / CH) * Tw) * CH + (slot & (CH - 1));
             const int j = p / W.nx, i = p - j * W.nx;
             const float mi = (float)(W.i0 + i) - W.halfNx;
             const float mj = (float)(W.j0 + j) - W.halfNy;
@@ -1033,7 +1044,7 @@ __global__ void __launch_bounds__(512, 4) search_kernel(LaunchArgs a)
             const int tot = n_var * npts;
             for (int e = threadIdx.x; e < tot; e += blockDim.x) {
                 const int v = e / npts, slot = e - v * npts;
-                const int64_t o = W.out_base + (int64_t)v * W.npts + (tk + (slot / CH) * Tw) * CH +
+                const int64_t o = W.out_base + (int64_t)v * W.npts + (pk + (slot / CH) * Tw) * CH +
                                   (slot & (CH - 1));
                 if (a.score) a.score[o] = OS[v * TP + slot];
                 if (a.mask) a.mask[o] = OM[v * TP + slot];
@@ -1053,7 +1064,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(LaunchArgs a)
     __shared__ int s_wi;
     const int f = blockIdx.x;
     const int tid = threadIdx.x;
-    if (f == 0 && tid == 0 && a.counter) *a.counter = 0u;
+    if (f == 0 && tid < 8 && a.counter) a.counter[tid] = 0u;  // the search's 8 counters
     if (a.n_frames_dev && f >= *a.n_frames_dev) return;
     const FrameDev F = a.frames[f];
     // the frame's tile records, or one record per workgroup of a one-frame

@@ -164,8 +164,8 @@ int dpps_search_batch_noalloc(dpps_ctx *c, int32_t n_frames, const dpps_frame *f
     pack_tables(b->T, L, (char *)c->na_pinned);
     HIP_OK(hipMemcpyAsync(base, c->na_pinned, L.total, hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(c->na_staged, st));
-    // the array keeps the last call's contents: the work counter starts at 0
-    if (launch_zero_words(b->d_counter, 1, (void *)st))
+    // the array keeps the last call's contents: the 8 work counters start at 0
+    if (launch_zero_words(b->d_counter, 8, (void *)st))
         return fail(DPPS_E_DEVICE, "clearing the work counter failed: %s",
                     hipGetErrorString(hipGetLastError()));
     return run_batch(c, b, out, st, false);
