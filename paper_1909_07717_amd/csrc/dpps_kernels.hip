@@ -1941,11 +1941,11 @@ __device__ __forceinline__ float robot_time_pt(const DevParams &P, float4 r, flo
 __device__ __forceinline__ double slab_enter(double cx, double cy, double dx, double dy,
                                              double x0, double x1, double y0, double y1)
 {
+    // the slab's near side chosen before the one division per axis (the
+    // same quotients; lanes whose dy signs differ share one division)
     double t = 0.0;
-    if (dx > 0.0) t = fmax(t, (x0 - cx) / dx);
-    if (dx < 0.0) t = fmax(t, (x1 - cx) / dx);
-    if (dy > 0.0) t = fmax(t, (y0 - cy) / dy);
-    if (dy < 0.0) t = fmax(t, (y1 - cy) / dy);
+    if (dx != 0.0) t = fmax(t, ((dx > 0.0 ? x0 : x1) - cx) / dx);
+    if (dy != 0.0) t = fmax(t, ((dy > 0.0 ? y0 : y1) - cy) / dy);
     return fmin(t, 1.0);
 }
 
